@@ -1,0 +1,463 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests needs a GPU.  Each check is chosen so that a plausible
+slip in the oracle (a dropped self-loop test, a wrong tie rule, flags cleared
+after the scan, marks applied at the end of the sweep, a transposed index,
+a wrong modularity term) fails at least one of them.
+"""
+import itertools
+import json
+import random
+from fractions import Fraction
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_08140_amd import graphgen as gg
+from tests.tiny_ref import dense, lpa_dense
+
+GOLDEN = Path(__file__).resolve().parent / "golden"
+
+
+def cliques(c, k):
+    edges = []
+    for b in range(c):
+        vs = range(b * k, (b + 1) * k)
+        edges += [(u, v) for u, v in itertools.combinations(vs, 2)]
+    return gg.from_edges(c * k, edges)
+
+
+def two_cliques(k, bridge):
+    edges = [(u, v) for u, v in itertools.combinations(range(k), 2)]
+    edges += [(u, v) for u, v in itertools.combinations(range(k, 2 * k), 2)]
+    edges.append(bridge)
+    return gg.from_edges(2 * k, edges)
+
+
+def star(L):
+    return gg.from_edges(L + 1, [(0, i) for i in range(1, L + 1)])
+
+
+def random_graph(rng, n, p, weighted=False, self_loops=False):
+    edges, w = [], []
+    for u in range(n):
+        for v in range(u if self_loops else u + 1, n):
+            if rng.random() < p:
+                edges.append((u, v))
+                w.append(rng.randint(0, 5) if weighted else 1)
+    if not edges:
+        edges, w = [(0, 0)], [1]
+        self_loops = True
+    return gg.from_edges(n, edges, w if weighted else None, keep_self_loops=self_loops)
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("c,k", [(1, 3), (3, 3), (4, 5), (7, 4)])
+def test_disjoint_cliques_closed_form(c, k):
+    """c disjoint k-cliques: the first vertex of a clique sees only ties and
+    takes the smallest other id; every later vertex then sees that label with
+    the largest weight.  Each clique ends labelled by its second-smallest id,
+    and Q = 1 - 1/c (Eq. (1) with equal communities)."""
+    g = cliques(c, k)
+    r = oracle.lpa(g)
+    want = np.repeat(np.arange(c) * k + 1, k)
+    assert np.array_equal(r["labels"], want)
+    assert oracle.modularity(g, r["labels"]) == pytest.approx(1 - 1 / c, abs=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_disjoint_cliques_partition_any_order(seed):
+    """The clique partition does not depend on the visiting order."""
+    g = cliques(5, 6)
+    order = np.random.default_rng(seed).permutation(g.n).astype(np.int32)
+    r = oracle.lpa(g, order=order)
+    lab = r["labels"].reshape(5, 6)
+    assert all(len(set(row)) == 1 for row in lab.tolist())
+    assert len(set(lab[:, 0].tolist())) == 5
+    for b in range(5):  # the label is a vertex of the clique
+        assert b * 6 <= lab[b, 0] < (b + 1) * 6
+
+
+def test_two_cliques_bridge_far_end():
+    """Two 4-cliques A={0..3}, B={4..7}, bridge (3,7).  Sweep 0 in id order:
+    0 takes 1 (all ties), 1 keeps 1, 2 and 3 take 1 (weight 2 and 3), 4 takes
+    5, 5 keeps 5, 6 and 7 take 5: six changes.  Every vertex is re-marked and
+    nothing moves in sweep 1.  Q = 24/26 - 1/2 (2m = 26, sigma = 12 per side,
+    Sigma = 13 per side)."""
+    gold = json.loads((GOLDEN / "appendix_cases.json").read_text())["two_cliques_k4_bridge_3_7"]
+    g = two_cliques(4, (3, 7))
+    r = oracle.lpa(g)
+    assert r["labels"].tolist() == gold["labels"]
+    assert r["changed"].tolist() == gold["changed"]
+    assert r["iterations"] == gold["iterations"] and r["converged"]
+    assert oracle.modularity(g, r["labels"]) == pytest.approx(24 / 26 - 0.5, abs=1e-15)
+
+
+def test_two_cliques_bridge_near_end():
+    """Bridge (3,4): vertex 4 sees labels {5,6,7} and 1 (from 3), all weight
+    1, so it takes 1, and B follows: one community, Q = 0."""
+    g = two_cliques(4, (3, 4))
+    r = oracle.lpa(g)
+    assert r["labels"].tolist() == [1] * 8
+    assert oracle.modularity(g, r["labels"]) == 0.0
+
+
+@pytest.mark.parametrize("L", [2, 6, 40])
+def test_star(L):
+    """Star, centre 0: the centre takes 1 and marks the leaves; the leaves are
+    then visited (and unmarked) in the same sweep: 1 keeps its label, 2..L
+    take 1 and mark the centre.  Sweep 1 visits only the centre, which stays:
+    dN = [L, 0], processed = [L+1, 1].  Marks take effect within the sweep."""
+    g = star(L)
+    r = oracle.lpa(g)
+    assert r["labels"].tolist() == [1] * (L + 1)
+    assert r["changed"].tolist() == [L, 0]
+    assert r["processed"].tolist() == [L + 1, 1]
+    assert r["scanned"].tolist() == [2 * L, L]
+    assert oracle.modularity(g, r["labels"]) == 0.0
+
+
+def test_star_golden():
+    gold = json.loads((GOLDEN / "appendix_cases.json").read_text())["star_L6"]
+    r = oracle.lpa(star(6))
+    assert r["labels"].tolist() == gold["labels"]
+    assert r["changed"].tolist() == gold["changed"]
+    assert r["processed"].tolist() == gold["processed"]
+
+
+def test_tie_prefers_smallest_not_incumbent():
+    """Path 0-1-2 visited as (1, 0, 2): vertex 1 sees labels 0 and 2 with
+    equal weight and takes 0, the smallest id (its own label 1 is not among
+    the candidates; self is excluded from the scan)."""
+    g = gg.from_edges(3, [(0, 1), (1, 2)])
+    r = oracle.lpa(g, order=np.array([1, 0, 2], np.int32), max_iters=1)
+    assert r["labels"][1] == 0
+
+
+def test_incumbent_loses_tie_to_smaller_label():
+    """Vertex 2 has neighbours 1 and 3 (labels 1 and 3, weight 1 each): the
+    tie goes to label 1, the smaller id."""
+    g = gg.from_edges(4, [(2, 1), (2, 3)])
+    init = np.array([0, 1, 2, 3], np.int32)
+    r = oracle.lpa(g, order=np.array([2, 0, 1, 3], np.int32), max_iters=1, init_labels=init)
+    assert r["labels"][2] == 1
+
+
+def test_weights_decide():
+    """Weighted: vertex 0 with neighbours 1 (w=1), 2 (w=1), 3 (w=3) takes 3."""
+    g = gg.from_edges(4, [(0, 1), (0, 2), (0, 3)], [1, 1, 3])
+    r = oracle.lpa(g, max_iters=1)
+    assert r["labels"][0] == 3
+
+
+def test_weights_sum_per_label():
+    """Labels are summed before the argmax: two weight-2 edges into label 1
+    beat one weight-3 edge into label 3."""
+    g = gg.from_edges(5, [(0, 1), (0, 2), (0, 3)], [2, 2, 3])
+    init = np.array([0, 1, 1, 3, 4], np.int32)
+    r = oracle.lpa(g, max_iters=1, order=np.array([0, 1, 2, 3, 4], np.int32), init_labels=init)
+    assert r["labels"][0] == 1
+
+
+def test_self_loops_ignored():
+    """A self-loop never contributes to the scan and is never re-marked."""
+    g = gg.from_edges(3, [(0, 0), (0, 1), (1, 2)], [9, 1, 1], keep_self_loops=True)
+    r = oracle.lpa(g, max_iters=1)
+    assert r["labels"][0] == 1
+    only_loop = gg.from_edges(2, [(0, 0), (1, 1)], keep_self_loops=True)
+    r = oracle.lpa(only_loop)
+    assert r["labels"].tolist() == [0, 1] and r["changed"].tolist() == [0]
+
+
+def test_isolated_vertices_keep_label():
+    g = gg.from_edges(5, [(1, 2)])
+    r = oracle.lpa(g)
+    assert r["labels"][0] == 0 and r["labels"][3] == 3 and r["labels"][4] == 4
+    assert r["processed"][0] == 2  # only vertices with stored entries count
+
+
+def test_zero_weight_edge_is_a_candidate():
+    """A stored zero-weight entry still offers its label (weight 0)."""
+    g = gg.from_edges(2, [(0, 1)], [0])
+    r = oracle.lpa(g, max_iters=1)
+    assert r["labels"].tolist() == [1, 1]
+
+
+def test_stop_test_is_inclusive():
+    """dN / N <= tau stops (Algorithm 1's convergence test): 1 change among
+    20 vertices with tau = 0.05 converges after the first sweep."""
+    edges = [(0, 1)]
+    g = gg.from_edges(20, edges)
+    r = oracle.lpa(g, tau=0.05)
+    assert r["changed"].tolist() == [1] and r["iterations"] == 1 and r["converged"]
+    r = oracle.lpa(g, tau=0.049)
+    assert r["iterations"] == 2
+
+
+def test_max_iters_not_converged():
+    g = cliques(3, 4)
+    r = oracle.lpa(g, tau=0.0, max_iters=1)
+    assert r["iterations"] == 1 and not r["converged"]
+
+
+# ---------------------------------------------------------------- brute force
+
+def _check_against_brute(g, order=None, prune=True, tau=0.05, max_iters=20):
+    W, adj = dense(g.n, g.offsets, g.indices, g.weights)
+    lab, hist, conv = lpa_dense(W, adj, order=order, tau=tau, max_iters=max_iters, prune=prune)
+    r = oracle.lpa(g, order=None if order is None else np.asarray(order, np.int32), tau=tau,
+                   max_iters=max_iters, prune=prune)
+    assert r["labels"].tolist() == lab
+    assert r["changed"].tolist() == hist
+    assert r["converged"] == conv
+
+
+def test_brute_force_all_graphs_n5():
+    """Every simple graph on 5 vertices (1024), id order, with and without pruning."""
+    pairs = list(itertools.combinations(range(5), 2))
+    for mask in range(1 << len(pairs)):
+        edges = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+        g = gg.from_edges(5, edges) if edges else gg.from_edges(5, [(0, 0)], keep_self_loops=True)
+        _check_against_brute(g, prune=bool(mask & 1), tau=0.0, max_iters=6)
+
+
+def test_brute_force_random_small():
+    rng = random.Random(12345)
+    for trial in range(300):
+        n = rng.randint(1, 12)
+        g = random_graph(rng, n, rng.uniform(0.1, 0.9), weighted=trial % 2 == 0, self_loops=trial % 3 == 0)
+        order = list(range(n))
+        rng.shuffle(order)
+        _check_against_brute(g, order=order, prune=trial % 4 != 0, tau=rng.choice([0.0, 0.05, 0.2]),
+                             max_iters=rng.randint(1, 8))
+
+
+# ---------------------------------------------------------------- invariants
+
+def _best_label(g, labels, v):
+    tally = {}
+    for k in range(g.offsets[v], g.offsets[v + 1]):
+        j = int(g.indices[k])
+        if j == v:
+            continue
+        w = 1 if g.weights is None else int(g.weights[k])
+        tally[int(labels[j])] = tally.get(int(labels[j]), 0) + w
+    if not tally:
+        return int(labels[v])
+    return max(tally.items(), key=lambda kv: (kv[1], -kv[0]))[0]
+
+
+@pytest.mark.parametrize("prune", [True, False])
+def test_fixed_point(prune):
+    """With tau = 0 and a long cap, a final sweep with dN = 0 leaves every
+    vertex on its smallest-id argmax label (Eq. (2) holds everywhere)."""
+    for seed in range(3):
+        g = gg.sbm(300, 6, 0.08, 0.01, seed=seed, weighted="ones" if seed else False)
+        r = oracle.lpa(g, tau=0.0, max_iters=200, prune=prune)
+        assert r["changed"][-1] == 0
+        for v in range(g.n):
+            assert r["labels"][v] == _best_label(g, r["labels"], v)
+
+
+def test_pruning_is_exact_sequentially():
+    """A vertex left unmarked has an unchanged neighbourhood since its last
+    scan, so re-scanning it cannot move it: pruning changes neither the
+    labels nor dN per sweep in a sequential run (Section 4.1.4's pruning only
+    saves work)."""
+    for seed in range(4):
+        g = gg.rmat(10, 8, seed=seed)
+        order = np.random.default_rng(seed).permutation(g.n).astype(np.int32)
+        a = oracle.lpa(g, order=order, tau=0.0, max_iters=12, prune=True)
+        b = oracle.lpa(g, order=order, tau=0.0, max_iters=12, prune=False)
+        assert np.array_equal(a["labels"], b["labels"])
+        assert np.array_equal(a["changed"], b["changed"])
+        assert a["scanned"].sum() <= b["scanned"].sum()
+
+
+def _components(g):
+    parent = list(range(g.n))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+    for v in range(g.n):
+        for k in range(g.offsets[v], g.offsets[v + 1]):
+            a, b = find(v), find(int(g.indices[k]))
+            if a != b:
+                parent[a] = b
+    return [find(v) for v in range(g.n)]
+
+
+def test_label_in_component_and_monotone_label_set():
+    """Labels travel only along edges: every final label is the id of a vertex
+    in the same connected component, and the set of labels in use never
+    gains a member from one sweep to the next."""
+    g = gg.rmat(11, 4, seed=3)
+    comp = _components(g)
+    prev = set(range(g.n))
+    labels = None
+    flags = None
+    for s in range(10):
+        r = oracle.lpa(g, max_iters=1, tau=-1.0, init_labels=labels, init_flags=flags)
+        labels, flags = r["labels"], r["flags"]
+        cur = set(labels.tolist())
+        assert cur <= prev
+        prev = cur
+    for v in range(g.n):
+        assert comp[int(labels[v])] == comp[v]
+
+
+def test_resume_equals_uninterrupted():
+    """State is (labels, flags, sweep): k sweeps + resume = one run."""
+    g = gg.rmat(11, 8, seed=5)
+    full = oracle.lpa(g, tau=-1.0, max_iters=5)
+    a = oracle.lpa(g, tau=-1.0, max_iters=2)
+    b = oracle.lpa(g, tau=-1.0, max_iters=3, init_labels=a["labels"], init_flags=a["flags"])
+    assert np.array_equal(full["labels"], b["labels"])
+    assert full["changed"].tolist() == a["changed"].tolist() + b["changed"].tolist()
+
+
+# ---------------------------------------------------------------- colouring
+
+def fmix32(h):
+    h ^= h >> 16
+    h = (h * 0x85EBCA6B) & 0xFFFFFFFF
+    h ^= h >> 13
+    h = (h * 0xC2B2AE35) & 0xFFFFFFFF
+    h ^= h >> 16
+    return h
+
+
+def test_fmix32_vectors():
+    for x, y in json.loads((GOLDEN / "murmur3_vectors.json").read_text())["fmix32"]:
+        assert fmix32(x) == y
+
+
+@pytest.mark.parametrize("seed", [0, 7, 0xDEADBEEF])
+def test_colouring_is_greedy_in_priority_order(seed):
+    """The oracle colouring equals networkx's greedy colouring when nodes are
+    offered in decreasing (fmix32(v ^ seed), v) order, and is proper."""
+    import networkx as nx
+    g = gg.rmat(10, 8, seed=2)
+    colors, ncol = oracle.color(g, seed)
+    G = nx.Graph()
+    G.add_nodes_from(range(g.n))
+    for v in range(g.n):
+        for k in range(g.offsets[v], g.offsets[v + 1]):
+            if int(g.indices[k]) != v:
+                G.add_edge(v, int(g.indices[k]))
+    prio = sorted(range(g.n), key=lambda v: (fmix32(v ^ seed), v), reverse=True)
+    ref = nx.coloring.greedy_color(G, strategy=lambda G_, c: iter(prio))
+    assert all(colors[v] == ref[v] for v in range(g.n))
+    assert ncol == max(ref.values()) + 1
+    assert ncol <= int(g.degrees().max()) + 1
+    for u, v in G.edges():
+        assert colors[u] != colors[v]
+
+
+def test_colour_order_groups_classes():
+    g = gg.rmat(9, 8, seed=4)
+    colors, ncol = oracle.color(g, 1)
+    order = oracle.color_order(colors, ncol)
+    assert sorted(order.tolist()) == list(range(g.n))
+    key = [(int(colors[v]), int(v)) for v in order]
+    assert key == sorted(key)
+
+
+def test_deterministic_order_independent_within_colour():
+    """Within a colour class vertices are pairwise non-adjacent, so any order
+    inside a class gives the same labels and dN: the property that lets the
+    GPU process a class in parallel."""
+    g = gg.rmat(11, 8, seed=6)
+    colors, ncol = oracle.color(g, 3)
+    base = oracle.lpa(g, order=oracle.color_order(colors, ncol))
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        tie = rng.permutation(g.n)
+        order = np.lexsort((tie, colors)).astype(np.int32)
+        r = oracle.lpa(g, order=order)
+        assert np.array_equal(r["labels"], base["labels"])
+        assert np.array_equal(r["changed"], base["changed"])
+
+
+# ---------------------------------------------------------------- modularity
+
+def test_modularity_matches_networkx_and_exact_fraction():
+    import networkx as nx
+    rng = np.random.default_rng(1)
+    for seed in range(4):
+        g = gg.rmat(9, 6, seed=seed)
+        labels = rng.integers(0, 12, g.n).astype(np.int32)
+        q = oracle.modularity(g, labels)
+        G = nx.Graph()
+        G.add_nodes_from(range(g.n))
+        for v in range(g.n):
+            for k in range(g.offsets[v], g.offsets[v + 1]):
+                u = int(g.indices[k])
+                if u > v:
+                    G.add_edge(v, u, weight=float(g.weights[k]))
+        comms = [set(np.nonzero(labels == c)[0].tolist()) for c in np.unique(labels)]
+        qn = nx.algorithms.community.modularity(G, comms, weight="weight")
+        assert q == pytest.approx(qn, abs=1e-12)
+        # exact rational evaluation of the community form
+        K = {}
+        sig = {}
+        two_m = 0
+        for v in range(g.n):
+            for k in range(g.offsets[v], g.offsets[v + 1]):
+                w = int(g.weights[k])
+                two_m += w
+                K[labels[v]] = K.get(labels[v], 0) + w
+                if labels[int(g.indices[k])] == labels[v]:
+                    sig[labels[v]] = sig.get(labels[v], 0) + w
+        exact = sum(Fraction(sig.get(c, 0), two_m) - Fraction(K[c], two_m) ** 2 for c in K)
+        assert q == pytest.approx(float(exact), abs=2e-16)
+
+
+def test_modularity_closed_forms():
+    g = cliques(4, 5)
+    assert oracle.modularity(g, np.zeros(g.n, np.int32)) == 0.0
+    singles = oracle.modularity(g, np.arange(g.n, dtype=np.int32))
+    deg = g.degrees().astype(np.float64)
+    assert singles == pytest.approx(-np.sum((deg / deg.sum()) ** 2), abs=1e-15)
+    for k in (3, 4, 6):
+        g2 = two_cliques(k, (k - 1, 2 * k - 1))
+        lab = np.array([0] * k + [1] * k, np.int32)
+        want = 2 * k * (k - 1) / (2 * k * (k - 1) + 2) - 0.5
+        assert oracle.modularity(g2, lab) == pytest.approx(want, abs=1e-15)
+
+
+def test_modularity_range():
+    rng = np.random.default_rng(3)
+    for seed in range(5):
+        g = gg.rmat(8, 4, seed=seed)
+        for _ in range(5):
+            lab = rng.integers(0, rng.integers(1, g.n), g.n).astype(np.int32)
+            q = oracle.modularity(g, lab)
+            assert -0.5 <= q <= 1.0
+
+
+def test_modularity_bipartite_swap_state_is_minus_half():
+    """Two-colouring a bipartite graph (what a fully synchronous update does to
+    a star) gives Q = -1/2, the bottom of the range."""
+    g = star(5)
+    lab = np.array([0] + [1] * 5, np.int32)
+    assert oracle.modularity(g, lab) == pytest.approx(-0.5, abs=1e-15)
+
+
+# ---------------------------------------------------------------- batch oracle
+
+def test_batch_oracle_equals_independent_runs():
+    g, vptr = gg.sbm_batch(count=6, master_seed=3, n_range=(50, 400))
+    res = oracle.lpa_batch(g, vptr, deterministic=False)
+    for k in range(6):
+        lo, hi = int(vptr[k]), int(vptr[k + 1])
+        sub = oracle.subgraph(g, lo, hi)
+        r = oracle.lpa(sub)
+        assert np.array_equal(res[k]["labels"], r["labels"] + lo)
+        assert res[k]["iterations"] == r["iterations"]
