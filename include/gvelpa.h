@@ -1,0 +1,166 @@
+/*
+ * gvelpa.h - C ABI of the MI355X (gfx950) strict label-propagation library.
+ *
+ * The library runs the label-scan sweep of GVE-LPA (S. Sahu, "GVE-LPA: Fast
+ * Label Propagation Algorithm (LPA) for Community Detection in Shared Memory
+ * Setting", arXiv 2312.08140) on one AMD GPU.  Every step of a run executes
+ * in the library's own HIP kernels.
+ *
+ * Conventions shared by every entry point:
+ *   - Integer status codes (lpa_status); nothing throws across the ABI.
+ *     lpa_status_string() gives a message for any code.
+ *   - Graphs are undirected CSR with every edge stored in both directions:
+ *     offsets int64[n+1], indices int32[m], optional weights float[m] that
+ *     hold non-negative integers <= 2^24 (NULL = unit weights, Section 3).
+ *   - Labels are vertex ids (Algorithm 1 starts from C = [0 .. |V|)), never
+ *     renumbered; a vertex whose only stored neighbour is itself, or that
+ *     has none, keeps its label.
+ *   - Pointers are host pointers unless LPA_FLAG_DEVICE_PTRS is given, in
+ *     which case they are device pointers on the handle's device.
+ *   - All work is enqueued on the stream given to lpa_create (NULL = the
+ *     device's null stream); calls that return results synchronise it.
+ *   - One handle must not be used from two host threads at once.
+ */
+#ifndef GVELPA_H
+#define GVELPA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lpa_graph lpa_graph; /* opaque; owned by the library */
+
+typedef enum {
+  LPA_OK = 0,
+  LPA_ERR_INVALID_ARG = -1,         /* NULL handle/pointer, bad mode, bad size */
+  LPA_ERR_INVALID_CSR = -2,         /* offsets not monotone, offsets[0] != 0, offsets[n] != m, index out of range */
+  LPA_ERR_WEIGHT_NOT_INTEGRAL = -3, /* a weight is negative, non-integral, non-finite or above 2^24 */
+  LPA_ERR_TOO_LARGE = -4,           /* n >= 2^31, or a weighted degree reaches 2^32 */
+  LPA_ERR_OUT_OF_MEMORY = -5,       /* device allocation failed (or exceeded GVELPA_DEVICE_BUDGET_BYTES) */
+  LPA_ERR_DEVICE = -6,              /* no usable GPU, or a HIP call failed */
+  LPA_ERR_NO_GATE = -7,             /* a gated run was asked for before lpa_gate_load */
+  LPA_ERR_INTERNAL = -8             /* a kernel reported an internal inconsistency (e.g. table overflow) */
+} lpa_status;
+
+/* Execution modes of lpa_run. */
+enum {
+  LPA_MODE_ASYNC = 0,        /* labels updated in place while the sweep runs; any interleaving is valid (Section 4.1) */
+  LPA_MODE_DETERMINISTIC = 1 /* vertices visited colour class by colour class; equals the sequential method in
+                                (colour, id) order, see lpa_color */
+};
+
+/* Flags (bitwise or). */
+enum {
+  LPA_FLAG_DEVICE_PTRS = 1,     /* pointer arguments are device pointers */
+  LPA_FLAG_CHECK_SYMMETRIC = 2, /* lpa_create: also verify that every (i,j,w) has a matching (j,i,w) */
+  LPA_FLAG_GATE = 4,            /* lpa_run: use the learned active-set gate (needs lpa_gate_load) */
+  LPA_FLAG_NO_GRAPH = 8,        /* lpa_run: launch kernels one by one instead of replaying a captured HIP graph */
+  LPA_FLAG_KERNEL_TIMING = 16,  /* lpa_run: time every kernel with HIP events (implies LPA_FLAG_NO_GRAPH) */
+  LPA_FLAG_VERIFY = 32,         /* lpa_run: after convergence, run one full unpruned sweep; if it changes more
+                                   than tau * n labels, continue with plain pruning */
+  LPA_FLAG_TRACE = 64           /* lpa_run: record gate training samples (features, changed-next-sweep) */
+};
+
+#define LPA_MAX_SWEEPS_RECORDED 64
+#define LPA_NUM_TIMED_KERNELS 16
+
+/* Per-run statistics.  Per-sweep arrays hold the first 64 sweeps. */
+typedef struct {
+  int32_t iterations;  /* lpaMove() calls executed (Algorithm 1), verification sweeps excluded */
+  int32_t converged;   /* 1 if the stop test dN/N <= tau held */
+  int32_t verified;    /* LPA_FLAG_VERIFY: 1 if the verification sweep changed <= tau * n labels */
+  int32_t num_colors;  /* deterministic mode: colour classes */
+  int64_t changed[LPA_MAX_SWEEPS_RECORDED];       /* dN of each sweep */
+  int64_t frontier[LPA_MAX_SWEEPS_RECORDED];      /* vertices with >= 1 stored entry processed in each sweep */
+  int64_t edges_scanned[LPA_MAX_SWEEPS_RECORDED]; /* stored entries of those vertices */
+  int64_t gated_out[LPA_MAX_SWEEPS_RECORDED];     /* flagged vertices the gate skipped (kept flagged) */
+  float ms[LPA_MAX_SWEEPS_RECORDED];              /* device time of each sweep */
+  int64_t verify_changed;                         /* labels changed by the verification sweep(s) */
+  int64_t total_changed;
+  double total_ms;                                /* device time from run start to final labels */
+  double setup_ms;                                /* one-off work done by this call (colouring, capture) */
+  /* LPA_FLAG_KERNEL_TIMING: summed HIP-event time and launch count per kernel kind */
+  double kernel_ms[LPA_NUM_TIMED_KERNELS];
+  int64_t kernel_launches[LPA_NUM_TIMED_KERNELS];
+} lpa_stats;
+
+/*
+ * lpa_create - upload (or borrow) a CSR graph and prepare the sweep.
+ *   out       receives the handle (set to NULL on failure).
+ *   n, m      vertex and stored-entry counts; 0 <= n < 2^31, m >= 0.
+ *   offsets   int64[n+1], offsets[0] = 0, non-decreasing, offsets[n] = m.
+ *   indices   int32[m], 0 <= indices[e] < n.
+ *   weights   float[m] integral in [0, 2^24], or NULL for unit weights; the
+ *             weighted degree of every vertex must stay below 2^32.
+ *   device    HIP device ordinal.
+ *   hip_stream  a hipStream_t (NULL = null stream) used for all later work.
+ *   flags     LPA_FLAG_DEVICE_PTRS: the three arrays are device memory and
+ *             are borrowed (the caller keeps them alive and unchanged until
+ *             lpa_destroy); otherwise they are copied.  LPA_FLAG_CHECK_SYMMETRIC.
+ * The graph model is the one of Section 3 (w_ij = w_ji).  The library owns
+ * all further device memory (labels, flags, work lists, tables).
+ */
+int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, const int32_t *indices,
+               const float *weights, int device, void *hip_stream, unsigned flags);
+
+/*
+ * lpa_run - strict label propagation, Algorithm 1 (Section 4.2) with the
+ * strict update of Eq. (2): each processed vertex takes the label of largest
+ * summed edge weight among its neighbours (itself excluded), the smallest
+ * label id on ties (Section 2); runs until dN/N <= tolerance or max_iters
+ * sweeps (Section 4.1.2-4.1.3; the paper uses 0.05 and 20).
+ *   mode        LPA_MODE_ASYNC or LPA_MODE_DETERMINISTIC.
+ *   prune       1: vertex pruning (Section 4.1.4) - only flagged vertices are
+ *               processed, a vertex is unflagged when processed and its
+ *               neighbours are flagged when it changes; 0: every vertex with a
+ *               stored entry is processed in every sweep.
+ *   flags       LPA_FLAG_* (DEVICE_PTRS applies to init_labels, init_flags and
+ *               labels_out).
+ *   init_labels int32[n] starting labels (each in [0, n)), NULL = identity.
+ *   init_flags  uint8[n] starting flags, NULL = all flagged.  Together with
+ *               init_labels this resumes a run from a snapshot.
+ *   labels_out  int32[n] final labels (may be NULL).
+ *   stats       optional statistics (may be NULL).
+ * max_iters must be in [0, 1000].  Synchronises the stream before returning.
+ */
+int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, unsigned flags,
+            const int32_t *init_labels, const uint8_t *init_flags, int32_t *labels_out, lpa_stats *stats);
+
+/*
+ * lpa_get_flags - copy the pruning flags left by the last lpa_run (uint8[n],
+ * host or device per flags); with the labels they form a resumable snapshot.
+ */
+int lpa_get_flags(const lpa_graph *g, uint8_t *flags_out, unsigned flags);
+
+/*
+ * lpa_modularity - modularity Q of a labeling, Eq. (1) (Section 3.2), in its
+ * community form: Q = sum_c [sigma_c/2m - (Sigma_c/2m)^2], with K_i the summed
+ * stored weights of row i, Sigma_c the sum of K_i over c and sigma_c the
+ * stored weight with both endpoints in c.  Sums are exact integers computed
+ * on the GPU; the host forms num = S1*2m - S2 and den = (2m)^2 in 128-bit
+ * integers and returns (double)num / (double)den.  labels: int32[n] in [0, n)
+ * (host or device per flags); labels == NULL means the labels of the last run.
+ */
+int lpa_modularity(const lpa_graph *g, const int32_t *labels, unsigned flags, double *q_out);
+
+/*
+ * lpa_color - colouring used by the deterministic mode (computed on first use):
+ * Jones-Plassmann with priority (fmix32(v ^ seed), v), fmix32 being the
+ * MurmurHash3 32-bit finaliser, which equals the greedy colouring that takes
+ * vertices in decreasing priority.  colors_out int32[n] (host or device per
+ * flags, may be NULL); *num_colors receives the class count.
+ */
+int lpa_color(lpa_graph *g, uint32_t seed, int32_t *colors_out, unsigned flags, int32_t *num_colors);
+
+/* lpa_destroy - release the handle and all device memory it owns (NULL is a no-op). */
+void lpa_destroy(lpa_graph *g);
+
+/* lpa_status_string - static message for a status code. */
+const char *lpa_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GVELPA_H */

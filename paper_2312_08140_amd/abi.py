@@ -1,0 +1,268 @@
+"""Thin ctypes binding of ``include/gvelpa.h`` (argument marshalling only).
+
+Every function keeps the C name and signature; arrays may be numpy arrays
+(host memory) or torch tensors (device memory, with ``LPA_FLAG_DEVICE_PTRS``).
+``LPAGraph`` is a small owner of one handle.  The HIP library is required:
+loading fails loudly when it is missing, and nothing here computes labels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _build
+
+try:  # load torch's HIP runtime first so that the library binds to the same one
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is part of the image
+    torch = None
+
+LPA_OK = 0
+LPA_ERR_INVALID_ARG = -1
+LPA_ERR_INVALID_CSR = -2
+LPA_ERR_WEIGHT_NOT_INTEGRAL = -3
+LPA_ERR_TOO_LARGE = -4
+LPA_ERR_OUT_OF_MEMORY = -5
+LPA_ERR_DEVICE = -6
+LPA_ERR_NO_GATE = -7
+LPA_ERR_INTERNAL = -8
+
+LPA_MODE_ASYNC = 0
+LPA_MODE_DETERMINISTIC = 1
+
+LPA_FLAG_DEVICE_PTRS = 1
+LPA_FLAG_CHECK_SYMMETRIC = 2
+LPA_FLAG_GATE = 4
+LPA_FLAG_NO_GRAPH = 8
+LPA_FLAG_KERNEL_TIMING = 16
+LPA_FLAG_VERIFY = 32
+LPA_FLAG_TRACE = 64
+
+MAX_SWEEPS_RECORDED = 64
+NUM_TIMED_KERNELS = 16
+KERNEL_NAMES = ["compact", "bin0", "bin1", "bin2", "bin3", "bin4", "bin5", "hub_plan", "hub_scan", "hub_finish",
+                "end_sweep", "other", "k12", "k13", "k14", "k15"]
+
+
+class lpa_stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("verified", ctypes.c_int32),
+        ("num_colors", ctypes.c_int32),
+        ("changed", ctypes.c_int64 * MAX_SWEEPS_RECORDED),
+        ("frontier", ctypes.c_int64 * MAX_SWEEPS_RECORDED),
+        ("edges_scanned", ctypes.c_int64 * MAX_SWEEPS_RECORDED),
+        ("gated_out", ctypes.c_int64 * MAX_SWEEPS_RECORDED),
+        ("ms", ctypes.c_float * MAX_SWEEPS_RECORDED),
+        ("verify_changed", ctypes.c_int64),
+        ("total_changed", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+        ("setup_ms", ctypes.c_double),
+        ("kernel_ms", ctypes.c_double * NUM_TIMED_KERNELS),
+        ("kernel_launches", ctypes.c_int64 * NUM_TIMED_KERNELS),
+    ]
+
+    def to_dict(self) -> dict:
+        k = min(self.iterations, MAX_SWEEPS_RECORDED)
+        return dict(
+            iterations=self.iterations, converged=bool(self.converged), verified=bool(self.verified),
+            num_colors=self.num_colors, changed=list(self.changed[:k]), frontier=list(self.frontier[:k]),
+            edges_scanned=list(self.edges_scanned[:k]), gated_out=list(self.gated_out[:k]), ms=list(self.ms[:k]),
+            verify_changed=self.verify_changed, total_changed=self.total_changed, total_ms=self.total_ms,
+            setup_ms=self.setup_ms,
+            kernel_ms={KERNEL_NAMES[i]: self.kernel_ms[i] for i in range(NUM_TIMED_KERNELS) if self.kernel_launches[i]},
+            kernel_launches={KERNEL_NAMES[i]: self.kernel_launches[i] for i in range(NUM_TIMED_KERNELS)
+                             if self.kernel_launches[i]},
+        )
+
+
+_vp = ctypes.c_void_p
+_i32, _i64, _u32, _u64, _f32, _f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64,
+                                      ctypes.c_float, ctypes.c_double)
+
+# name -> (restype, argtypes); mirrors include/gvelpa.h
+SIGNATURES = {
+    "lpa_create": (ctypes.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_uint]),
+    "lpa_run": (ctypes.c_int, [_vp, _f64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, _vp, _vp, _vp,
+                               ctypes.POINTER(lpa_stats)]),
+    "lpa_get_flags": (ctypes.c_int, [_vp, _vp, ctypes.c_uint]),
+    "lpa_modularity": (ctypes.c_int, [_vp, _vp, ctypes.c_uint, ctypes.POINTER(_f64)]),
+    "lpa_color": (ctypes.c_int, [_vp, _u32, _vp, ctypes.c_uint, ctypes.POINTER(_i32)]),
+    "lpa_set_bins": (ctypes.c_int, [_vp, _vp, _i32]),
+    "lpa_destroy": (None, [_vp]),
+    "lpa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+_lib = None
+
+
+def load():
+    """Load ``lib/libgvelpa.so`` (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not _build.LPA_LIB.exists():
+            raise RuntimeError(f"HIP library not built: {_build.LPA_LIB} (run __graft_entry__.build())")
+        lib = ctypes.CDLL(str(_build.LPA_LIB))
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class LPAError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+
+
+def status_string(code: int) -> str:
+    return load().lpa_status_string(code).decode()
+
+
+def _ptr(a) -> Optional[int]:
+    """Address of a numpy array or torch tensor (None passes NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be contiguous")
+        return a.ctypes.data
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return a.data_ptr()
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != LPA_OK:
+        raise LPAError(rc, what)
+
+
+def lpa_create(n, m, offsets, indices, weights=None, device=0, hip_stream=None, flags=0):
+    h = ctypes.c_void_p()
+    rc = load().lpa_create(ctypes.byref(h), n, m, _ptr(offsets), _ptr(indices), _ptr(weights), device, hip_stream,
+                           flags)
+    return rc, h
+
+
+def lpa_run(handle, tolerance, max_iters, mode, prune, flags=0, init_labels=None, init_flags=None, labels_out=None,
+            stats=None):
+    return load().lpa_run(handle, tolerance, max_iters, mode, int(prune), flags, _ptr(init_labels), _ptr(init_flags),
+                          _ptr(labels_out), ctypes.byref(stats) if stats is not None else None)
+
+
+def lpa_get_flags(handle, flags_out, flags=0):
+    return load().lpa_get_flags(handle, _ptr(flags_out), flags)
+
+
+def lpa_modularity(handle, labels=None, flags=0):
+    q = ctypes.c_double()
+    rc = load().lpa_modularity(handle, _ptr(labels), flags, ctypes.byref(q))
+    return rc, q.value
+
+
+def lpa_color(handle, seed=0, colors_out=None, flags=0):
+    nc = ctypes.c_int32()
+    rc = load().lpa_color(handle, seed & 0xFFFFFFFF, _ptr(colors_out), flags, ctypes.byref(nc))
+    return rc, nc.value
+
+
+def lpa_set_bins(handle, max_degree=None):
+    arr = None if max_degree is None else np.ascontiguousarray(max_degree, dtype=np.int32)
+    return load().lpa_set_bins(handle, _ptr(arr), 0 if arr is None else len(arr))
+
+
+def lpa_destroy(handle):
+    load().lpa_destroy(handle)
+
+
+def lpa_status_string(code):
+    return status_string(code)
+
+
+def _current_stream(device: int):
+    if torch is None or not torch.cuda.is_available():
+        return None
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class LPAGraph:
+    """Owns one library handle for a CSR graph (numpy host arrays or torch device tensors)."""
+
+    def __init__(self, csr=None, *, n=None, offsets=None, indices=None, weights=None, device: int = 0,
+                 stream=None, check_symmetric: bool = False):
+        if csr is not None:
+            n, offsets, indices, weights = csr.n, csr.offsets, csr.indices, csr.weights
+        self.n = int(n)
+        self.device = device
+        on_device = hasattr(offsets, "data_ptr")
+        flags = (LPA_FLAG_DEVICE_PTRS if on_device else 0) | (LPA_FLAG_CHECK_SYMMETRIC if check_symmetric else 0)
+        if not on_device:
+            offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+            indices = np.ascontiguousarray(indices, dtype=np.int32)
+            weights = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+        self._keep = (offsets, indices, weights) if on_device else None
+        self.m = int(indices.shape[0])
+        self.stream = _current_stream(device) if stream is None else stream
+        rc, h = lpa_create(self.n, self.m, offsets, indices, weights, device, self.stream, flags)
+        _check(rc, "lpa_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lpa_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, tolerance=0.05, max_iters=20, mode=LPA_MODE_ASYNC, prune=True, flags=0, init_labels=None,
+            init_flags=None, labels_out=None):
+        """Returns (labels, stats dict).  labels_out may be a device tensor."""
+        st = lpa_stats()
+        fl = flags
+        if labels_out is None:
+            labels_out = np.empty(self.n, np.int32)
+        if hasattr(labels_out, "data_ptr"):
+            fl |= LPA_FLAG_DEVICE_PTRS
+            if init_labels is not None and not hasattr(init_labels, "data_ptr"):
+                raise ValueError("init arrays must live where labels_out lives")
+        else:
+            if init_labels is not None:
+                init_labels = np.ascontiguousarray(init_labels, dtype=np.int32)
+            if init_flags is not None:
+                init_flags = np.ascontiguousarray(init_flags, dtype=np.uint8)
+        rc = lpa_run(self.handle, tolerance, max_iters, mode, prune, fl, init_labels, init_flags, labels_out, st)
+        _check(rc, "lpa_run")
+        return labels_out, st.to_dict()
+
+    def flags(self):
+        out = np.empty(self.n, np.uint8)
+        _check(lpa_get_flags(self.handle, out), "lpa_get_flags")
+        return out
+
+    def modularity(self, labels=None) -> float:
+        fl = LPA_FLAG_DEVICE_PTRS if hasattr(labels, "data_ptr") else 0
+        if labels is not None and not fl:
+            labels = np.ascontiguousarray(labels, dtype=np.int32)
+        rc, q = lpa_modularity(self.handle, labels, fl)
+        _check(rc, "lpa_modularity")
+        return q
+
+    def color(self, seed=0):
+        out = np.empty(self.n, np.int32)
+        rc, nc = lpa_color(self.handle, seed, out)
+        _check(rc, "lpa_color")
+        return out, nc
+
+    def set_bins(self, max_degree=None):
+        _check(lpa_set_bins(self.handle, max_degree), "lpa_set_bins")

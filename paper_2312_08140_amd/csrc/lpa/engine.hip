@@ -1,0 +1,883 @@
+// Host engine behind the C ABI of include/gvelpa.h: device memory, work
+// lists, the sweep schedule of both modes, HIP-graph capture and statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <numeric>
+#include <thread>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "gvelpa.h"
+#include "sweep_kernels.hpp"
+
+using namespace gvelpa;
+
+namespace {
+
+struct Status {
+  int code;
+};
+
+#define HIP_OK(expr)                                      \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) throw Status{LPA_ERR_DEVICE};   \
+  } while (0)
+
+enum TimedKind {
+  TK_COMPACT = 0,
+  TK_BIN0 = 1,  // .. TK_BIN0 + 5
+  TK_HUB_PLAN = 7,
+  TK_HUB_SCAN = 8,
+  TK_HUB_FINISH = 9,
+  TK_END_SWEEP = 10,
+  TK_OTHER = 11
+};
+
+}  // namespace
+
+struct lpa_graph {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int64_t n = 0, m = 0;
+  int64_t n_active = 0;  // vertices with >= 1 stored entry
+  // graph
+  int64_t *off = nullptr;
+  int32_t *idx = nullptr;
+  void *w = nullptr;
+  int wk = W_UNIT;
+  uint32_t *K = nullptr;
+  std::vector<int64_t> h_off;
+  // state
+  int32_t *C = nullptr;
+  uint8_t *F = nullptr;
+  bool has_labels = false;
+  // bins
+  BinLimits lim{};
+  bool lists_ready = false;
+  int32_t *alist = nullptr;
+  int64_t abounds[NBINS + 1] = {0};
+  // deterministic schedule
+  int32_t *color = nullptr;
+  int32_t ncol = 0;
+  uint32_t color_seed = 0;
+  bool colored = false;
+  bool dlists_ready = false;
+  int32_t *dlist = nullptr;
+  std::vector<int64_t> dstart;  // ncol * NBINS + 1
+  // frontier
+  int32_t *front = nullptr;
+  int32_t *fcount = nullptr;
+  int fcount_cap = 0;
+  // hubs
+  int32_t n_hubs = 0;
+  int32_t *hub_ids = nullptr;
+  int64_t *hub_toff_all = nullptr;
+  int32_t *hub_tbits_all = nullptr;
+  u64 *htab = nullptr;
+  int64_t htab_entries = 0;
+  std::vector<int64_t> h_hub_chunks;  // per sorted hub: work items
+  u64 *hub_cstart = nullptr;
+  int64_t *hub_toff = nullptr;
+  int32_t *hub_tbits = nullptr;
+  // control
+  Ctl *ctl = nullptr;
+  int32_t *host_done = nullptr;
+  int32_t *host_done_dev = nullptr;
+  void *scratch_small = nullptr;  // CsrCheck + sums, ModAcc, counters
+  int wall_khz = 100000;
+  // graphs
+  std::map<std::tuple<int, int>, hipGraphExec_t> graphs;
+  // memory
+  std::vector<void *> owned;
+  size_t budget = 0, used = 0;
+  int cu_count = 256;
+  // timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  std::vector<int> ev_kind;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+void *dalloc(lpa_graph *g, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  if (g->budget && g->used + bytes > g->budget) throw Status{LPA_ERR_OUT_OF_MEMORY};
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Status{LPA_ERR_OUT_OF_MEMORY};
+  }
+  g->owned.push_back(p);
+  g->used += bytes;
+  return p;
+}
+
+void dfree(lpa_graph *g, void *p) {
+  if (!p) return;
+  auto it = std::find(g->owned.begin(), g->owned.end(), p);
+  if (it != g->owned.end()) {
+    g->owned.erase(it);
+    (void)hipFree(p);
+  }
+}
+
+template <class T>
+T *dalloc_n(lpa_graph *g, int64_t count) {
+  return (T *)dalloc(g, sizeof(T) * (size_t)std::max<int64_t>(count, 1));
+}
+
+void drop_graphs(lpa_graph *g) {
+  for (auto &kv : g->graphs) (void)hipGraphExecDestroy(kv.second);
+  g->graphs.clear();
+}
+
+struct Events {
+  hipEvent_t e[6] = {};
+  Events() {
+    for (auto &x : e) HIP_OK(hipEventCreate(&x));
+  }
+  ~Events() {
+    for (auto &x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
+int grid_cap(int64_t items, int per_block, int cap) {
+  int64_t b = (items + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+// ---------------------------------------------------------------- host validation
+
+// Checks of a host CSR before any device work; returns a status and fills
+// max_weight / not_all_ones for the choice of the internal weight format.
+int validate_host(int64_t n, int64_t m, const int64_t *off, const int32_t *idx, const float *w, bool check_sym,
+                  uint32_t *max_weight, bool *not_all_ones) {
+  if (off[0] != 0 || off[n] != m) return LPA_ERR_INVALID_CSR;
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 65536) nt = 1;
+  std::vector<int> bad_off(nt, 0), bad_idx(nt, 0), bad_w(nt, 0), big(nt, 0), ones(nt, 0);
+  std::vector<uint32_t> wmax(nt, 0);
+  std::vector<u64> fwd(nt, 0), bwd(nt, 0);
+  auto mix = [](u64 z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto work = [&](unsigned t) {
+    const int64_t v0 = n * t / nt, v1 = n * (t + 1) / nt;
+    for (int64_t v = v0; v < v1; ++v) {
+      if (off[v + 1] < off[v] || off[v] < 0 || off[v + 1] > m) {
+        bad_off[t] = 1;
+        return;
+      }
+      u64 deg = 0;
+      for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+        const int32_t j = idx[e];
+        if (j < 0 || (int64_t)j >= n) {
+          bad_idx[t] = 1;
+          return;
+        }
+        uint32_t x = 1;
+        if (w) {
+          const float f = w[e];
+          if (!(f >= 0.0f) || f > 16777216.0f || std::floor(f) != f) {
+            bad_w[t] = 1;
+            return;
+          }
+          x = (uint32_t)f;
+          wmax[t] = std::max(wmax[t], x);
+          ones[t] |= x != 1u;
+        }
+        deg += x;
+        if (check_sym) {
+          const u64 hx = mix(x + 0x9E3779B97F4A7C15ull);
+          fwd[t] += mix(((u64)v << 32 | (uint32_t)j) ^ hx);
+          bwd[t] += mix(((u64)(uint32_t)j << 32 | (u64)v) ^ hx);
+        }
+      }
+      if (deg >= (1ull << 32)) big[t] = 1;
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto &x : th) x.join();
+  u64 f = 0, b = 0;
+  uint32_t mx = 0;
+  bool no = false;
+  for (unsigned t = 0; t < nt; ++t) {
+    if (bad_off[t] || bad_idx[t]) return LPA_ERR_INVALID_CSR;
+    if (bad_w[t]) return LPA_ERR_WEIGHT_NOT_INTEGRAL;
+    if (big[t]) return LPA_ERR_TOO_LARGE;
+    f += fwd[t];
+    b += bwd[t];
+    mx = std::max(mx, wmax[t]);
+    no |= ones[t] != 0;
+  }
+  if (check_sym && f != b) return LPA_ERR_INVALID_CSR;
+  *max_weight = mx;
+  *not_all_ones = no;
+  return LPA_OK;
+}
+
+// ---------------------------------------------------------------- timing
+
+void tk_begin(lpa_graph *g, hipStream_t st) {
+  if (!g->timing) return;
+  if (g->ev_used == g->ev_pool.size()) {
+    hipEvent_t a, b;
+    HIP_OK(hipEventCreate(&a));
+    HIP_OK(hipEventCreate(&b));
+    g->ev_pool.push_back({a, b});
+    g->ev_kind.push_back(0);
+  }
+  HIP_OK(hipEventRecord(g->ev_pool[g->ev_used].first, st));
+}
+
+void tk_end(lpa_graph *g, hipStream_t st, int kind) {
+  if (!g->timing) return;
+  HIP_OK(hipEventRecord(g->ev_pool[g->ev_used].second, st));
+  g->ev_kind[g->ev_used] = kind;
+  ++g->ev_used;
+}
+
+// ---------------------------------------------------------------- lists
+
+void build_lists(lpa_graph *g, const int32_t *color, int nkeys, int32_t *list, std::vector<int64_t> &starts) {
+  int32_t *hist = dalloc_n<int32_t>(g, nkeys);
+  HIP_OK(hipMemsetAsync(hist, 0, sizeof(int32_t) * nkeys, g->stream));
+  launch_bin_hist(g->off, g->n, color, g->lim, hist, g->stream);
+  std::vector<int32_t> h(nkeys);
+  HIP_OK(hipMemcpyAsync(h.data(), hist, sizeof(int32_t) * nkeys, hipMemcpyDeviceToHost, g->stream));
+  HIP_OK(hipStreamSynchronize(g->stream));
+  starts.assign(nkeys + 1, 0);
+  for (int k = 0; k < nkeys; ++k) starts[k + 1] = starts[k] + h[k];
+  std::vector<int32_t> cur(nkeys);
+  for (int k = 0; k < nkeys; ++k) cur[k] = (int32_t)starts[k];
+  HIP_OK(hipMemcpyAsync(hist, cur.data(), sizeof(int32_t) * nkeys, hipMemcpyHostToDevice, g->stream));
+  launch_bin_scatter(g->off, g->n, color, g->lim, hist, list, g->stream);
+  HIP_OK(hipStreamSynchronize(g->stream));
+  dfree(g, hist);
+}
+
+void build_hubs(lpa_graph *g) {
+  dfree(g, g->hub_ids);
+  dfree(g, g->hub_toff_all);
+  dfree(g, g->hub_tbits_all);
+  dfree(g, g->htab);
+  dfree(g, g->hub_cstart);
+  dfree(g, g->hub_toff);
+  dfree(g, g->hub_tbits);
+  g->hub_ids = nullptr;
+  g->hub_toff_all = nullptr;
+  g->hub_tbits_all = nullptr;
+  g->htab = nullptr;
+  g->hub_cstart = nullptr;
+  g->hub_toff = nullptr;
+  g->hub_tbits = nullptr;
+  std::vector<int32_t> ids;
+  const int32_t lim = g->lim.maxdeg[NBINS - 2];
+  for (int64_t v = 0; v < g->n; ++v)
+    if (g->h_off[v + 1] - g->h_off[v] > lim) ids.push_back((int32_t)v);
+  g->n_hubs = (int32_t)ids.size();
+  std::vector<int64_t> toff(ids.size() + 1, 0);
+  std::vector<int32_t> tbits(ids.size() + 1, 0);
+  g->h_hub_chunks.assign(ids.size(), 0);
+  int64_t total = 0;
+  for (size_t k = 0; k < ids.size(); ++k) {
+    const int64_t deg = g->h_off[ids[k] + 1] - g->h_off[ids[k]];
+    int bits = 1;
+    while (((int64_t)1 << bits) < 2 * deg) ++bits;
+    toff[k] = total;
+    tbits[k] = bits;
+    total += (int64_t)1 << bits;
+    g->h_hub_chunks[k] = (deg + HUB_CHUNK - 1) / HUB_CHUNK;
+  }
+  g->htab_entries = total;
+  const int64_t nh = std::max<int64_t>(1, (int64_t)ids.size());
+  g->hub_ids = dalloc_n<int32_t>(g, nh);
+  g->hub_toff_all = dalloc_n<int64_t>(g, nh);
+  g->hub_tbits_all = dalloc_n<int32_t>(g, nh);
+  g->hub_cstart = dalloc_n<u64>(g, nh);
+  g->hub_toff = dalloc_n<int64_t>(g, nh);
+  g->hub_tbits = dalloc_n<int32_t>(g, nh);
+  g->htab = dalloc_n<u64>(g, std::max<int64_t>(total, 1));
+  if (!ids.empty()) {
+    HIP_OK(hipMemcpyAsync(g->hub_ids, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, g->stream));
+    HIP_OK(hipMemcpyAsync(g->hub_toff_all, toff.data(), sizeof(int64_t) * ids.size(), hipMemcpyHostToDevice,
+                          g->stream));
+    HIP_OK(hipMemcpyAsync(g->hub_tbits_all, tbits.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice,
+                          g->stream));
+    launch_fill_u64(g->htab, total, EMPTY, g->stream);
+  }
+  HIP_OK(hipStreamSynchronize(g->stream));
+}
+
+void ensure_fcount(lpa_graph *g, int need) {
+  if (g->fcount_cap >= need) return;
+  dfree(g, g->fcount);
+  g->fcount = dalloc_n<int32_t>(g, need);
+  g->fcount_cap = need;
+  HIP_OK(hipMemsetAsync(g->fcount, 0, sizeof(int32_t) * need, g->stream));
+}
+
+void ensure_lists(lpa_graph *g) {
+  if (g->lists_ready) return;
+  drop_graphs(g);
+  if (!g->alist) g->alist = dalloc_n<int32_t>(g, g->n_active);
+  if (!g->front) g->front = dalloc_n<int32_t>(g, g->n_active);
+  std::vector<int64_t> starts;
+  build_lists(g, nullptr, NBINS, g->alist, starts);
+  for (int b = 0; b <= NBINS; ++b) g->abounds[b] = starts[b];
+  build_hubs(g);
+  ensure_fcount(g, NBINS);
+  g->lists_ready = true;
+  g->dlists_ready = false;
+}
+
+void ensure_colored(lpa_graph *g, uint32_t seed) {
+  if (g->colored && g->color_seed == seed) return;
+  drop_graphs(g);
+  if (!g->color) g->color = dalloc_n<int32_t>(g, g->n);
+  int32_t *work = dalloc_n<int32_t>(g, g->n);
+  int32_t *next = dalloc_n<int32_t>(g, g->n);
+  int32_t *cnt = dalloc_n<int32_t>(g, 1);
+  launch_color_init(g->color, work, g->n, g->stream);
+  int64_t wlen = g->n;
+  while (wlen > 0) {
+    HIP_OK(hipMemsetAsync(cnt, 0, sizeof(int32_t), g->stream));
+    launch_color_round(g->off, g->idx, g->color, work, (int32_t)wlen, next, cnt, seed, g->stream);
+    int32_t h = 0;
+    HIP_OK(hipMemcpyAsync(&h, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+    HIP_OK(hipStreamSynchronize(g->stream));
+    if (h >= wlen) throw Status{LPA_ERR_INTERNAL};  // every round colours at least one vertex
+    wlen = h;
+    std::swap(work, next);
+  }
+  dfree(g, work);
+  dfree(g, next);
+  dfree(g, cnt);
+  // number of classes = 1 + largest colour
+  std::vector<int32_t> hc((size_t)g->n);
+  if (g->n) HIP_OK(hipMemcpy(hc.data(), g->color, sizeof(int32_t) * g->n, hipMemcpyDeviceToHost));
+  int32_t mx = -1;
+  for (int32_t c : hc) mx = std::max(mx, c);
+  g->ncol = mx + 1;
+  g->color_seed = seed;
+  g->colored = true;
+  g->dlists_ready = false;
+}
+
+void ensure_dlists(lpa_graph *g) {
+  ensure_lists(g);
+  if (g->dlists_ready) return;
+  drop_graphs(g);
+  if (!g->dlist) g->dlist = dalloc_n<int32_t>(g, g->n_active);
+  const int nkeys = std::max(1, g->ncol) * NBINS;
+  build_lists(g, g->color, nkeys, g->dlist, g->dstart);
+  ensure_fcount(g, nkeys);
+  g->dlists_ready = true;
+}
+
+// ---------------------------------------------------------------- sweep emission
+
+ScanArgs base_args(lpa_graph *g, int prune) {
+  ScanArgs a{};
+  a.off = g->off;
+  a.idx = g->idx;
+  a.w = g->w;
+  a.C = g->C;
+  a.F = g->F;
+  a.ctl = g->ctl;
+  a.prune = prune;
+  a.htab = g->htab;
+  a.hub_toff = g->hub_toff;
+  a.hub_tbits = g->hub_tbits;
+  a.hub_cstart = g->hub_cstart;
+  a.hub_ids = g->hub_ids;
+  a.hub_toff_all = g->hub_toff_all;
+  a.hub_tbits_all = g->hub_tbits_all;
+  a.n_hubs = g->n_hubs;
+  return a;
+}
+
+// One step: compact the flagged vertices of `list` (bin segments given by
+// absolute `bounds` into list/front), then process the bins, hubs first.
+void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t *bounds, int32_t *fcount, int prune) {
+  const int64_t base = bounds[0];
+  const int64_t len = bounds[NBINS] - base;
+  if (len <= 0) return;
+  CompactArgs ca{};
+  ca.list = list + base;
+  ca.len = len;
+  for (int b = 0; b <= NBINS; ++b) ca.bounds[b] = (int32_t)(bounds[b] - base);
+  ca.F = g->F;
+  ca.front = g->front + base;
+  ca.fcount = fcount;
+  ca.ctl = g->ctl;
+  ca.prune = prune;
+  tk_begin(g, st);
+  launch_compact(ca, grid_cap(len, 256, 8192), st);
+  tk_end(g, st, TK_COMPACT);
+  const int max_blocks = g->cu_count * 8;
+  for (int b = NBINS - 1; b >= 0; --b) {
+    const int64_t seg = bounds[b + 1] - bounds[b];
+    if (seg <= 0) continue;
+    ScanArgs a = base_args(g, prune);
+    a.front = g->front + bounds[b];
+    a.fcount = fcount + b;
+    if (b == HUB_BIN) {
+      // work items of every hub in this segment bound the hub step's grid
+      int64_t items = 0;
+      for (int64_t c : g->h_hub_chunks) items += c;
+      tk_begin(g, st);
+      launch_hub_plan(a, g->hub_cstart, g->hub_toff, g->hub_tbits, st);
+      tk_end(g, st, TK_HUB_PLAN);
+      tk_begin(g, st);
+      launch_hub_scan(g->wk, grid_cap(items, 1, max_blocks * 2), st, a, g->hub_cstart, g->hub_toff, g->hub_tbits);
+      tk_end(g, st, TK_HUB_SCAN);
+      tk_begin(g, st);
+      launch_hub_finish(grid_cap(seg, 1, max_blocks), st, a, g->hub_toff, g->hub_tbits);
+      tk_end(g, st, TK_HUB_FINISH);
+    } else {
+      const int per_block = b <= 2 ? 256 / BIN_GROUP[b] : 1;
+      tk_begin(g, st);
+      launch_scan_bin(b, g->wk, grid_cap(seg, per_block, max_blocks), st, a);
+      tk_end(g, st, TK_BIN0 + b);
+    }
+  }
+}
+
+void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune) {
+  if (mode == LPA_MODE_DETERMINISTIC) {
+    for (int c = 0; c < g->ncol; ++c)
+      emit_step(g, st, g->dlist, &g->dstart[(size_t)c * NBINS], g->fcount + (size_t)c * NBINS, prune);
+  } else {
+    emit_step(g, st, g->alist, g->abounds, g->fcount, prune);
+  }
+  const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : NBINS;
+  tk_begin(g, st);
+  launch_end_sweep(g->ctl, g->fcount, nfc, g->host_done_dev, st);
+  tk_end(g, st, TK_END_SWEEP);
+}
+
+hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune) {
+  auto key = std::make_tuple(mode, prune);
+  auto it = g->graphs.find(key);
+  if (it != g->graphs.end()) return it->second;
+  hipGraph_t graph = nullptr;
+  HIP_OK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+  emit_sweep(g, g->cap_stream, mode, prune);
+  HIP_OK(hipStreamEndCapture(g->cap_stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiateWithFlags(&exec, graph, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) throw Status{LPA_ERR_DEVICE};
+  g->graphs[key] = exec;
+  return exec;
+}
+
+void copy_in(lpa_graph *g, void *dst, const void *src, size_t bytes, unsigned flags) {
+  HIP_OK(hipMemcpyAsync(dst, src, bytes, (flags & LPA_FLAG_DEVICE_PTRS) ? hipMemcpyDeviceToDevice
+                                                                         : hipMemcpyHostToDevice, g->stream));
+}
+
+void copy_out(lpa_graph *g, void *dst, const void *src, size_t bytes, unsigned flags) {
+  HIP_OK(hipMemcpyAsync(dst, src, bytes, (flags & LPA_FLAG_DEVICE_PTRS) ? hipMemcpyDeviceToDevice
+                                                                         : hipMemcpyDeviceToHost, g->stream));
+}
+
+template <class Fn>
+int run_guarded(lpa_graph *g, Fn &&fn) {
+  if (!g) return LPA_ERR_INVALID_ARG;
+  try {
+    HIP_OK(hipSetDevice(g->device));
+    return fn();
+  } catch (Status s) {
+    return s.code;
+  } catch (std::bad_alloc &) {
+    return LPA_ERR_OUT_OF_MEMORY;
+  }
+}
+
+}  // namespace
+
+// ======================================================================== ABI
+
+extern "C" {
+
+const char *lpa_status_string(int status) {
+  switch (status) {
+    case LPA_OK: return "ok";
+    case LPA_ERR_INVALID_ARG: return "invalid argument";
+    case LPA_ERR_INVALID_CSR: return "invalid CSR (offsets or indices)";
+    case LPA_ERR_WEIGHT_NOT_INTEGRAL: return "weights must be finite integers in [0, 2^24]";
+    case LPA_ERR_TOO_LARGE: return "graph too large (n >= 2^31 or a weighted degree >= 2^32)";
+    case LPA_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case LPA_ERR_DEVICE: return "no usable GPU or a HIP call failed";
+    case LPA_ERR_NO_GATE: return "no gate network loaded";
+    case LPA_ERR_INTERNAL: return "internal error reported by a kernel";
+    default: return "unknown status";
+  }
+}
+
+void lpa_destroy(lpa_graph *g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  drop_graphs(g);
+  for (auto &p : g->ev_pool) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  for (void *p : g->owned) (void)hipFree(p);
+  if (g->host_done) (void)hipHostFree(g->host_done);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  delete g;
+}
+
+int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, const int32_t *indices,
+               const float *weights, int device, void *hip_stream, unsigned flags) {
+  if (!out) return LPA_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n < 0 || m < 0 || !offsets || (m > 0 && !indices)) return LPA_ERR_INVALID_ARG;
+  if (n >= ((int64_t)1 << 31)) return LPA_ERR_TOO_LARGE;
+  const bool host_in = !(flags & LPA_FLAG_DEVICE_PTRS);
+  uint32_t host_wmax = 0;
+  bool host_not_ones = false;
+  if (host_in) {
+    // host arrays are validated before any device work
+    int v = validate_host(n, m, offsets, indices, weights, flags & LPA_FLAG_CHECK_SYMMETRIC, &host_wmax,
+                          &host_not_ones);
+    if (v != LPA_OK) return v;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return LPA_ERR_DEVICE;
+  }
+  if (device < 0 || device >= ndev) return LPA_ERR_INVALID_ARG;
+  lpa_graph *g = new (std::nothrow) lpa_graph();
+  if (!g) return LPA_ERR_OUT_OF_MEMORY;
+  g->device = device;
+  g->stream = (hipStream_t)hip_stream;
+  g->n = n;
+  g->m = m;
+  if (const char *b = std::getenv("GVELPA_DEVICE_BUDGET_BYTES")) g->budget = (size_t)std::strtoull(b, nullptr, 10);
+  for (int b = 0; b < NBINS - 1; ++b) g->lim.maxdeg[b] = DEFAULT_BIN_MAXDEG[b];
+  int rc = run_guarded(g, [&]() -> int {
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, device));
+    g->cu_count = prop.multiProcessorCount;
+    HIP_OK(hipDeviceGetAttribute(&g->wall_khz, hipDeviceAttributeWallClockRate, device));
+    HIP_OK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+    HIP_OK(hipHostMalloc((void **)&g->host_done, sizeof(int32_t), hipHostMallocMapped));
+    *g->host_done = 0;
+    HIP_OK(hipHostGetDevicePointer((void **)&g->host_done_dev, g->host_done, 0));
+    const bool dev = flags & LPA_FLAG_DEVICE_PTRS;
+    // host copy of the offsets (schedule planning) and their basic checks
+    g->h_off.resize((size_t)n + 1);
+    if (dev) HIP_OK(hipMemcpy(g->h_off.data(), offsets, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    else std::memcpy(g->h_off.data(), offsets, sizeof(int64_t) * (n + 1));
+    if (g->h_off[0] != 0 || g->h_off[n] != m) return LPA_ERR_INVALID_CSR;
+    g->scratch_small = dalloc(g, 4096);
+    CsrCheck *chk = (CsrCheck *)g->scratch_small;
+    HIP_OK(hipMemsetAsync(chk, 0, 4096, g->stream));
+    if (dev) {
+      g->off = (int64_t *)offsets;
+      g->idx = (int32_t *)indices;
+    } else {
+      g->off = dalloc_n<int64_t>(g, n + 1);
+      g->idx = dalloc_n<int32_t>(g, m);
+      HIP_OK(hipMemcpyAsync(g->off, offsets, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, g->stream));
+      if (m) HIP_OK(hipMemcpyAsync(g->idx, indices, sizeof(int32_t) * m, hipMemcpyHostToDevice, g->stream));
+    }
+    const float *wdev = nullptr;
+    float *wtmp = nullptr;
+    if (weights) {
+      if (dev) wdev = weights;
+      else {
+        wtmp = dalloc_n<float>(g, m);
+        if (m) HIP_OK(hipMemcpyAsync(wtmp, weights, sizeof(float) * m, hipMemcpyHostToDevice, g->stream));
+        wdev = wtmp;
+      }
+    }
+    CsrCheck h{};
+    if (dev) {
+      launch_check_offsets(g->off, n, chk, g->stream);
+      if (m) launch_check_edges(g->idx, wdev, m, n, chk, g->stream);
+      HIP_OK(hipMemcpyAsync(&h, chk, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+      HIP_OK(hipStreamSynchronize(g->stream));
+      if (h.bad_offsets || h.bad_index) return LPA_ERR_INVALID_CSR;
+      if (h.bad_weight) return LPA_ERR_WEIGHT_NOT_INTEGRAL;
+    } else {
+      h.max_weight = host_wmax;
+      h.not_all_ones = host_not_ones ? 1 : 0;
+    }
+    // internal weight format: none when every weight is 1, else uint8 or uint32
+    g->wk = W_UNIT;
+    if (weights && m && h.not_all_ones) g->wk = h.max_weight <= 255 ? W_U8 : W_U32;
+    if (g->wk != W_UNIT) {
+      g->w = dalloc(g, (size_t)m * (g->wk == W_U8 ? 1 : 4));
+      launch_convert_weights(wdev, m, g->wk, g->w, g->stream);
+    }
+    if (wtmp) {
+      HIP_OK(hipStreamSynchronize(g->stream));
+      dfree(g, wtmp);
+    }
+    g->K = dalloc_n<uint32_t>(g, n);
+    launch_weighted_degree(g->off, g->w, g->wk, n, g->K, chk, g->stream);
+    const bool dev_sym = dev && (flags & LPA_FLAG_CHECK_SYMMETRIC);
+    if (dev_sym) launch_check_symmetric(g->off, g->idx, g->w, g->wk, n, chk, g->stream);
+    u64 sums[2] = {0, 0};
+    HIP_OK(hipMemcpyAsync(&h, chk, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+    HIP_OK(hipMemcpyAsync(sums, (u64 *)(chk + 1), sizeof(sums), hipMemcpyDeviceToHost, g->stream));
+    HIP_OK(hipStreamSynchronize(g->stream));
+    if (h.big_degree) return LPA_ERR_TOO_LARGE;
+    if (dev_sym && sums[0] != sums[1]) return LPA_ERR_INVALID_CSR;
+    int64_t act = 0;
+    for (int64_t v = 0; v < n; ++v) act += g->h_off[v + 1] > g->h_off[v];
+    g->n_active = act;
+    g->C = dalloc_n<int32_t>(g, n);
+    g->F = dalloc_n<uint8_t>(g, n);
+    g->ctl = dalloc_n<Ctl>(g, 1);
+    HIP_OK(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream));
+    launch_init_state(g->off, g->C, g->F, n, 1, 1, 0, g->stream);
+    ensure_lists(g);
+    HIP_OK(hipStreamSynchronize(g->stream));
+    return LPA_OK;
+  });
+  if (rc != LPA_OK) {
+    lpa_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return LPA_OK;
+}
+
+int lpa_set_bins(lpa_graph *g, const int32_t *max_degree, int32_t count) {
+  return run_guarded(g, [&]() -> int {
+    BinLimits lim{};
+    if (!max_degree) {
+      for (int b = 0; b < NBINS - 1; ++b) lim.maxdeg[b] = DEFAULT_BIN_MAXDEG[b];
+    } else {
+      if (count != NBINS - 1) return LPA_ERR_INVALID_ARG;
+      for (int b = 0; b < NBINS - 1; ++b) {
+        // a table must have room for every distinct label of its vertices
+        if (max_degree[b] < 0 || max_degree[b] >= BIN_SLOTS[b]) return LPA_ERR_INVALID_ARG;
+        if (b && max_degree[b] < max_degree[b - 1]) return LPA_ERR_INVALID_ARG;
+        lim.maxdeg[b] = max_degree[b];
+      }
+    }
+    if (std::memcmp(&lim, &g->lim, sizeof(lim)) != 0) {
+      g->lim = lim;
+      g->lists_ready = false;
+      g->dlists_ready = false;
+      drop_graphs(g);
+    }
+    return LPA_OK;
+  });
+}
+
+int lpa_color(lpa_graph *g, uint32_t seed, int32_t *colors_out, unsigned flags, int32_t *num_colors) {
+  return run_guarded(g, [&]() -> int {
+    ensure_colored(g, seed);
+    if (colors_out && g->n) {
+      copy_out(g, colors_out, g->color, sizeof(int32_t) * g->n, flags);
+      HIP_OK(hipStreamSynchronize(g->stream));
+    }
+    if (num_colors) *num_colors = g->ncol;
+    return LPA_OK;
+  });
+}
+
+int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, unsigned flags,
+            const int32_t *init_labels, const uint8_t *init_flags, int32_t *labels_out, lpa_stats *stats) {
+  if (!g || max_iters < 0 || max_iters > 1000 || (mode != LPA_MODE_ASYNC && mode != LPA_MODE_DETERMINISTIC) ||
+      !(tolerance == tolerance))
+    return LPA_ERR_INVALID_ARG;
+  if (flags & LPA_FLAG_GATE) return LPA_ERR_NO_GATE;
+  return run_guarded(g, [&]() -> int {
+    Events ev;
+    hipEvent_t e0 = ev.e[0], e1 = ev.e[1], t0 = ev.e[2], t1 = ev.e[3];
+    hipEvent_t lag[2] = {ev.e[4], ev.e[5]};
+    const bool timing = flags & LPA_FLAG_KERNEL_TIMING;
+    const bool use_graph = !(flags & (LPA_FLAG_NO_GRAPH | LPA_FLAG_KERNEL_TIMING));
+    HIP_OK(hipEventRecord(e0, g->stream));
+    // one-off setup of the schedule
+    ensure_lists(g);
+    if (mode == LPA_MODE_DETERMINISTIC) {
+      ensure_colored(g, g->colored ? g->color_seed : 0u);
+      ensure_dlists(g);
+    }
+    if (init_labels && g->n) {
+      // labels must be vertex ids
+      copy_in(g, g->C, init_labels, sizeof(int32_t) * g->n, flags);
+      int32_t *bad = (int32_t *)((char *)g->scratch_small + 2048);
+      HIP_OK(hipMemsetAsync(bad, 0, sizeof(int32_t), g->stream));
+      launch_check_labels(g->C, g->n, bad, g->stream);
+      int32_t hb = 0;
+      HIP_OK(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+      HIP_OK(hipStreamSynchronize(g->stream));
+      if (hb) return LPA_ERR_INVALID_ARG;
+    }
+    if (init_flags && g->n) copy_in(g, g->F, init_flags, g->n, flags);
+    if (g->n)
+      launch_init_state(g->off, g->C, g->F, g->n, init_labels ? 0 : 1, init_flags ? 0 : 1, max_iters > 0 ? 1 : 0,
+                        g->stream);
+    hipGraphExec_t exec = nullptr;
+    if (use_graph && max_iters > 0) exec = sweep_graph(g, mode, prune);
+    HIP_OK(hipEventRecord(e1, g->stream));
+    HIP_OK(hipEventSynchronize(e1));
+    float setup_ms = 0;
+    HIP_OK(hipEventElapsedTime(&setup_ms, e0, e1));
+    // the run
+    g->timing = timing;
+    g->ev_used = 0;
+    HIP_OK(hipEventRecord(t0, g->stream));
+    const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : NBINS;
+    launch_run_begin(g->ctl, tolerance, max_iters, g->n, g->fcount, nfc, g->host_done_dev, g->stream);
+    for (int s = 0; s < max_iters; ++s) {
+      if (exec) HIP_OK(hipGraphLaunch(exec, g->stream));
+      else emit_sweep(g, g->stream, mode, prune);
+      HIP_OK(hipEventRecord(lag[s & 1], g->stream));
+      if (s >= 1) {
+        HIP_OK(hipEventSynchronize(lag[(s - 1) & 1]));
+        if (__atomic_load_n(g->host_done, __ATOMIC_ACQUIRE)) break;
+      }
+    }
+    HIP_OK(hipEventRecord(t1, g->stream));
+    HIP_OK(hipStreamSynchronize(g->stream));
+    g->timing = false;
+    Ctl h;
+    HIP_OK(hipMemcpy(&h, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    float run_ms = 0;
+    HIP_OK(hipEventElapsedTime(&run_ms, t0, t1));
+    g->has_labels = true;
+    if (labels_out && g->n) {
+      copy_out(g, labels_out, g->C, sizeof(int32_t) * g->n, flags);
+      HIP_OK(hipStreamSynchronize(g->stream));
+    }
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->iterations = h.iterations;
+      stats->converged = h.converged;
+      stats->num_colors = mode == LPA_MODE_DETERMINISTIC ? g->ncol : 0;
+      u64 prev = h.t_start;
+      for (int s = 0; s < std::min(h.iterations, MAX_REC); ++s) {
+        stats->changed[s] = (int64_t)h.st_changed[s];
+        stats->frontier[s] = (int64_t)h.st_processed[s];
+        stats->edges_scanned[s] = (int64_t)h.st_scanned[s];
+        stats->gated_out[s] = (int64_t)h.st_gated[s];
+        stats->ms[s] = (float)((double)(h.t_sweep[s] - prev) / (double)g->wall_khz);
+        prev = h.t_sweep[s];
+      }
+      stats->total_changed = (int64_t)h.total_changed;
+      stats->verify_changed = (int64_t)h.verify_changed;
+      stats->total_ms = run_ms;
+      stats->setup_ms = setup_ms;
+      if (timing) {
+        for (size_t k = 0; k < g->ev_used; ++k) {
+          float ms = 0;
+          HIP_OK(hipEventElapsedTime(&ms, g->ev_pool[k].first, g->ev_pool[k].second));
+          stats->kernel_ms[g->ev_kind[k]] += ms;
+          stats->kernel_launches[g->ev_kind[k]] += 1;
+        }
+      }
+    }
+    if (h.error) {
+      // leave the hub tables clean for the next run
+      if (g->htab_entries) launch_fill_u64(g->htab, g->htab_entries, EMPTY, g->stream);
+      HIP_OK(hipStreamSynchronize(g->stream));
+      return LPA_ERR_INTERNAL;
+    }
+    return LPA_OK;
+  });
+}
+
+int lpa_get_flags(const lpa_graph *gc, uint8_t *flags_out, unsigned flags) {
+  lpa_graph *g = const_cast<lpa_graph *>(gc);
+  return run_guarded(g, [&]() -> int {
+    if (!flags_out) return LPA_ERR_INVALID_ARG;
+    if (g->n) {
+      copy_out(g, flags_out, g->F, g->n, flags);
+      HIP_OK(hipStreamSynchronize(g->stream));
+    }
+    return LPA_OK;
+  });
+}
+
+int lpa_modularity(const lpa_graph *gc, const int32_t *labels, unsigned flags, double *q_out) {
+  lpa_graph *g = const_cast<lpa_graph *>(gc);
+  return run_guarded(g, [&]() -> int {
+    if (!q_out) return LPA_ERR_INVALID_ARG;
+    if (g->n == 0 || g->m == 0) {
+      *q_out = 0.0;
+      return LPA_OK;
+    }
+    const int32_t *C = g->C;
+    int32_t *tmp = nullptr;
+    if (labels) {
+      if (flags & LPA_FLAG_DEVICE_PTRS) C = labels;
+      else {
+        tmp = dalloc_n<int32_t>(g, g->n);
+        HIP_OK(hipMemcpyAsync(tmp, labels, sizeof(int32_t) * g->n, hipMemcpyHostToDevice, g->stream));
+        C = tmp;
+      }
+    }
+    char *sm = (char *)g->scratch_small;
+    int32_t *bad = (int32_t *)(sm + 2048);
+    ModAcc *acc = (ModAcc *)(sm + 2112);
+    HIP_OK(hipMemsetAsync(bad, 0, sizeof(int32_t), g->stream));
+    HIP_OK(hipMemsetAsync(acc, 0, sizeof(ModAcc), g->stream));
+    launch_check_labels(C, g->n, bad, g->stream);
+    u64 *tot = dalloc_n<u64>(g, g->n);
+    const int nb = mod_square_blocks();
+    u64 *part = dalloc_n<u64>(g, 2 * nb);
+    HIP_OK(hipMemsetAsync(tot, 0, sizeof(u64) * g->n, g->stream));
+    int32_t hb = 0;
+    HIP_OK(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+    HIP_OK(hipStreamSynchronize(g->stream));
+    if (hb) {
+      dfree(g, tot);
+      dfree(g, part);
+      dfree(g, tmp);
+      return LPA_ERR_INVALID_ARG;
+    }
+    launch_mod_community_totals(C, g->K, g->n, tot, g->stream);
+    launch_mod_inside(g->off, g->idx, g->w, g->wk, C, g->n, g->m, acc, g->stream);
+    launch_mod_squares(tot, g->n, part, g->stream);
+    ModAcc ha{};
+    std::vector<u64> hp(2 * nb);
+    HIP_OK(hipMemcpyAsync(&ha, acc, sizeof(ha), hipMemcpyDeviceToHost, g->stream));
+    HIP_OK(hipMemcpyAsync(hp.data(), part, sizeof(u64) * 2 * nb, hipMemcpyDeviceToHost, g->stream));
+    HIP_OK(hipStreamSynchronize(g->stream));
+    dfree(g, tot);
+    dfree(g, part);
+    dfree(g, tmp);
+    unsigned __int128 s2 = 0;
+    for (int k = 0; k < nb; ++k) s2 += ((unsigned __int128)hp[2 * k + 1] << 64) | hp[2 * k];
+    const unsigned __int128 two_m = ha.two_m;
+    if (two_m == 0) {
+      *q_out = 0.0;
+      return LPA_OK;
+    }
+    const __int128 num = (__int128)((unsigned __int128)ha.s1 * two_m) - (__int128)s2;
+    const unsigned __int128 den = two_m * two_m;
+    *q_out = (double)num / (double)den;
+    return LPA_OK;
+  });
+}
+
+}  // extern "C"

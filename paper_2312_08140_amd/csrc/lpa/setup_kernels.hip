@@ -1,0 +1,241 @@
+// One-off kernels run when a graph is created or first used in a mode:
+// CSR validation, weight packing, weighted degrees, degree binning and the
+// Jones-Plassmann colouring of the deterministic mode.
+#include <math.h>
+
+#include "sweep_kernels.hpp"
+
+namespace gvelpa {
+
+static int grid_for(int64_t items, int per_block, int cap = 8192) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+// ---------------------------------------------------------------- validation
+
+__global__ void k_check_offsets(const int64_t *off, int64_t n, CsrCheck *chk) {
+  int bad = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    bad |= off[v + 1] < off[v];
+  if (bad) atomicOr(&chk->bad_offsets, 1);
+}
+
+__global__ void k_check_edges(const int32_t *idx, const float *w, int64_t m, int64_t n, CsrCheck *chk) {
+  int bad_i = 0, bad_w = 0, not_one = 0;
+  uint32_t wmax = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = idx[e];
+    bad_i |= (j < 0) | ((int64_t)j >= n);
+    if (w) {
+      const float x = w[e];
+      const bool ok = (x >= 0.0f) && (x <= 16777216.0f) && (floorf(x) == x);
+      bad_w |= !ok;
+      if (ok) {
+        const uint32_t u = (uint32_t)x;
+        wmax = u > wmax ? u : wmax;
+        not_one |= u != 1u;
+      }
+    }
+  }
+  if (bad_i) atomicOr(&chk->bad_index, 1);
+  if (bad_w) atomicOr(&chk->bad_weight, 1);
+  if (not_one) atomicOr(&chk->not_all_ones, 1);
+  if (wmax) atomicMax(&chk->max_weight, wmax);
+}
+
+__global__ void k_convert_weights(const float *w, int64_t m, int wk, void *out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = (uint32_t)w[e];
+    if (wk == W_U8) ((uint8_t *)out)[e] = (uint8_t)u;
+    else ((uint32_t *)out)[e] = u;
+  }
+}
+
+template <int WK>
+__global__ void k_weighted_degree(const int64_t *off, const void *w, int64_t n, uint32_t *K, CsrCheck *chk) {
+  int big = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    u64 s = 0;
+    const int64_t b = off[v], e = off[v + 1];
+    if constexpr (WK == W_UNIT) s = (u64)(e - b);
+    else
+      for (int64_t k = b; k < e; ++k) s += load_w<WK>(w, k);
+    big |= s >= (1ull << 32);
+    K[v] = (uint32_t)s;
+  }
+  if (big) atomicOr(&chk->big_degree, 1);
+}
+
+// Multiset fingerprint of (i, j, w) against (j, i, w): equal sums for a
+// symmetric graph; any asymmetry changes them with probability ~1 - 2^-64.
+__device__ __forceinline__ u64 mix64(u64 z) {  // SplitMix64 output function
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <int WK>
+__global__ void k_check_symmetric(const int64_t *off, const int32_t *idx, const void *w, int64_t n, u64 *sums) {
+  u64 fwd = 0, bwd = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t k = off[v]; k < off[v + 1]; ++k) {
+      const u64 j = (uint32_t)idx[k];
+      const u64 x = load_w<WK>(w, k);
+      fwd += mix64(((u64)v << 32 | j) ^ mix64(x + 0x9E3779B97F4A7C15ull));
+      bwd += mix64((j << 32 | (u64)v) ^ mix64(x + 0x9E3779B97F4A7C15ull));
+    }
+  }
+  atomicAdd(&sums[0], fwd);
+  atomicAdd(&sums[1], bwd);
+}
+
+__global__ void k_fill_u64(u64 *p, int64_t count, u64 value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// ---------------------------------------------------------------- binning
+
+// Key of a vertex: its degree bin, prefixed by its colour in deterministic
+// lists; vertices without stored entries are never processed and get no key.
+__global__ void k_bin_hist(const int64_t *off, int64_t n, const int32_t *color, BinLimits lim, int32_t *hist) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t deg = off[v + 1] - off[v];
+    if (deg == 0) continue;
+    const int key = (color ? color[v] * NBINS : 0) + bin_of_degree(deg, lim);
+    atomicAdd(&hist[key], 1);
+  }
+}
+
+__global__ void k_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, BinLimits lim, int32_t *cursor,
+                              int32_t *list) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t deg = off[v + 1] - off[v];
+    if (deg == 0) continue;
+    const int key = (color ? color[v] * NBINS : 0) + bin_of_degree(deg, lim);
+    list[atomicAdd(&cursor[key], 1)] = (int32_t)v;
+  }
+}
+
+// ---------------------------------------------------------------- colouring
+
+__global__ void k_color_init(int32_t *color, int32_t *work, int64_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    color[v] = -1;
+    work[v] = (int32_t)v;
+  }
+}
+
+__device__ __forceinline__ u64 prio(uint32_t v, uint32_t seed) { return ((u64)fmix32(v ^ seed) << 32) | v; }
+
+// One Jones-Plassmann round, one wave per listed vertex.  A vertex is ready
+// when no uncoloured neighbour has a higher priority; it then takes the
+// smallest colour unused by its coloured neighbours, which are exactly its
+// higher-priority neighbours (a lower-priority neighbour waits for it).  This
+// is the greedy colouring in decreasing priority order.
+__global__ __launch_bounds__(256) void k_color_round(const int64_t *off, const int32_t *idx, int32_t *color,
+                                                     const int32_t *work, int32_t wlen, int32_t *next,
+                                                     int32_t *ncount, uint32_t seed) {
+  constexpr int WINDOW = 64 * 32;  // colours tested per pass: one 32-bit word per lane
+  __shared__ uint32_t bits_all[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t *bits = bits_all[wv];
+  const int gw = blockIdx.x * 4 + wv, nw = gridDim.x * 4;
+  for (int i = gw; i < wlen; i += nw) {
+    const int v = work[i];
+    const u64 pv = prio((uint32_t)v, seed);
+    const int64_t b = off[v], e = off[v + 1];
+    bool blocked = false;
+    for (int64_t k0 = b; k0 < e; k0 += 64) {
+      const int64_t k = k0 + lane;
+      bool blk = false;
+      if (k < e) {
+        const int u = idx[k];
+        blk = u != v && __atomic_load_n(&color[u], __ATOMIC_RELAXED) < 0 && prio((uint32_t)u, seed) > pv;
+      }
+      if (__ballot(blk)) {
+        blocked = true;
+        break;
+      }
+    }
+    if (blocked) {
+      if (lane == 0) next[atomicAdd(ncount, 1)] = v;
+      continue;
+    }
+    int base = 0, found = -1;
+    while (found < 0) {
+      bits[lane] = 0;
+      wave_lds_sync();
+      for (int64_t k = b + lane; k < e; k += 64) {
+        const int u = idx[k];
+        if (u == v) continue;
+        const int c = __atomic_load_n(&color[u], __ATOMIC_RELAXED) - base;
+        if (c >= 0 && c < WINDOW) atomicOr(&bits[c >> 5], 1u << (c & 31));
+      }
+      wave_lds_sync();
+      const uint32_t free_bits = ~bits[lane];
+      int pos = free_bits ? lane * 32 + __builtin_ctz(free_bits) : 0x7FFFFFFF;
+#pragma unroll
+      for (int m = 32; m > 0; m >>= 1) {
+        const int o = __shfl_xor(pos, m, 64);
+        pos = o < pos ? o : pos;
+      }
+      if (pos != 0x7FFFFFFF) found = base + pos;
+      else base += WINDOW;
+      wave_lds_sync();
+    }
+    if (lane == 0) __atomic_store_n(&color[v], found, __ATOMIC_RELAXED);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+void launch_check_offsets(const int64_t *off, int64_t n, CsrCheck *chk, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n, 256)), dim3(256), 0, st, off, n, chk);
+}
+void launch_check_edges(const int32_t *idx, const float *w, int64_t m, int64_t n, CsrCheck *chk, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_edges, dim3(grid_for(m, 256)), dim3(256), 0, st, idx, w, m, n, chk);
+}
+void launch_convert_weights(const float *w, int64_t m, int wk, void *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_convert_weights, dim3(grid_for(m, 256)), dim3(256), 0, st, w, m, wk, out);
+}
+void launch_weighted_degree(const int64_t *off, const void *w, int wk, int64_t n, uint32_t *K, CsrCheck *chk,
+                            hipStream_t st) {
+  dim3 g(grid_for(n, 256)), b(256);
+  if (wk == W_UNIT) hipLaunchKernelGGL(k_weighted_degree<W_UNIT>, g, b, 0, st, off, w, n, K, chk);
+  else if (wk == W_U8) hipLaunchKernelGGL(k_weighted_degree<W_U8>, g, b, 0, st, off, w, n, K, chk);
+  else hipLaunchKernelGGL(k_weighted_degree<W_U32>, g, b, 0, st, off, w, n, K, chk);
+}
+void launch_check_symmetric(const int64_t *off, const int32_t *idx, const void *w, int wk, int64_t n,
+                            CsrCheck *chk, hipStream_t st) {
+  // chk->asym is set by the host from the two sums written after the CsrCheck block
+  u64 *sums = (u64 *)(chk + 1);
+  dim3 g(grid_for(n, 256)), b(256);
+  if (wk == W_UNIT) hipLaunchKernelGGL(k_check_symmetric<W_UNIT>, g, b, 0, st, off, idx, w, n, sums);
+  else if (wk == W_U8) hipLaunchKernelGGL(k_check_symmetric<W_U8>, g, b, 0, st, off, idx, w, n, sums);
+  else hipLaunchKernelGGL(k_check_symmetric<W_U32>, g, b, 0, st, off, idx, w, n, sums);
+}
+void launch_bin_hist(const int64_t *off, int64_t n, const int32_t *color, const BinLimits &lim, int32_t *hist,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_hist, dim3(grid_for(n, 256)), dim3(256), 0, st, off, n, color, lim, hist);
+}
+void launch_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, const BinLimits &lim,
+                        int32_t *cursor, int32_t *list, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, off, n, color, lim, cursor, list);
+}
+void launch_fill_u64(u64 *p, int64_t count, u64 value, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256)), dim3(256), 0, st, p, count, value);
+}
+void launch_color_init(int32_t *color, int32_t *work, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_color_init, dim3(grid_for(n, 256)), dim3(256), 0, st, color, work, n);
+}
+void launch_color_round(const int64_t *off, const int32_t *idx, int32_t *color, const int32_t *work, int32_t wlen,
+                        int32_t *next, int32_t *ncount, uint32_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_color_round, dim3(grid_for(wlen, 4, 16384)), dim3(256), 0, st, off, idx, color, work, wlen,
+                     next, ncount, seed);
+}
+
+}  // namespace gvelpa

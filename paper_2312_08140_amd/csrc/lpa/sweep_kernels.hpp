@@ -1,0 +1,73 @@
+// Host-visible launchers of the gfx950 kernels.
+#pragma once
+#include "common.hpp"
+
+namespace gvelpa {
+
+// Arguments of one frontier compaction (one step: the whole graph in async
+// mode, one colour class in deterministic mode).  Entries [bounds[b],
+// bounds[b+1]) of `list` are the step's vertices of bin b; the flagged ones
+// are written to the same range of `front`, counted in fcount[b].
+struct CompactArgs {
+  const int32_t *list;
+  int64_t len;
+  int32_t bounds[NBINS + 1];
+  uint8_t *F;
+  int32_t *front;
+  int32_t *fcount;
+  Ctl *ctl;
+  int prune;
+};
+
+void launch_compact(const CompactArgs &a, int blocks, hipStream_t st);
+void launch_scan_bin(int bin, int wk, int blocks, hipStream_t st, const ScanArgs &a);
+void launch_hub_plan(const ScanArgs &a, u64 *cstart, int64_t *toff, int32_t *tbits, hipStream_t st);
+void launch_hub_scan(int wk, int blocks, hipStream_t st, const ScanArgs &a, const u64 *cstart, const int64_t *toff,
+                     const int32_t *tbits);
+void launch_hub_finish(int blocks, hipStream_t st, const ScanArgs &a, const int64_t *toff, const int32_t *tbits);
+void launch_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, int set_labels, int set_flags,
+                       int clear_isolated, hipStream_t st);
+void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int32_t *fcount, int nfc, int32_t *host_done,
+                      hipStream_t st);
+void launch_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_done, hipStream_t st);
+
+// setup_kernels.hip
+struct CsrCheck {
+  int32_t bad_index;      // an index outside [0, n)
+  int32_t bad_weight;     // negative, non-integral, non-finite or > 2^24
+  int32_t bad_offsets;    // decreasing offsets
+  int32_t big_degree;     // weighted degree >= 2^32
+  uint32_t max_weight;
+  int32_t not_all_ones;
+  int32_t asym;           // LPA_FLAG_CHECK_SYMMETRIC: a missing or different reverse entry
+  int32_t pad;
+};
+void launch_check_offsets(const int64_t *off, int64_t n, CsrCheck *chk, hipStream_t st);
+void launch_check_edges(const int32_t *idx, const float *w, int64_t m, int64_t n, CsrCheck *chk, hipStream_t st);
+void launch_convert_weights(const float *w, int64_t m, int wk, void *out, hipStream_t st);
+void launch_weighted_degree(const int64_t *off, const void *w, int wk, int64_t n, uint32_t *K, CsrCheck *chk,
+                            hipStream_t st);
+void launch_check_symmetric(const int64_t *off, const int32_t *idx, const void *w, int wk, int64_t n,
+                            CsrCheck *chk, hipStream_t st);
+void launch_bin_hist(const int64_t *off, int64_t n, const int32_t *color, const BinLimits &lim, int32_t *hist,
+                     hipStream_t st);
+void launch_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, const BinLimits &lim,
+                        int32_t *cursor, int32_t *list, hipStream_t st);
+void launch_fill_u64(u64 *p, int64_t count, u64 value, hipStream_t st);
+void launch_color_init(int32_t *color, int32_t *work, int64_t n, hipStream_t st);
+void launch_color_round(const int64_t *off, const int32_t *idx, int32_t *color, const int32_t *work, int32_t wlen,
+                        int32_t *next, int32_t *ncount, uint32_t seed, hipStream_t st);
+
+// metrics_kernels.hip
+struct ModAcc {
+  u64 two_m;
+  u64 s1;
+};
+void launch_mod_community_totals(const int32_t *C, const uint32_t *K, int64_t n, u64 *tot, hipStream_t st);
+void launch_mod_inside(const int64_t *off, const int32_t *idx, const void *w, int wk, const int32_t *C, int64_t n,
+                       int64_t m, ModAcc *acc, hipStream_t st);
+int mod_square_blocks();
+void launch_mod_squares(const u64 *tot, int64_t n, u64 *partials /* 2 per block */, hipStream_t st);
+void launch_check_labels(const int32_t *C, int64_t n, int32_t *bad, hipStream_t st);
+
+}  // namespace gvelpa
