@@ -81,9 +81,19 @@ typedef struct {
   int64_t total_changed;
   double total_ms;                                /* device time from run start to final labels */
   double setup_ms;                                /* one-off work done by this call (colouring, capture) */
-  /* LPA_FLAG_KERNEL_TIMING: summed HIP-event time and launch count per kernel kind */
+  /* LPA_FLAG_KERNEL_TIMING: summed HIP-event time and launch count per kernel kind:
+     0 compaction, 1..6 degree bins 0..5, 7..9 hub plan/scan/finish, 10 end of sweep */
   double kernel_ms[LPA_NUM_TIMED_KERNELS];
   int64_t kernel_launches[LPA_NUM_TIMED_KERNELS];
+  /* run totals per degree bin (bin 6 = hubs): vertices processed, stored entries
+     scanned, labels changed, neighbour marks written; and of the compaction:
+     list entries read and vertices taken.  With weight_bytes (bytes per stored
+     weight inside the library: 0 unit, 1 or 4) they give the bytes each kernel
+     must move. */
+  int64_t bin_vertices[8], bin_edges[8], bin_changed[8], bin_marks[8];
+  int64_t compact_listed, compact_taken;
+  int32_t weight_bytes;
+  int32_t reserved;
 } lpa_stats;
 
 /*
@@ -146,9 +156,22 @@ int lpa_get_flags(const lpa_graph *g, uint8_t *flags_out, unsigned flags);
 int lpa_modularity(const lpa_graph *g, const int32_t *labels, unsigned flags, double *q_out);
 
 /*
+ * lpa_set_async_phases - schedule of an asynchronous sweep (default: 16 steps
+ * by colour).  The flagged
+ * vertices of a sweep are split into `phases` steps processed one after the
+ * other, every vertex of a step at once, so a step sees the labels earlier
+ * steps wrote in place (Section 4.1).  by_colour = 0: steps by a fixed hash of
+ * the vertex id; by_colour = 1: runs of consecutive colour classes of
+ * lpa_color, about n / phases vertices each (vertices of one class are never
+ * adjacent).  phases in [1, 1024]; takes effect for the next lpa_run.
+ */
+int lpa_set_async_phases(lpa_graph *g, int32_t phases, int32_t by_colour);
+
+/*
  * lpa_color - colouring used by the deterministic mode (computed on first use):
- * Jones-Plassmann with priority (fmix32(v ^ seed), v), fmix32 being the
- * MurmurHash3 32-bit finaliser, which equals the greedy colouring that takes
+ * Jones-Plassmann with priority (deg(v), fmix32(v ^ seed), v) compared
+ * lexicographically - deg(v) being the stored entries of row v and fmix32 the
+ * MurmurHash3 32-bit finaliser - which equals the greedy colouring that takes
  * vertices in decreasing priority.  colors_out int32[n] (host or device per
  * flags, may be NULL); *num_colors receives the class count.
  */

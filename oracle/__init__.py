@@ -6,7 +6,7 @@ calls it and shares no code with it.
 
 * ``lpa``          Algorithm 1 (Section 4.2) executed sequentially in an
                    explicit vertex order (C, ``lpa_oracle.c``).
-* ``color``        greedy colouring in decreasing hash priority; with
+* ``color``        greedy colouring in decreasing (degree, hash, id) priority; with
                    ``color_order`` it fixes the order of the deterministic mode.
 * ``modularity``   Eq. (1), community form, exact integers + one FP64 division.
 * ``nmi``          normalised mutual information (``metrics.py``).
@@ -88,7 +88,7 @@ def lpa(g, order=None, tau: float = 0.05, max_iters: int = 20, prune: bool = Tru
 
 
 def color(g, seed: int = 0):
-    """Greedy colouring in decreasing priority (fmix32(v ^ seed), v)."""
+    """Greedy colouring in decreasing priority (deg(v), fmix32(v ^ seed), v)."""
     lib = _load()
     off, idx, _ = _csr_arrays(g)
     colors = np.empty(max(int(g.n), 1), np.int32)

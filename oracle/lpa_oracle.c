@@ -14,8 +14,9 @@
  *                      label-propagation argmax, Section 3.3) in its strict
  *                      form (Section 4.1.5, and the smallest-id tie rule
  *                      stated in Section 2).
- *   oracle_color       greedy colouring in decreasing hash priority; defines
- *                      the vertex order of the deterministic GPU mode.
+ *   oracle_color       greedy colouring in decreasing (degree, hash, id)
+ *                      priority; defines the vertex order of the
+ *                      deterministic GPU mode.
  *   oracle_modularity  Eq. (1) (Section 3.2), community form, in exact integers with one
  *                      final FP64 division.
  *
@@ -146,12 +147,17 @@ int oracle_lpa(int64_t n, const int64_t *off, const int32_t *idx, const float *w
   return 0;
 }
 
-/* Priority of v: (fmix32(v ^ seed), v); larger is coloured first. */
-static uint64_t prio(uint32_t v, uint32_t seed) { return ((uint64_t)fmix32(v ^ seed) << 32) | v; }
+/* Priority of v: (deg(v), fmix32(v ^ seed), v) compared lexicographically,
+ * deg(v) = stored entries of row v; larger is coloured first. */
+typedef struct {
+  uint64_t key; /* deg << 32 | fmix32(v ^ seed) */
+  uint32_t v;
+} prio_t;
 
 static int cmp_desc(const void *a, const void *b) {
-  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
-  return x < y ? 1 : (x > y ? -1 : 0);
+  const prio_t *x = (const prio_t *)a, *y = (const prio_t *)b;
+  if (x->key != y->key) return x->key < y->key ? 1 : -1;
+  return x->v < y->v ? 1 : (x->v > y->v ? -1 : 0);
 }
 
 /*
@@ -161,21 +167,23 @@ static int cmp_desc(const void *a, const void *b) {
  * or -1 on allocation failure.
  */
 int64_t oracle_color(int64_t n, const int64_t *off, const int32_t *idx, uint32_t seed, int32_t *colors) {
-  uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+  prio_t *keys = (prio_t *)malloc(sizeof(prio_t) * (size_t)(n > 0 ? n : 1));
   int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 2));
   if (!keys || !stamp) {
     free(keys); free(stamp);
     return -1;
   }
   for (int64_t v = 0; v < n; ++v) {
-    keys[v] = prio((uint32_t)v, seed);
+    const uint64_t deg = (uint64_t)(off[v + 1] - off[v]);
+    keys[v].key = (deg << 32) | fmix32((uint32_t)v ^ seed);
+    keys[v].v = (uint32_t)v;
     colors[v] = -1;
   }
   for (int64_t c = 0; c < n + 2; ++c) stamp[c] = -1;
-  qsort(keys, (size_t)n, sizeof(uint64_t), cmp_desc);
+  qsort(keys, (size_t)n, sizeof(prio_t), cmp_desc);
   int64_t ncol = 0;
   for (int64_t p = 0; p < n; ++p) {
-    const int64_t v = (int64_t)(uint32_t)keys[p];
+    const int64_t v = (int64_t)keys[p].v;
     for (int64_t k = off[v]; k < off[v + 1]; ++k) {
       const int32_t j = idx[k];
       if (j != v && colors[j] >= 0) stamp[colors[j]] = v;

@@ -42,8 +42,8 @@ LPA_FLAG_TRACE = 64
 
 MAX_SWEEPS_RECORDED = 64
 NUM_TIMED_KERNELS = 16
-KERNEL_NAMES = ["compact", "bin0", "bin1", "bin2", "bin3", "bin4", "bin5", "hub_plan", "hub_scan", "hub_finish",
-                "end_sweep", "other", "k12", "k13", "k14", "k15"]
+KERNEL_NAMES = ["compact", "bin0", "bin1", "bin2", "bin3", "bin4", "bin5", "hub_plan", "hub_chunk", "hub_finish",
+                "end_sweep", "hub_part", "other", "k13", "k14", "k15"]
 
 
 class lpa_stats(ctypes.Structure):
@@ -63,6 +63,14 @@ class lpa_stats(ctypes.Structure):
         ("setup_ms", ctypes.c_double),
         ("kernel_ms", ctypes.c_double * NUM_TIMED_KERNELS),
         ("kernel_launches", ctypes.c_int64 * NUM_TIMED_KERNELS),
+        ("bin_vertices", ctypes.c_int64 * 8),
+        ("bin_edges", ctypes.c_int64 * 8),
+        ("bin_changed", ctypes.c_int64 * 8),
+        ("bin_marks", ctypes.c_int64 * 8),
+        ("compact_listed", ctypes.c_int64),
+        ("compact_taken", ctypes.c_int64),
+        ("weight_bytes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def to_dict(self) -> dict:
@@ -76,6 +84,9 @@ class lpa_stats(ctypes.Structure):
             kernel_ms={KERNEL_NAMES[i]: self.kernel_ms[i] for i in range(NUM_TIMED_KERNELS) if self.kernel_launches[i]},
             kernel_launches={KERNEL_NAMES[i]: self.kernel_launches[i] for i in range(NUM_TIMED_KERNELS)
                              if self.kernel_launches[i]},
+            bin_vertices=list(self.bin_vertices[:7]), bin_edges=list(self.bin_edges[:7]),
+            bin_changed=list(self.bin_changed[:7]), bin_marks=list(self.bin_marks[:7]),
+            compact_listed=self.compact_listed, compact_taken=self.compact_taken, weight_bytes=self.weight_bytes,
         )
 
 
@@ -92,6 +103,7 @@ SIGNATURES = {
     "lpa_modularity": (ctypes.c_int, [_vp, _vp, ctypes.c_uint, ctypes.POINTER(_f64)]),
     "lpa_color": (ctypes.c_int, [_vp, _u32, _vp, ctypes.c_uint, ctypes.POINTER(_i32)]),
     "lpa_set_bins": (ctypes.c_int, [_vp, _vp, _i32]),
+    "lpa_set_async_phases": (ctypes.c_int, [_vp, _i32, _i32]),
     "lpa_destroy": (None, [_vp]),
     "lpa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -176,6 +188,10 @@ def lpa_color(handle, seed=0, colors_out=None, flags=0):
 def lpa_set_bins(handle, max_degree=None):
     arr = None if max_degree is None else np.ascontiguousarray(max_degree, dtype=np.int32)
     return load().lpa_set_bins(handle, _ptr(arr), 0 if arr is None else len(arr))
+
+
+def lpa_set_async_phases(handle, phases, by_colour=0):
+    return load().lpa_set_async_phases(handle, phases, int(by_colour))
 
 
 def lpa_destroy(handle):
@@ -266,3 +282,6 @@ class LPAGraph:
 
     def set_bins(self, max_degree=None):
         _check(lpa_set_bins(self.handle, max_degree), "lpa_set_bins")
+
+    def set_async_phases(self, phases, by_colour=False):
+        _check(lpa_set_async_phases(self.handle, phases, by_colour), "lpa_set_async_phases")

@@ -8,17 +8,32 @@ namespace gvelpa {
 typedef unsigned long long u64;
 
 // ---------------------------------------------------------------- sweep bins
-// Vertices with at least one stored entry are split by degree.  A bin is
-// processed by groups of GROUP lanes sharing an LDS open-addressing table of
-// SLOTS 64-bit entries; the last bin ("hub") keeps its tables in HBM.  A
-// table never holds more distinct labels than the vertex has entries, so a
-// bin's degree limit must stay below its SLOTS (load factor <= 1/2 by default).
+// Vertices with at least one stored entry are split by degree.  Bins 0-3 are
+// processed by GROUP lanes of one wave per vertex (one lane per vertex in bin
+// 0), bins 4-5 by a workgroup per vertex; each vertex owns an LDS open-addressing table of SLOTS 64-bit
+// entries.  A table never holds more distinct labels than the vertex has
+// entries, so a bin's degree limit must stay below its SLOTS (the defaults
+// keep the load factor <= 1/2).  The last bin ("hub") splits a vertex over
+// many workgroups (see the hub kernels).
 constexpr int NBINS = 7;
 constexpr int HUB_BIN = NBINS - 1;
-constexpr int BIN_GROUP[NBINS - 1] = {8, 16, 64, 256, 256, 512};
-constexpr int BIN_SLOTS[NBINS - 1] = {16, 64, 256, 1024, 4096, 8192};
-constexpr int DEFAULT_BIN_MAXDEG[NBINS - 1] = {8, 32, 128, 512, 2048, 4096};
-constexpr int HUB_CHUNK = 4096;  // edges per hub work item
+constexpr int BIN_GROUP[NBINS - 1] = {1, 2, 8, 32, 128, 256};
+constexpr int BIN_SLOTS[NBINS - 1] = {8, 32, 128, 512, 2048, 8192};
+constexpr int DEFAULT_BIN_MAXDEG[NBINS - 1] = {4, 16, 64, 256, 1024, 4096};
+
+// Hub path: a hub's entries are cut into chunks of HUB_CHUNK; a chunk's labels
+// are merged in LDS and scattered into 2^pbits label partitions (by hash),
+// each of capacity HUB_PART_CAP entries in HBM; one workgroup then merges each
+// partition in an LDS table of HUB_PART_SLOTS.  Partitions are sized for at
+// most HUB_PART_TARGET distinct labels; a partition that fills up spills into
+// a shared overflow area, so results never depend on the label distribution.
+constexpr int HUB_CHUNK = 2048;
+constexpr int HUB_CHUNK_SLOTS = 4096;
+constexpr int HUB_PART_TARGET = 1024;
+constexpr int HUB_PART_CAP = 1536;
+constexpr int HUB_PART_SLOTS = 2048;
+constexpr int HUB_MAX_PBITS = 12;
+constexpr int64_t HUB_OVERFLOW_CAP = 1 << 22;  // shared spill area for over-full partitions
 
 // Runtime degree limits of bins 0..NBINS-2 (the hub bin takes the rest).
 struct BinLimits {
@@ -86,10 +101,13 @@ struct Ctl {
   double tau;
   int64_t n;
   u64 changed, processed, scanned, gated;  // current sweep
-  u64 hub_chunks;                          // hub work items of the current step
+  u64 hub_chunks, hub_parts;               // hub work items of the current step
   u64 st_changed[MAX_REC], st_processed[MAX_REC], st_scanned[MAX_REC], st_gated[MAX_REC];
   u64 t_start, t_sweep[MAX_REC];
   u64 verify_changed, total_changed;
+  // run totals per bin (byte accounting of the kernels)
+  u64 bin_vertices[NBINS], bin_edges[NBINS], bin_changed[NBINS], bin_marks[NBINS];
+  u64 compact_listed, compact_taken;
 };
 
 // Per-step arguments of the scan kernels.
@@ -103,15 +121,30 @@ struct ScanArgs {
   const int32_t *fcount;  // its length (device)
   Ctl *ctl;
   int prune;
-  // hub path
-  u64 *htab;
-  const int64_t *hub_toff;   // per frontier entry: table offset (entries)
-  const int32_t *hub_tbits;  // per frontier entry: log2 table size
-  const u64 *hub_cstart;     // per frontier entry: first chunk id (exclusive scan)
-  const int32_t *hub_ids;    // sorted ids of every hub vertex
-  const int64_t *hub_toff_all;
-  const int32_t *hub_tbits_all;
+  int bin;
+};
+
+// Hub metadata (per hub, sorted by id) and per-step scratch.
+struct HubArgs {
   int32_t n_hubs;
+  int32_t part_cap;          // entries kept per partition before spilling (<= HUB_PART_CAP)
+  const int32_t *ids;        // sorted hub ids
+  const int32_t *chunks;     // chunks of each hub
+  const int32_t *pbits;      // log2 partitions of each hub
+  const int64_t *pair_base;  // first pair slot of each hub (partition p at pair_base + p * HUB_PART_CAP)
+  const int64_t *cnt_base;   // first partition counter of each hub
+  u64 *pairs;                // (label << 32 | weight) entries
+  int32_t *pcnt;             // entries written per (hub, partition); zero between steps
+  u64 *partbest;             // best key per (frontier hub, partition) of the step
+  uint32_t *ovf;             // spill entries: (global part, label, weight, unused)
+  u64 *ovf_count;
+  int32_t *ord;              // per frontier entry: hub ordinal
+  u64 *cstart;               // per frontier entry: first chunk id of the step
+  u64 *pstart;               // per frontier entry: first partition id of the step
+  int32_t *chunk_owner;      // per chunk id of the step: frontier entry
+  int32_t *part_owner;       // per partition id of the step: frontier entry
+  int32_t *changed;          // per frontier entry: 1 if the hub took a new label
+  int32_t max_pbits;         // largest pbits of any hub (sizes the chunk kernel's LDS)
 };
 
 // Wave64 helpers.

@@ -38,7 +38,8 @@ enum TimedKind {
   TK_HUB_SCAN = 8,
   TK_HUB_FINISH = 9,
   TK_END_SWEEP = 10,
-  TK_OTHER = 11
+  TK_HUB_PART = 11,
+  TK_OTHER = 12
 };
 
 }  // namespace
@@ -64,12 +65,17 @@ struct lpa_graph {
   BinLimits lim{};
   bool lists_ready = false;
   int32_t *alist = nullptr;
-  int64_t abounds[NBINS + 1] = {0};
+  int nphase = 16;                  // asynchronous mode: steps per sweep
+  bool async_by_colour = true;      // steps made of consecutive colour classes (else a hash of the id)
+  std::vector<int32_t> h_async_group;  // per vertex step of the asynchronous schedule (host)
+  std::vector<int64_t> astart;      // nphase * NBINS + 1 list bounds
+  std::vector<int64_t> ph_hub_chunks, ph_hub_parts;
   // deterministic schedule
   int32_t *color = nullptr;
   int32_t ncol = 0;
   uint32_t color_seed = 0;
   bool colored = false;
+  int32_t color_rounds = 0;
   bool dlists_ready = false;
   int32_t *dlist = nullptr;
   std::vector<int64_t> dstart;  // ncol * NBINS + 1
@@ -77,17 +83,24 @@ struct lpa_graph {
   int32_t *front = nullptr;
   int32_t *fcount = nullptr;
   int fcount_cap = 0;
-  // hubs
+  // hubs (sorted by id) and per-step scratch
   int32_t n_hubs = 0;
-  int32_t *hub_ids = nullptr;
-  int64_t *hub_toff_all = nullptr;
-  int32_t *hub_tbits_all = nullptr;
-  u64 *htab = nullptr;
-  int64_t htab_entries = 0;
-  std::vector<int64_t> h_hub_chunks;  // per sorted hub: work items
-  u64 *hub_cstart = nullptr;
-  int64_t *hub_toff = nullptr;
-  int32_t *hub_tbits = nullptr;
+  int64_t hub_chunks_total = 0, hub_parts_total = 0;
+  int32_t hub_part_cap = HUB_PART_CAP;
+  std::vector<int32_t> h_hub_ids, h_hub_chunks, h_hub_parts;
+  std::vector<int64_t> col_hub_chunks, col_hub_parts;  // per colour class (deterministic grids)
+  std::vector<int32_t> h_color;
+  int32_t *hub_ids = nullptr, *hub_chunks = nullptr, *hub_pbits = nullptr;
+  int64_t *hub_pair_base = nullptr, *hub_cnt_base = nullptr;
+  u64 *hub_pairs = nullptr;
+  int32_t *hub_pcnt = nullptr;
+  u64 *hub_partbest = nullptr;
+  uint32_t *hub_ovf = nullptr;
+  u64 *hub_ovf_count = nullptr;
+  int32_t *hub_ord = nullptr;
+  u64 *hub_cstart = nullptr, *hub_pstart = nullptr;
+  int32_t *hub_chunk_owner = nullptr, *hub_part_owner = nullptr, *hub_changed = nullptr;
+  int32_t hub_max_pbits = 0;
   // control
   Ctl *ctl = nullptr;
   int32_t *host_done = nullptr;
@@ -254,10 +267,11 @@ void tk_end(lpa_graph *g, hipStream_t st, int kind) {
 
 // ---------------------------------------------------------------- lists
 
-void build_lists(lpa_graph *g, const int32_t *color, int nkeys, int32_t *list, std::vector<int64_t> &starts) {
+void build_lists(lpa_graph *g, const int32_t *color, const int32_t *cmap, int nphase, int nkeys, int32_t *list,
+                 std::vector<int64_t> &starts) {
   int32_t *hist = dalloc_n<int32_t>(g, nkeys);
   HIP_OK(hipMemsetAsync(hist, 0, sizeof(int32_t) * nkeys, g->stream));
-  launch_bin_hist(g->off, g->n, color, g->lim, hist, g->stream);
+  launch_bin_hist(g->off, g->n, color, cmap, nphase, g->lim, hist, nkeys, g->stream);
   std::vector<int32_t> h(nkeys);
   HIP_OK(hipMemcpyAsync(h.data(), hist, sizeof(int32_t) * nkeys, hipMemcpyDeviceToHost, g->stream));
   HIP_OK(hipStreamSynchronize(g->stream));
@@ -266,62 +280,104 @@ void build_lists(lpa_graph *g, const int32_t *color, int nkeys, int32_t *list, s
   std::vector<int32_t> cur(nkeys);
   for (int k = 0; k < nkeys; ++k) cur[k] = (int32_t)starts[k];
   HIP_OK(hipMemcpyAsync(hist, cur.data(), sizeof(int32_t) * nkeys, hipMemcpyHostToDevice, g->stream));
-  launch_bin_scatter(g->off, g->n, color, g->lim, hist, list, g->stream);
+  launch_bin_scatter(g->off, g->n, color, cmap, nphase, g->lim, hist, list, nkeys, g->stream);
   HIP_OK(hipStreamSynchronize(g->stream));
   dfree(g, hist);
 }
 
 void build_hubs(lpa_graph *g) {
-  dfree(g, g->hub_ids);
-  dfree(g, g->hub_toff_all);
-  dfree(g, g->hub_tbits_all);
-  dfree(g, g->htab);
-  dfree(g, g->hub_cstart);
-  dfree(g, g->hub_toff);
-  dfree(g, g->hub_tbits);
-  g->hub_ids = nullptr;
-  g->hub_toff_all = nullptr;
-  g->hub_tbits_all = nullptr;
-  g->htab = nullptr;
-  g->hub_cstart = nullptr;
-  g->hub_toff = nullptr;
-  g->hub_tbits = nullptr;
+  void **bufs[] = {(void **)&g->hub_ids, (void **)&g->hub_chunks, (void **)&g->hub_pbits,
+                   (void **)&g->hub_pair_base, (void **)&g->hub_cnt_base, (void **)&g->hub_pairs,
+                   (void **)&g->hub_pcnt, (void **)&g->hub_partbest, (void **)&g->hub_ovf,
+                   (void **)&g->hub_ovf_count, (void **)&g->hub_ord, (void **)&g->hub_cstart,
+                   (void **)&g->hub_pstart, (void **)&g->hub_chunk_owner, (void **)&g->hub_part_owner,
+                   (void **)&g->hub_changed};
+  for (void **b : bufs) {
+    dfree(g, *b);
+    *b = nullptr;
+  }
   std::vector<int32_t> ids;
   const int32_t lim = g->lim.maxdeg[NBINS - 2];
   for (int64_t v = 0; v < g->n; ++v)
     if (g->h_off[v + 1] - g->h_off[v] > lim) ids.push_back((int32_t)v);
-  g->n_hubs = (int32_t)ids.size();
-  std::vector<int64_t> toff(ids.size() + 1, 0);
-  std::vector<int32_t> tbits(ids.size() + 1, 0);
-  g->h_hub_chunks.assign(ids.size(), 0);
-  int64_t total = 0;
-  for (size_t k = 0; k < ids.size(); ++k) {
+  const size_t nh = ids.size();
+  g->n_hubs = (int32_t)nh;
+  std::vector<int32_t> chunks(nh), pbits(nh);
+  std::vector<int64_t> pair_base(nh), cnt_base(nh);
+  int64_t pairs = 0, parts = 0, nch = 0;
+  for (size_t k = 0; k < nh; ++k) {
     const int64_t deg = g->h_off[ids[k] + 1] - g->h_off[ids[k]];
-    int bits = 1;
-    while (((int64_t)1 << bits) < 2 * deg) ++bits;
-    toff[k] = total;
-    tbits[k] = bits;
-    total += (int64_t)1 << bits;
-    g->h_hub_chunks[k] = (deg + HUB_CHUNK - 1) / HUB_CHUNK;
+    chunks[k] = (int32_t)((deg + HUB_CHUNK - 1) / HUB_CHUNK);
+    int pb = 0;
+    while (pb < HUB_MAX_PBITS && ((int64_t)HUB_PART_TARGET << pb) < deg) ++pb;
+    pbits[k] = pb;
+    pair_base[k] = pairs;
+    cnt_base[k] = parts;
+    pairs += ((int64_t)1 << pb) * HUB_PART_CAP;
+    parts += (int64_t)1 << pb;
+    nch += chunks[k];
   }
-  g->htab_entries = total;
-  const int64_t nh = std::max<int64_t>(1, (int64_t)ids.size());
-  g->hub_ids = dalloc_n<int32_t>(g, nh);
-  g->hub_toff_all = dalloc_n<int64_t>(g, nh);
-  g->hub_tbits_all = dalloc_n<int32_t>(g, nh);
-  g->hub_cstart = dalloc_n<u64>(g, nh);
-  g->hub_toff = dalloc_n<int64_t>(g, nh);
-  g->hub_tbits = dalloc_n<int32_t>(g, nh);
-  g->htab = dalloc_n<u64>(g, std::max<int64_t>(total, 1));
-  if (!ids.empty()) {
-    HIP_OK(hipMemcpyAsync(g->hub_ids, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, g->stream));
-    HIP_OK(hipMemcpyAsync(g->hub_toff_all, toff.data(), sizeof(int64_t) * ids.size(), hipMemcpyHostToDevice,
+  g->hub_chunks_total = nch;
+  g->hub_parts_total = parts;
+  g->hub_max_pbits = 0;
+  for (int32_t pb : pbits) g->hub_max_pbits = std::max(g->hub_max_pbits, pb);
+  g->hub_chunk_owner = dalloc_n<int32_t>(g, std::max<int64_t>(1, nch));
+  g->hub_part_owner = dalloc_n<int32_t>(g, std::max<int64_t>(1, parts));
+  g->h_hub_ids = ids;
+  g->h_hub_chunks = chunks;
+  g->h_hub_parts.resize(nh);
+  for (size_t k = 0; k < nh; ++k) g->h_hub_parts[k] = 1 << pbits[k];
+  const int64_t n1 = std::max<int64_t>(1, (int64_t)nh);
+  g->hub_ids = dalloc_n<int32_t>(g, n1);
+  g->hub_chunks = dalloc_n<int32_t>(g, n1);
+  g->hub_pbits = dalloc_n<int32_t>(g, n1);
+  g->hub_pair_base = dalloc_n<int64_t>(g, n1);
+  g->hub_cnt_base = dalloc_n<int64_t>(g, n1);
+  g->hub_ord = dalloc_n<int32_t>(g, n1);
+  g->hub_cstart = dalloc_n<u64>(g, n1);
+  g->hub_pstart = dalloc_n<u64>(g, n1);
+  g->hub_changed = dalloc_n<int32_t>(g, n1);
+  g->hub_pairs = dalloc_n<u64>(g, std::max<int64_t>(1, pairs));
+  g->hub_pcnt = dalloc_n<int32_t>(g, std::max<int64_t>(1, parts));
+  g->hub_partbest = dalloc_n<u64>(g, std::max<int64_t>(1, parts));
+  g->hub_ovf_count = dalloc_n<u64>(g, 1);
+  g->hub_ovf = dalloc_n<uint32_t>(g, nh ? 4 * HUB_OVERFLOW_CAP : 4);
+  HIP_OK(hipMemsetAsync(g->hub_pcnt, 0, sizeof(int32_t) * std::max<int64_t>(1, parts), g->stream));
+  HIP_OK(hipMemsetAsync(g->hub_ovf_count, 0, sizeof(u64), g->stream));
+  if (nh) {
+    HIP_OK(hipMemcpyAsync(g->hub_ids, ids.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, g->stream));
+    HIP_OK(hipMemcpyAsync(g->hub_chunks, chunks.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, g->stream));
+    HIP_OK(hipMemcpyAsync(g->hub_pbits, pbits.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, g->stream));
+    HIP_OK(hipMemcpyAsync(g->hub_pair_base, pair_base.data(), sizeof(int64_t) * nh, hipMemcpyHostToDevice,
                           g->stream));
-    HIP_OK(hipMemcpyAsync(g->hub_tbits_all, tbits.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice,
+    HIP_OK(hipMemcpyAsync(g->hub_cnt_base, cnt_base.data(), sizeof(int64_t) * nh, hipMemcpyHostToDevice,
                           g->stream));
-    launch_fill_u64(g->htab, total, EMPTY, g->stream);
   }
   HIP_OK(hipStreamSynchronize(g->stream));
+}
+
+HubArgs hub_args(lpa_graph *g) {
+  HubArgs h{};
+  h.n_hubs = g->n_hubs;
+  h.part_cap = g->hub_part_cap;
+  h.ids = g->hub_ids;
+  h.chunks = g->hub_chunks;
+  h.pbits = g->hub_pbits;
+  h.pair_base = g->hub_pair_base;
+  h.cnt_base = g->hub_cnt_base;
+  h.pairs = g->hub_pairs;
+  h.pcnt = g->hub_pcnt;
+  h.partbest = g->hub_partbest;
+  h.ovf = g->hub_ovf;
+  h.ovf_count = g->hub_ovf_count;
+  h.ord = g->hub_ord;
+  h.cstart = g->hub_cstart;
+  h.pstart = g->hub_pstart;
+  h.chunk_owner = g->hub_chunk_owner;
+  h.part_owner = g->hub_part_owner;
+  h.changed = g->hub_changed;
+  h.max_pbits = g->hub_max_pbits;
+  return h;
 }
 
 void ensure_fcount(lpa_graph *g, int need) {
@@ -332,44 +388,85 @@ void ensure_fcount(lpa_graph *g, int need) {
   HIP_OK(hipMemsetAsync(g->fcount, 0, sizeof(int32_t) * need, g->stream));
 }
 
+void ensure_colored(lpa_graph *g, uint32_t seed);
+
+// Asynchronous lists: every flagged vertex of a step is processed at once;
+// the steps of a sweep are either nphase groups by a hash of the id, or runs
+// of consecutive colour classes holding about n_active / nphase vertices each.
 void ensure_lists(lpa_graph *g) {
   if (g->lists_ready) return;
   drop_graphs(g);
   if (!g->alist) g->alist = dalloc_n<int32_t>(g, g->n_active);
   if (!g->front) g->front = dalloc_n<int32_t>(g, g->n_active);
-  std::vector<int64_t> starts;
-  build_lists(g, nullptr, NBINS, g->alist, starts);
-  for (int b = 0; b <= NBINS; ++b) g->abounds[b] = starts[b];
   build_hubs(g);
-  ensure_fcount(g, NBINS);
+  std::vector<int32_t> cmap;
+  if (g->async_by_colour) {
+    ensure_colored(g, g->colored ? g->color_seed : 0u);
+    std::vector<int64_t> csize(std::max(1, g->ncol), 0);
+    for (int64_t v = 0; v < g->n; ++v)
+      if (g->h_off[v + 1] > g->h_off[v]) csize[g->h_color[v]] += 1;
+    cmap.assign(csize.size(), 0);
+    const double per = std::max(1.0, (double)g->n_active / g->nphase);
+    int64_t before = 0;
+    for (size_t c = 0; c < csize.size(); ++c) {
+      cmap[c] = std::min(g->nphase - 1, (int)((double)before / per));
+      before += csize[c];
+    }
+  }
+  int32_t *d_cmap = nullptr;
+  if (!cmap.empty()) {
+    d_cmap = dalloc_n<int32_t>(g, (int64_t)cmap.size());
+    HIP_OK(hipMemcpyAsync(d_cmap, cmap.data(), sizeof(int32_t) * cmap.size(), hipMemcpyHostToDevice, g->stream));
+  }
+  build_lists(g, g->async_by_colour ? g->color : nullptr, d_cmap, g->nphase, g->nphase * NBINS, g->alist, g->astart);
+  dfree(g, d_cmap);
+  ensure_fcount(g, g->nphase * NBINS);
+  g->ph_hub_chunks.assign(g->nphase, 0);
+  g->ph_hub_parts.assign(g->nphase, 0);
+  for (size_t k = 0; k < g->h_hub_ids.size(); ++k) {
+    const uint32_t v = (uint32_t)g->h_hub_ids[k];
+    int ph = 0;
+    if (g->async_by_colour) ph = cmap[g->h_color[v]];
+    else if (g->nphase > 1) ph = (int)(fmix32(v ^ phase_seed()) % (uint32_t)g->nphase);
+    g->ph_hub_chunks[ph] += g->h_hub_chunks[k];
+    g->ph_hub_parts[ph] += g->h_hub_parts[k];
+  }
   g->lists_ready = true;
-  g->dlists_ready = false;
 }
 
 void ensure_colored(lpa_graph *g, uint32_t seed) {
   if (g->colored && g->color_seed == seed) return;
   drop_graphs(g);
   if (!g->color) g->color = dalloc_n<int32_t>(g, g->n);
-  int32_t *work = dalloc_n<int32_t>(g, g->n);
-  int32_t *next = dalloc_n<int32_t>(g, g->n);
-  int32_t *cnt = dalloc_n<int32_t>(g, 1);
-  launch_color_init(g->color, work, g->n, g->stream);
-  int64_t wlen = g->n;
-  while (wlen > 0) {
-    HIP_OK(hipMemsetAsync(cnt, 0, sizeof(int32_t), g->stream));
-    launch_color_round(g->off, g->idx, g->color, work, (int32_t)wlen, next, cnt, seed, g->stream);
-    int32_t h = 0;
-    HIP_OK(hipMemcpyAsync(&h, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+  int32_t *work[2] = {dalloc_n<int32_t>(g, g->n), dalloc_n<int32_t>(g, g->n)};
+  int32_t *pending = dalloc_n<int32_t>(g, g->n);
+  u64 *pk = dalloc_n<u64>(g, g->n);
+  constexpr int MAX_ROUNDS = 1 << 22, BATCH = 64;
+  int32_t *counts = dalloc_n<int32_t>(g, MAX_ROUNDS + 2);
+  HIP_OK(hipMemsetAsync(counts, 0, sizeof(int32_t) * (MAX_ROUNDS + 2), g->stream));
+  launch_color_init(g->off, g->idx, g->color, pk, pending, work[0], counts, g->n, seed, g->stream);
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + 3) / 4, (int64_t)g->cu_count * 16));
+  int r = 0;
+  for (;;) {
+    // rounds are queued in batches; a round with an empty list exits at once
+    for (int k = 0; k < BATCH && r < MAX_ROUNDS; ++k, ++r)
+      launch_color_round(g->off, g->idx, g->color, pk, pending, work[r & 1], work[(r + 1) & 1], counts, r, blocks,
+                         g->stream);
+    int32_t left = 0;
+    HIP_OK(hipMemcpyAsync(&left, counts + r, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
     HIP_OK(hipStreamSynchronize(g->stream));
-    if (h >= wlen) throw Status{LPA_ERR_INTERNAL};  // every round colours at least one vertex
-    wlen = h;
-    std::swap(work, next);
+    if (left == 0) break;
+    if (r >= MAX_ROUNDS) throw Status{LPA_ERR_INTERNAL};
   }
-  dfree(g, work);
-  dfree(g, next);
-  dfree(g, cnt);
+  g->color_rounds = r;
+  dfree(g, work[0]);
+  dfree(g, work[1]);
+  dfree(g, pending);
+  dfree(g, pk);
+  dfree(g, counts);
   // number of classes = 1 + largest colour
-  std::vector<int32_t> hc((size_t)g->n);
+  std::vector<int32_t> &hc = g->h_color;
+  hc.assign((size_t)g->n, 0);
   if (g->n) HIP_OK(hipMemcpy(hc.data(), g->color, sizeof(int32_t) * g->n, hipMemcpyDeviceToHost));
   int32_t mx = -1;
   for (int32_t c : hc) mx = std::max(mx, c);
@@ -377,6 +474,7 @@ void ensure_colored(lpa_graph *g, uint32_t seed) {
   g->color_seed = seed;
   g->colored = true;
   g->dlists_ready = false;
+  if (g->async_by_colour) g->lists_ready = false;
 }
 
 void ensure_dlists(lpa_graph *g) {
@@ -385,8 +483,15 @@ void ensure_dlists(lpa_graph *g) {
   drop_graphs(g);
   if (!g->dlist) g->dlist = dalloc_n<int32_t>(g, g->n_active);
   const int nkeys = std::max(1, g->ncol) * NBINS;
-  build_lists(g, g->color, nkeys, g->dlist, g->dstart);
+  build_lists(g, g->color, nullptr, 0, nkeys, g->dlist, g->dstart);
   ensure_fcount(g, nkeys);
+  g->col_hub_chunks.assign(std::max(1, g->ncol), 0);
+  g->col_hub_parts.assign(std::max(1, g->ncol), 0);
+  for (size_t k = 0; k < g->h_hub_ids.size(); ++k) {
+    const int c = g->h_color[g->h_hub_ids[k]];
+    g->col_hub_chunks[c] += g->h_hub_chunks[k];
+    g->col_hub_parts[c] += g->h_hub_parts[k];
+  }
   g->dlists_ready = true;
 }
 
@@ -401,20 +506,13 @@ ScanArgs base_args(lpa_graph *g, int prune) {
   a.F = g->F;
   a.ctl = g->ctl;
   a.prune = prune;
-  a.htab = g->htab;
-  a.hub_toff = g->hub_toff;
-  a.hub_tbits = g->hub_tbits;
-  a.hub_cstart = g->hub_cstart;
-  a.hub_ids = g->hub_ids;
-  a.hub_toff_all = g->hub_toff_all;
-  a.hub_tbits_all = g->hub_tbits_all;
-  a.n_hubs = g->n_hubs;
   return a;
 }
 
 // One step: compact the flagged vertices of `list` (bin segments given by
 // absolute `bounds` into list/front), then process the bins, hubs first.
-void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t *bounds, int32_t *fcount, int prune) {
+void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t *bounds, int32_t *fcount, int prune,
+               int64_t hub_chunks, int64_t hub_parts) {
   const int64_t base = bounds[0];
   const int64_t len = bounds[NBINS] - base;
   if (len <= 0) return;
@@ -428,30 +526,32 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
   ca.ctl = g->ctl;
   ca.prune = prune;
   tk_begin(g, st);
-  launch_compact(ca, grid_cap(len, 256, 8192), st);
+  launch_compact(ca, grid_cap(len, 2048, 4096), st);
   tk_end(g, st, TK_COMPACT);
   const int max_blocks = g->cu_count * 8;
   for (int b = NBINS - 1; b >= 0; --b) {
     const int64_t seg = bounds[b + 1] - bounds[b];
     if (seg <= 0) continue;
     ScanArgs a = base_args(g, prune);
+    a.bin = b;
     a.front = g->front + bounds[b];
     a.fcount = fcount + b;
     if (b == HUB_BIN) {
-      // work items of every hub in this segment bound the hub step's grid
-      int64_t items = 0;
-      for (int64_t c : g->h_hub_chunks) items += c;
+      const HubArgs h = hub_args(g);
       tk_begin(g, st);
-      launch_hub_plan(a, g->hub_cstart, g->hub_toff, g->hub_tbits, st);
+      launch_hub_plan(a, h, grid_cap(seg, 1, max_blocks), st);
       tk_end(g, st, TK_HUB_PLAN);
       tk_begin(g, st);
-      launch_hub_scan(g->wk, grid_cap(items, 1, max_blocks * 2), st, a, g->hub_cstart, g->hub_toff, g->hub_tbits);
+      launch_hub_chunk(g->wk, grid_cap(hub_chunks, 1, max_blocks * 2), st, a, h);
       tk_end(g, st, TK_HUB_SCAN);
       tk_begin(g, st);
-      launch_hub_finish(grid_cap(seg, 1, max_blocks), st, a, g->hub_toff, g->hub_tbits);
+      launch_hub_part(grid_cap(hub_parts, 1, max_blocks * 2), st, a, h);
+      tk_end(g, st, TK_HUB_PART);
+      tk_begin(g, st);
+      launch_hub_finish(grid_cap(seg, 4, max_blocks), grid_cap(hub_chunks, 1, max_blocks * 2), prune, st, a, h);
       tk_end(g, st, TK_HUB_FINISH);
     } else {
-      const int per_block = b <= 2 ? 256 / BIN_GROUP[b] : 1;
+      const int per_block = b <= 3 ? 256 / BIN_GROUP[b] : 1;
       tk_begin(g, st);
       launch_scan_bin(b, g->wk, grid_cap(seg, per_block, max_blocks), st, a);
       tk_end(g, st, TK_BIN0 + b);
@@ -462,11 +562,14 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
 void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune) {
   if (mode == LPA_MODE_DETERMINISTIC) {
     for (int c = 0; c < g->ncol; ++c)
-      emit_step(g, st, g->dlist, &g->dstart[(size_t)c * NBINS], g->fcount + (size_t)c * NBINS, prune);
+      emit_step(g, st, g->dlist, &g->dstart[(size_t)c * NBINS], g->fcount + (size_t)c * NBINS, prune,
+                g->col_hub_chunks[c], g->col_hub_parts[c]);
   } else {
-    emit_step(g, st, g->alist, g->abounds, g->fcount, prune);
+    for (int ph = 0; ph < g->nphase; ++ph)
+      emit_step(g, st, g->alist, &g->astart[(size_t)ph * NBINS], g->fcount + (size_t)ph * NBINS, prune,
+                g->ph_hub_chunks[ph], g->ph_hub_parts[ph]);
   }
-  const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : NBINS;
+  const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : g->nphase * NBINS;
   tk_begin(g, st);
   launch_end_sweep(g->ctl, g->fcount, nfc, g->host_done_dev, st);
   tk_end(g, st, TK_END_SWEEP);
@@ -575,6 +678,8 @@ int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, co
   g->n = n;
   g->m = m;
   if (const char *b = std::getenv("GVELPA_DEVICE_BUDGET_BYTES")) g->budget = (size_t)std::strtoull(b, nullptr, 10);
+  if (const char *c = std::getenv("GVELPA_HUB_PART_CAP"))  // testing: force the partition spill path
+    g->hub_part_cap = (int32_t)std::max(1L, std::min((long)HUB_PART_CAP, std::strtol(c, nullptr, 10)));
   for (int b = 0; b < NBINS - 1; ++b) g->lim.maxdeg[b] = DEFAULT_BIN_MAXDEG[b];
   int rc = run_guarded(g, [&]() -> int {
     hipDeviceProp_t prop;
@@ -654,7 +759,6 @@ int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, co
     g->ctl = dalloc_n<Ctl>(g, 1);
     HIP_OK(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream));
     launch_init_state(g->off, g->C, g->F, n, 1, 1, 0, g->stream);
-    ensure_lists(g);
     HIP_OK(hipStreamSynchronize(g->stream));
     return LPA_OK;
   });
@@ -682,6 +786,20 @@ int lpa_set_bins(lpa_graph *g, const int32_t *max_degree, int32_t count) {
     }
     if (std::memcmp(&lim, &g->lim, sizeof(lim)) != 0) {
       g->lim = lim;
+      g->lists_ready = false;
+      g->dlists_ready = false;
+      drop_graphs(g);
+    }
+    return LPA_OK;
+  });
+}
+
+int lpa_set_async_phases(lpa_graph *g, int32_t phases, int32_t by_colour) {
+  return run_guarded(g, [&]() -> int {
+    if (phases < 1 || phases > 1024) return LPA_ERR_INVALID_ARG;
+    if (phases != g->nphase || (by_colour != 0) != g->async_by_colour) {
+      g->nphase = phases;
+      g->async_by_colour = by_colour != 0;
       g->lists_ready = false;
       g->dlists_ready = false;
       drop_graphs(g);
@@ -746,7 +864,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     g->timing = timing;
     g->ev_used = 0;
     HIP_OK(hipEventRecord(t0, g->stream));
-    const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : NBINS;
+    const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : g->nphase * NBINS;
     launch_run_begin(g->ctl, tolerance, max_iters, g->n, g->fcount, nfc, g->host_done_dev, g->stream);
     for (int s = 0; s < max_iters; ++s) {
       if (exec) HIP_OK(hipGraphLaunch(exec, g->stream));
@@ -787,6 +905,15 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       stats->verify_changed = (int64_t)h.verify_changed;
       stats->total_ms = run_ms;
       stats->setup_ms = setup_ms;
+      for (int b = 0; b < NBINS; ++b) {
+        stats->bin_vertices[b] = (int64_t)h.bin_vertices[b];
+        stats->bin_edges[b] = (int64_t)h.bin_edges[b];
+        stats->bin_changed[b] = (int64_t)h.bin_changed[b];
+        stats->bin_marks[b] = (int64_t)h.bin_marks[b];
+      }
+      stats->compact_listed = (int64_t)h.compact_listed;
+      stats->compact_taken = (int64_t)h.compact_taken;
+      stats->weight_bytes = g->wk == W_UNIT ? 0 : (g->wk == W_U8 ? 1 : 4);
       if (timing) {
         for (size_t k = 0; k < g->ev_used; ++k) {
           float ms = 0;
@@ -797,8 +924,9 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       }
     }
     if (h.error) {
-      // leave the hub tables clean for the next run
-      if (g->htab_entries) launch_fill_u64(g->htab, g->htab_entries, EMPTY, g->stream);
+      // leave the hub partitions empty for the next run
+      if (g->hub_parts_total)
+        HIP_OK(hipMemsetAsync(g->hub_pcnt, 0, sizeof(int32_t) * g->hub_parts_total, g->stream));
       HIP_OK(hipStreamSynchronize(g->stream));
       return LPA_ERR_INTERNAL;
     }

@@ -1,0 +1,282 @@
+// Hub path of the sweep: vertices whose degree exceeds the largest LDS bin.
+//
+// A hub's scan (scanCommunities of Algorithm 1) is spread over many
+// workgroups without any table in HBM:
+//   k_hub_plan    per flagged hub: work items (chunks, label partitions);
+//   k_hub_owner   work item -> hub maps;
+//   k_hub_chunk   per chunk of HUB_CHUNK entries: gather the neighbour
+//                 labels, merge equal labels in an LDS table, and append the
+//                 merged (label, weight) pairs to the hub's label partitions;
+//   k_hub_part    per (hub, partition): merge the partition's pairs in LDS and
+//                 keep its heaviest label (smallest id on ties);
+//   k_hub_decide  per hub: best over the partitions, update;
+//   k_hub_mark    per chunk of a hub that changed: flag the neighbours.
+// Every label falls in exactly one partition, so the per-partition maxima
+// combine into the strict argmax of Eq. (2).
+#include "sweep_kernels.hpp"
+#include "tables.hpp"
+
+namespace gvelpa {
+
+__device__ __forceinline__ uint32_t part_of(uint32_t lbl, int pbits) {
+  return pbits ? (fmix32(lbl) >> (32 - pbits)) : 0u;
+}
+
+__global__ __launch_bounds__(1024) void k_hub_plan(ScanArgs a, HubArgs h) {
+  if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
+  __shared__ u64 wsum[2][16];
+  __shared__ u64 s_carry[2];
+  if (threadIdx.x == 0) {
+    s_carry[0] = s_carry[1] = 0;
+    *h.ovf_count = 0;
+  }
+  __syncthreads();
+  const int count = *a.fcount;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int tile = 0; tile < count; tile += 1024) {
+    const int i = tile + threadIdx.x;
+    u64 kc = 0, kp = 0;
+    if (i < count) {
+      const int v = a.front[i];
+      int lo = 0, hi = h.n_hubs;  // lower bound of v among the sorted hub ids
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (h.ids[mid] < v) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo >= h.n_hubs || h.ids[lo] != v) {  // every hub-bin vertex is listed; never expected
+        atomicOr(&a.ctl->error, 4);
+        lo = 0;
+      } else {
+        kc = (u64)h.chunks[lo];
+        kp = (u64)1 << h.pbits[lo];
+      }
+      h.ord[i] = lo;
+    }
+    u64 xc = kc, xp = kp;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const u64 yc = (u64)__shfl_up((unsigned long long)xc, d, 64);
+      const u64 yp = (u64)__shfl_up((unsigned long long)xp, d, 64);
+      if (lane >= d) {
+        xc += yc;
+        xp += yp;
+      }
+    }
+    if (lane == 63) {
+      wsum[0][wv] = xc;
+      wsum[1][wv] = xp;
+    }
+    __syncthreads();
+    u64 bc = 0, bp = 0;
+    for (int k = 0; k < wv; ++k) {
+      bc += wsum[0][k];
+      bp += wsum[1][k];
+    }
+    const u64 cc = s_carry[0], cp = s_carry[1];
+    if (i < count) {
+      h.cstart[i] = cc + bc + xc - kc;
+      h.pstart[i] = cp + bp + xp - kp;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) {
+      s_carry[0] = cc + bc + xc;
+      s_carry[1] = cp + bp + xp;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.ctl->hub_chunks = s_carry[0];
+    a.ctl->hub_parts = s_carry[1];
+  }
+}
+
+// Owner maps of the step's work items (chunk / partition -> frontier entry),
+// one workgroup per flagged hub.
+__global__ __launch_bounds__(256) void k_hub_owner(ScanArgs a, HubArgs h) {
+  if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
+  const int count = *a.fcount;
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const int k = h.ord[i];
+    const int kc = h.chunks[k], kp = 1 << h.pbits[k];
+    const u64 c0 = h.cstart[i], p0 = h.pstart[i];
+    for (int c = threadIdx.x; c < kc; c += 256) h.chunk_owner[c0 + c] = i;
+    for (int p = threadIdx.x; p < kp; p += 256) h.part_owner[p0 + p] = i;
+  }
+}
+
+template <int WK>
+__global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
+  if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
+  constexpr int BITS = __builtin_ctz(HUB_CHUNK_SLOTS);
+  __shared__ u64 T[HUB_CHUNK_SLOTS];
+  extern __shared__ int32_t dyn[];  // 2 << max_pbits counters
+  int32_t *hist = dyn;
+  int32_t *pbase = dyn + (1 << h.max_pbits);
+  const u64 total = a.ctl->hub_chunks;
+  int err = 0;
+  for (u64 c = blockIdx.x; c < total; c += gridDim.x) {
+    const int i = h.chunk_owner[c];
+    const int v = a.front[i];
+    const int k = h.ord[i];
+    const int pb = h.pbits[k];
+    const int P = 1 << pb;
+    const int64_t eb = a.off[v] + (int64_t)(c - h.cstart[i]) * HUB_CHUNK;
+    const int64_t ee = min(a.off[v + 1], eb + (int64_t)HUB_CHUNK);
+    for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) T[s] = EMPTY;
+    for (int p = threadIdx.x; p < P; p += 256) hist[p] = 0;
+    __syncthreads();
+    err |= scan_row<256, 8, BITS, WK>(a.idx, a.w, a.C, eb, ee, v, threadIdx.x, T);
+    __syncthreads();
+    for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) {
+      const u64 x = T[s];
+      if (x != EMPTY) atomicAdd(&hist[part_of((uint32_t)(x >> 32), pb)], 1);
+    }
+    __syncthreads();
+    int32_t *cnt = h.pcnt + h.cnt_base[k];
+    for (int p = threadIdx.x; p < P; p += 256) {
+      const int n = hist[p];
+      if (n) pbase[p] = atomicAdd(&cnt[p], n);
+      hist[p] = 0;
+    }
+    __syncthreads();
+    u64 *dst = h.pairs + h.pair_base[k];
+    for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) {
+      const u64 x = T[s];
+      if (x == EMPTY) continue;
+      const uint32_t p = part_of((uint32_t)(x >> 32), pb);
+      const int pos = pbase[p] + atomicAdd(&hist[p], 1);
+      if (pos < h.part_cap) {
+        dst[(int64_t)p * HUB_PART_CAP + pos] = x;
+      } else {  // partition full: spill (merged by the partition's workgroup)
+        const u64 q = atomicAdd(h.ovf_count, (u64)1);
+        if (q < (u64)HUB_OVERFLOW_CAP) {
+          uint32_t *o = h.ovf + 4 * q;
+          o[0] = (uint32_t)(h.pstart[i] + p);
+          o[1] = (uint32_t)(x >> 32);
+          o[2] = (uint32_t)x;
+        } else {
+          err |= 8;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (err) atomicOr(&a.ctl->error, err);
+}
+
+__global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
+  if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
+  constexpr int BITS = __builtin_ctz(HUB_PART_SLOTS);
+  __shared__ u64 T[HUB_PART_SLOTS];
+  __shared__ u64 red[4];
+  const u64 total = a.ctl->hub_parts;
+  const u64 nov = min(*h.ovf_count, (u64)HUB_OVERFLOW_CAP);
+  int err = 0;
+  for (u64 q = blockIdx.x; q < total; q += gridDim.x) {
+    const int i = h.part_owner[q];
+    const int k = h.ord[i];
+    const int p = (int)(q - h.pstart[i]);
+    for (int s = threadIdx.x; s < HUB_PART_SLOTS; s += 256) T[s] = EMPTY;
+    __syncthreads();
+    int32_t *cnt = h.pcnt + h.cnt_base[k] + p;
+    const int n = min(*cnt, h.part_cap);
+    const u64 *src = h.pairs + h.pair_base[k] + (int64_t)p * HUB_PART_CAP;
+    constexpr int R = (HUB_PART_CAP + 255) / 256;
+    u64 x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int s = threadIdx.x + r * 256;
+      x[r] = s < n ? src[s] : EMPTY;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (x[r] != EMPTY) err |= !lds_insert<BITS>(T, (uint32_t)(x[r] >> 32), (uint32_t)x[r]);
+    for (u64 s = threadIdx.x; s < nov; s += 256) {
+      const uint32_t *o = h.ovf + 4 * s;
+      if (o[0] == (uint32_t)q) err |= !lds_insert<BITS>(T, o[1], o[2]);
+    }
+    __syncthreads();
+    const u64 best = block_max<256>(table_best<256, HUB_PART_SLOTS>(T, threadIdx.x), red);
+    if (threadIdx.x == 0) {
+      h.partbest[q] = best;
+      *cnt = 0;  // partitions start empty at the next step
+    }
+    __syncthreads();
+  }
+  if (err) atomicOr(&a.ctl->error, 16);
+}
+
+// Strict argmax of each flagged hub over its partitions, and the update.
+// One wave per hub.
+__global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
+  if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
+  const int count = *a.fcount;
+  const int lane = threadIdx.x & 63;
+  u64 n_changed = 0, n_scanned = 0, n_vert = 0;
+  for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < count; i += gridDim.x * 4) {
+    const int v = a.front[i];
+    const int P = 1 << h.pbits[h.ord[i]];
+    const u64 *pb = h.partbest + h.pstart[i];
+    u64 best = 0;
+    for (int p = lane; p < P; p += 64) best = pb[p] > best ? pb[p] : best;
+    best = group_max<64>(best);
+    int changed = 0;
+    if (best != 0) {
+      const int32_t cs = (int32_t)key_label(best);
+      if (cs != a.C[v]) {
+        changed = 1;
+        if (lane == 0) {
+          a.C[v] = cs;
+          ++n_changed;
+        }
+      }
+    }
+    if (lane == 0) {
+      h.changed[i] = changed;
+      n_scanned += (u64)(a.off[v + 1] - a.off[v]);
+      ++n_vert;
+    }
+  }
+  block_accum<256>(n_changed, n_scanned, n_vert, 0, 0, a.ctl, a.bin);
+}
+
+// Neighbour marks of the hubs that changed, one workgroup per chunk.
+__global__ __launch_bounds__(256) void k_hub_mark(ScanArgs a, HubArgs h) {
+  if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
+  const u64 total = a.ctl->hub_chunks;
+  u64 n_marks = 0;
+  for (u64 c = blockIdx.x; c < total; c += gridDim.x) {
+    const int i = h.chunk_owner[c];
+    if (!h.changed[i]) continue;
+    const int v = a.front[i];
+    const int64_t eb = a.off[v] + (int64_t)(c - h.cstart[i]) * HUB_CHUNK;
+    const int64_t ee = min(a.off[v + 1], eb + (int64_t)HUB_CHUNK);
+    n_marks += mark_row<256, 8>(a.idx, a.F, eb, ee, v, threadIdx.x);
+  }
+  block_accum<256>(0, 0, 0, n_marks, 0, a.ctl, a.bin);
+}
+
+void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(1024), 0, st, a, h);
+  hipLaunchKernelGGL(k_hub_owner, dim3(blocks), dim3(256), 0, st, a, h);
+}
+
+void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h) {
+  const size_t lds = sizeof(int32_t) * (2u << h.max_pbits);
+  if (wk == W_UNIT) hipLaunchKernelGGL(k_hub_chunk<W_UNIT>, dim3(blocks), dim3(256), lds, st, a, h);
+  else if (wk == W_U8) hipLaunchKernelGGL(k_hub_chunk<W_U8>, dim3(blocks), dim3(256), lds, st, a, h);
+  else hipLaunchKernelGGL(k_hub_chunk<W_U32>, dim3(blocks), dim3(256), lds, st, a, h);
+}
+
+void launch_hub_part(int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h) {
+  hipLaunchKernelGGL(k_hub_part, dim3(blocks), dim3(256), 0, st, a, h);
+}
+
+void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, hipStream_t st, const ScanArgs &a,
+                       const HubArgs &h) {
+  hipLaunchKernelGGL(k_hub_decide, dim3(hub_blocks), dim3(256), 0, st, a, h);
+  if (prune) hipLaunchKernelGGL(k_hub_mark, dim3(chunk_blocks), dim3(256), 0, st, a, h);
+}
+
+}  // namespace gvelpa

@@ -101,70 +101,130 @@ __global__ void k_fill_u64(u64 *p, int64_t count, u64 value) {
 
 // Key of a vertex: its degree bin, prefixed by its colour in deterministic
 // lists; vertices without stored entries are never processed and get no key.
-__global__ void k_bin_hist(const int64_t *off, int64_t n, const int32_t *color, BinLimits lim, int32_t *hist) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t deg = off[v + 1] - off[v];
-    if (deg == 0) continue;
-    const int key = (color ? color[v] * NBINS : 0) + bin_of_degree(deg, lim);
-    atomicAdd(&hist[key], 1);
+// Counting is privatised in LDS (one global atomic per block and key) when
+// the key range fits; each block takes tiles of BIN_TILE consecutive ids.
+constexpr int BIN_TILE = 4096;
+constexpr int BIN_LDS_KEYS = 16384;
+
+// Group of a vertex in the list order: its colour (deterministic lists), or
+// its asynchronous phase fmix32(v ^ PHASE_SEED) mod nphase (async lists).
+constexpr uint32_t PHASE_SEED = 0x2545F491u;
+
+// With a colour map cmap, the group is cmap[colour] (asynchronous steps made
+// of consecutive colour classes).
+__device__ __forceinline__ int vertex_key(const int64_t *off, const int32_t *color, const int32_t *cmap, int nphase,
+                                          const BinLimits &lim, int64_t v) {
+  const int64_t deg = off[v + 1] - off[v];
+  if (deg == 0) return -1;
+  int grp;
+  if (color) grp = cmap ? cmap[color[v]] : color[v];
+  else grp = nphase > 1 ? (int)(fmix32((uint32_t)v ^ PHASE_SEED) % (uint32_t)nphase) : 0;
+  return grp * NBINS + bin_of_degree(deg, lim);
+}
+
+__global__ __launch_bounds__(256) void k_bin_hist(const int64_t *off, int64_t n, const int32_t *color,
+                                                  const int32_t *cmap, int nphase, BinLimits lim, int32_t *hist,
+                                                  int nkeys) {
+  extern __shared__ int32_t lh[];
+  const bool local = nkeys <= BIN_LDS_KEYS;
+  if (local) {
+    for (int k = threadIdx.x; k < nkeys; k += 256) lh[k] = 0;
+    __syncthreads();
+  }
+  for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+    const int key = vertex_key(off, color, cmap, nphase, lim, v);
+    if (key >= 0) atomicAdd(local ? &lh[key] : &hist[key], 1);
+  }
+  if (local) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < nkeys; k += 256)
+      if (lh[k]) atomicAdd(&hist[k], lh[k]);
   }
 }
 
-__global__ void k_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, BinLimits lim, int32_t *cursor,
-                              int32_t *list) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t deg = off[v + 1] - off[v];
-    if (deg == 0) continue;
-    const int key = (color ? color[v] * NBINS : 0) + bin_of_degree(deg, lim);
-    list[atomicAdd(&cursor[key], 1)] = (int32_t)v;
+__global__ __launch_bounds__(256) void k_bin_scatter(const int64_t *off, int64_t n, const int32_t *color,
+                                                     const int32_t *cmap, int nphase, BinLimits lim, int32_t *cursor,
+                                                     int32_t *list, int nkeys) {
+  extern __shared__ int32_t lh[];  // [0, nkeys): tile counts, then tile bases
+  const bool local = 2 * nkeys <= BIN_LDS_KEYS;
+  if (!local) {
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+      const int key = vertex_key(off, color, cmap, nphase, lim, v);
+      if (key >= 0) list[atomicAdd(&cursor[key], 1)] = (int32_t)v;
+    }
+    return;
+  }
+  int32_t *cnt = lh, *base = lh + nkeys;
+  for (int64_t t0 = (int64_t)blockIdx.x * BIN_TILE; t0 < n; t0 += (int64_t)gridDim.x * BIN_TILE) {
+    for (int k = threadIdx.x; k < nkeys; k += 256) cnt[k] = 0;
+    __syncthreads();
+    int key[BIN_TILE / 256], pos[BIN_TILE / 256];
+#pragma unroll
+    for (int r = 0; r < BIN_TILE / 256; ++r) {
+      const int64_t v = t0 + r * 256 + threadIdx.x;
+      key[r] = v < n ? vertex_key(off, color, cmap, nphase, lim, v) : -1;
+      pos[r] = key[r] >= 0 ? atomicAdd(&cnt[key[r]], 1) : 0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nkeys; k += 256)
+      if (cnt[k]) base[k] = atomicAdd(&cursor[k], cnt[k]);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < BIN_TILE / 256; ++r)
+      if (key[r] >= 0) list[base[key[r]] + pos[r]] = (int32_t)(t0 + r * 256 + threadIdx.x);
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- colouring
 
-__global__ void k_color_init(int32_t *color, int32_t *work, int64_t n) {
+// Priority of v: (deg(v), fmix32(v ^ seed), v) in lexicographic order; the
+// first two parts are packed in pk[v] = deg << 32 | fmix32(v ^ seed).
+__device__ __forceinline__ bool higher(u64 pu, int u, u64 pv, int v) { return pu > pv || (pu == pv && u > v); }
+
+__global__ void k_color_prio(const int64_t *off, int32_t *color, u64 *pk, int64_t n, uint32_t seed) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     color[v] = -1;
-    work[v] = (int32_t)v;
+    pk[v] = ((u64)(off[v + 1] - off[v]) << 32) | fmix32((uint32_t)v ^ seed);
   }
 }
 
-__device__ __forceinline__ u64 prio(uint32_t v, uint32_t seed) { return ((u64)fmix32(v ^ seed) << 32) | v; }
+// Jones-Plassmann, event driven.  pending[v] counts the neighbours of higher
+// priority that are not yet coloured; a vertex whose count reaches zero is
+// coloured in the next round with the smallest colour unused by its coloured
+// neighbours - exactly its higher-priority neighbours - which is the greedy
+// colouring in decreasing priority.  One wave per vertex.
+__global__ __launch_bounds__(256) void k_color_pending(const int64_t *off, const int32_t *idx, const u64 *pk,
+                                                       int32_t *pending, int32_t *front, int32_t *count, int64_t n) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < n; v += (int64_t)gridDim.x * 4) {
+    const u64 pv = pk[v];
+    int c = 0;
+    for (int64_t k = off[v] + lane; k < off[v + 1]; k += 64) {
+      const int u = idx[k];
+      c += (u != (int)v && higher(pk[u], u, pv, (int)v)) ? 1 : 0;
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) c += __shfl_xor(c, m, 64);
+    if (lane == 0) {
+      pending[v] = c;
+      if (c == 0) front[atomicAdd(count, 1)] = (int32_t)v;
+    }
+  }
+}
 
-// One Jones-Plassmann round, one wave per listed vertex.  A vertex is ready
-// when no uncoloured neighbour has a higher priority; it then takes the
-// smallest colour unused by its coloured neighbours, which are exactly its
-// higher-priority neighbours (a lower-priority neighbour waits for it).  This
-// is the greedy colouring in decreasing priority order.
 __global__ __launch_bounds__(256) void k_color_round(const int64_t *off, const int32_t *idx, int32_t *color,
-                                                     const int32_t *work, int32_t wlen, int32_t *next,
-                                                     int32_t *ncount, uint32_t seed) {
+                                                     const u64 *pk, int32_t *pending, const int32_t *work_in,
+                                                     int32_t *work_out, int32_t *counts, int r) {
   constexpr int WINDOW = 64 * 32;  // colours tested per pass: one 32-bit word per lane
   __shared__ uint32_t bits_all[4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t *bits = bits_all[wv];
   const int gw = blockIdx.x * 4 + wv, nw = gridDim.x * 4;
+  const int wlen = counts[r];
   for (int i = gw; i < wlen; i += nw) {
-    const int v = work[i];
-    const u64 pv = prio((uint32_t)v, seed);
+    const int v = work_in[i];
     const int64_t b = off[v], e = off[v + 1];
-    bool blocked = false;
-    for (int64_t k0 = b; k0 < e; k0 += 64) {
-      const int64_t k = k0 + lane;
-      bool blk = false;
-      if (k < e) {
-        const int u = idx[k];
-        blk = u != v && __atomic_load_n(&color[u], __ATOMIC_RELAXED) < 0 && prio((uint32_t)u, seed) > pv;
-      }
-      if (__ballot(blk)) {
-        blocked = true;
-        break;
-      }
-    }
-    if (blocked) {
-      if (lane == 0) next[atomicAdd(ncount, 1)] = v;
-      continue;
-    }
     int base = 0, found = -1;
     while (found < 0) {
       bits[lane] = 0;
@@ -188,6 +248,13 @@ __global__ __launch_bounds__(256) void k_color_round(const int64_t *off, const i
       wave_lds_sync();
     }
     if (lane == 0) __atomic_store_n(&color[v], found, __ATOMIC_RELAXED);
+    // release the lower-priority neighbours
+    const u64 pv = pk[v];
+    for (int64_t k = b + lane; k < e; k += 64) {
+      const int u = idx[k];
+      if (u != v && higher(pv, v, pk[u], u) && atomicSub(&pending[u], 1) == 1)
+        work_out[atomicAdd(&counts[r + 1], 1)] = u;
+    }
   }
 }
 
@@ -218,24 +285,34 @@ void launch_check_symmetric(const int64_t *off, const int32_t *idx, const void *
   else if (wk == W_U8) hipLaunchKernelGGL(k_check_symmetric<W_U8>, g, b, 0, st, off, idx, w, n, sums);
   else hipLaunchKernelGGL(k_check_symmetric<W_U32>, g, b, 0, st, off, idx, w, n, sums);
 }
-void launch_bin_hist(const int64_t *off, int64_t n, const int32_t *color, const BinLimits &lim, int32_t *hist,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_bin_hist, dim3(grid_for(n, 256)), dim3(256), 0, st, off, n, color, lim, hist);
+void launch_bin_hist(const int64_t *off, int64_t n, const int32_t *color, const int32_t *cmap, int nphase,
+                     const BinLimits &lim, int32_t *hist, int nkeys, hipStream_t st) {
+  const size_t lds = nkeys <= BIN_LDS_KEYS ? sizeof(int32_t) * nkeys : 0;
+  hipLaunchKernelGGL(k_bin_hist, dim3(grid_for(n, 256, 2048)), dim3(256), lds, st, off, n, color, cmap, nphase, lim,
+                     hist, nkeys);
 }
-void launch_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, const BinLimits &lim,
-                        int32_t *cursor, int32_t *list, hipStream_t st) {
-  hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, off, n, color, lim, cursor, list);
+void launch_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, const int32_t *cmap, int nphase,
+                        const BinLimits &lim, int32_t *cursor, int32_t *list, int nkeys, hipStream_t st) {
+  const size_t lds = 2 * nkeys <= BIN_LDS_KEYS ? sizeof(int32_t) * 2 * nkeys : 0;
+  hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(n, BIN_TILE, 4096)), dim3(256), lds, st, off, n, color, cmap, nphase,
+                     lim, cursor, list, nkeys);
 }
+uint32_t phase_seed() { return PHASE_SEED; }
+
 void launch_fill_u64(u64 *p, int64_t count, u64 value, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256)), dim3(256), 0, st, p, count, value);
 }
-void launch_color_init(int32_t *color, int32_t *work, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_color_init, dim3(grid_for(n, 256)), dim3(256), 0, st, color, work, n);
+void launch_color_init(const int64_t *off, const int32_t *idx, int32_t *color, u64 *pk, int32_t *pending,
+                       int32_t *front, int32_t *count, int64_t n, uint32_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_color_prio, dim3(grid_for(n, 256)), dim3(256), 0, st, off, color, pk, n, seed);
+  hipLaunchKernelGGL(k_color_pending, dim3(grid_for(n, 4, 16384)), dim3(256), 0, st, off, idx, pk, pending, front,
+                     count, n);
 }
-void launch_color_round(const int64_t *off, const int32_t *idx, int32_t *color, const int32_t *work, int32_t wlen,
-                        int32_t *next, int32_t *ncount, uint32_t seed, hipStream_t st) {
-  hipLaunchKernelGGL(k_color_round, dim3(grid_for(wlen, 4, 16384)), dim3(256), 0, st, off, idx, color, work, wlen,
-                     next, ncount, seed);
+void launch_color_round(const int64_t *off, const int32_t *idx, int32_t *color, const u64 *pk, int32_t *pending,
+                        const int32_t *work_in, int32_t *work_out, int32_t *counts, int r, int blocks,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_color_round, dim3(blocks), dim3(256), 0, st, off, idx, color, pk, pending, work_in, work_out,
+                     counts, r);
 }
 
 }  // namespace gvelpa

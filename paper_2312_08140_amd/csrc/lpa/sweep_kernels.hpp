@@ -21,10 +21,11 @@ struct CompactArgs {
 
 void launch_compact(const CompactArgs &a, int blocks, hipStream_t st);
 void launch_scan_bin(int bin, int wk, int blocks, hipStream_t st, const ScanArgs &a);
-void launch_hub_plan(const ScanArgs &a, u64 *cstart, int64_t *toff, int32_t *tbits, hipStream_t st);
-void launch_hub_scan(int wk, int blocks, hipStream_t st, const ScanArgs &a, const u64 *cstart, const int64_t *toff,
-                     const int32_t *tbits);
-void launch_hub_finish(int blocks, hipStream_t st, const ScanArgs &a, const int64_t *toff, const int32_t *tbits);
+void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, hipStream_t st);
+void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
+void launch_hub_part(int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
+void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, hipStream_t st, const ScanArgs &a,
+                       const HubArgs &h);
 void launch_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, int set_labels, int set_flags,
                        int clear_isolated, hipStream_t st);
 void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int32_t *fcount, int nfc, int32_t *host_done,
@@ -49,14 +50,17 @@ void launch_weighted_degree(const int64_t *off, const void *w, int wk, int64_t n
                             hipStream_t st);
 void launch_check_symmetric(const int64_t *off, const int32_t *idx, const void *w, int wk, int64_t n,
                             CsrCheck *chk, hipStream_t st);
-void launch_bin_hist(const int64_t *off, int64_t n, const int32_t *color, const BinLimits &lim, int32_t *hist,
-                     hipStream_t st);
-void launch_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, const BinLimits &lim,
-                        int32_t *cursor, int32_t *list, hipStream_t st);
+void launch_bin_hist(const int64_t *off, int64_t n, const int32_t *color, const int32_t *cmap, int nphase,
+                     const BinLimits &lim, int32_t *hist, int nkeys, hipStream_t st);
+void launch_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, const int32_t *cmap, int nphase,
+                        const BinLimits &lim, int32_t *cursor, int32_t *list, int nkeys, hipStream_t st);
+uint32_t phase_seed();
 void launch_fill_u64(u64 *p, int64_t count, u64 value, hipStream_t st);
-void launch_color_init(int32_t *color, int32_t *work, int64_t n, hipStream_t st);
-void launch_color_round(const int64_t *off, const int32_t *idx, int32_t *color, const int32_t *work, int32_t wlen,
-                        int32_t *next, int32_t *ncount, uint32_t seed, hipStream_t st);
+void launch_color_init(const int64_t *off, const int32_t *idx, int32_t *color, u64 *pk, int32_t *pending,
+                       int32_t *front, int32_t *count, int64_t n, uint32_t seed, hipStream_t st);
+void launch_color_round(const int64_t *off, const int32_t *idx, int32_t *color, const u64 *pk, int32_t *pending,
+                        const int32_t *work_in, int32_t *work_out, int32_t *counts, int r, int blocks,
+                        hipStream_t st);
 
 // metrics_kernels.hip
 struct ModAcc {

@@ -1,0 +1,182 @@
+// LDS open-addressing tables (label -> summed weight) and block reductions
+// shared by the scan kernels.
+#pragma once
+#include "common.hpp"
+
+namespace gvelpa {
+
+// Adds weight w to label lbl in a table of 2^BITS entries (linear probing).
+// Entry s of the table lives at T[s * STRIDE] (tables of several groups are
+// interleaved so that neighbouring lanes hit neighbouring LDS banks).
+// Returns false only if every slot holds another label.
+template <int BITS, int STRIDE = 1>
+__device__ __forceinline__ bool lds_insert(u64 *T, uint32_t lbl, uint32_t w) {
+  constexpr uint32_t MASK = (1u << BITS) - 1;
+  uint32_t h = slot_hash(lbl, BITS);
+  const u64 mine = ((u64)lbl << 32) | w;
+  for (int probe = 0; probe <= (int)MASK; ++probe) {
+    u64 *slot = &T[h * STRIDE];
+    const u64 cur = __atomic_load_n(slot, __ATOMIC_RELAXED);
+    if ((uint32_t)(cur >> 32) == lbl) {
+      atomicAdd(slot, (u64)w);
+      return true;
+    }
+    if (cur == EMPTY) {
+      const u64 old = atomicCAS(slot, EMPTY, mine);
+      if (old == EMPTY) return true;
+      if ((uint32_t)(old >> 32) == lbl) {
+        atomicAdd(slot, (u64)w);
+        return true;
+      }
+    }
+    h = (h + 1) & MASK;
+  }
+  return false;
+}
+
+// Gathers the labels of the entries [b, e) of row v, lanes lane, lane+G, ...,
+// U entries per lane in flight, and adds them to table T.  The vertex itself
+// is skipped (scanCommunities of Algorithm 1).
+template <int G, int U, int BITS, int WK>
+__device__ __forceinline__ int scan_row(const int32_t *__restrict__ idx, const void *__restrict__ w,
+                                        const int32_t *C, int64_t b, int64_t e, int v, int lane, u64 *T) {
+  int overflow = 0;
+  for (int64_t base = b + lane; base < e; base += (int64_t)G * U) {
+    int j[U];
+    uint32_t wt[U];
+#pragma unroll
+    for (int r = 0; r < U; ++r) {
+      const int64_t k = base + (int64_t)r * G;
+      j[r] = k < e ? idx[k] : -1;
+      wt[r] = k < e ? load_w<WK>(w, k) : 0u;
+    }
+    uint32_t lbl[U];
+#pragma unroll
+    for (int r = 0; r < U; ++r) lbl[r] = (j[r] >= 0 && j[r] != v) ? (uint32_t)C[j[r]] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int r = 0; r < U; ++r)
+      if (lbl[r] != 0xFFFFFFFFu) overflow |= !lds_insert<BITS>(T, lbl[r], wt[r]);
+  }
+  return overflow;
+}
+
+// scan_row for an interleaved table (entry s at T[s * STRIDE]).
+template <int G, int U, int BITS, int STRIDE, int WK>
+__device__ __forceinline__ int scan_row_strided(const int32_t *__restrict__ idx, const void *__restrict__ w,
+                                                const int32_t *C, int64_t b, int64_t e, int v, int lane, u64 *T) {
+  int overflow = 0;
+  for (int64_t base = b + lane; base < e; base += (int64_t)G * U) {
+    int j[U];
+    uint32_t wt[U];
+#pragma unroll
+    for (int r = 0; r < U; ++r) {
+      const int64_t k = base + (int64_t)r * G;
+      j[r] = k < e ? idx[k] : -1;
+      wt[r] = k < e ? load_w<WK>(w, k) : 0u;
+    }
+    uint32_t lbl[U];
+#pragma unroll
+    for (int r = 0; r < U; ++r) lbl[r] = (j[r] >= 0 && j[r] != v) ? (uint32_t)C[j[r]] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int r = 0; r < U; ++r)
+      if (lbl[r] != 0xFFFFFFFFu) overflow |= !lds_insert<BITS, STRIDE>(T, lbl[r], wt[r]);
+  }
+  return overflow;
+}
+
+// Flags the neighbours of v (not v itself) for the next visit; returns the
+// number of marks written.
+template <int G, int U>
+__device__ __forceinline__ u64 mark_row(const int32_t *__restrict__ idx, uint8_t *F, int64_t b, int64_t e, int v,
+                                        int lane) {
+  u64 marks = 0;
+  for (int64_t base = b + lane; base < e; base += (int64_t)G * U) {
+    int j[U];
+#pragma unroll
+    for (int r = 0; r < U; ++r) {
+      const int64_t k = base + (int64_t)r * G;
+      j[r] = k < e ? idx[k] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < U; ++r)
+      if (j[r] >= 0 && j[r] != v) {
+        F[j[r]] = 1;
+        ++marks;
+      }
+  }
+  return marks;
+}
+
+// Largest argmax key among the slots lane, lane+G, ... of T.
+template <int G, int SLOTS, int STRIDE = 1>
+__device__ __forceinline__ u64 table_best(const u64 *T, int lane) {
+  u64 best = 0;
+#pragma unroll 4
+  for (int s = lane; s < SLOTS; s += G) {
+    const u64 x = T[s * STRIDE];
+    if (x != EMPTY) {
+      const u64 kk = entry_key(x);
+      best = kk > best ? kk : best;
+    }
+  }
+  return best;
+}
+
+// Block-wide maximum (every thread gets the result); red holds BLOCK/64 entries.
+template <int BLOCK>
+__device__ __forceinline__ u64 block_max(u64 x, u64 *red) {
+  x = group_max<64>(x);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  x = red[0];
+#pragma unroll
+  for (int k = 1; k < BLOCK / 64; ++k) x = red[k] > x ? red[k] : x;
+  return x;
+}
+
+// Block-wide sums of the per-thread counters, then one atomic per counter
+// and block: sweep totals (changed, scanned) and run totals of the bin.
+template <int BLOCK>
+__device__ __forceinline__ void block_accum(u64 changed, u64 scanned, u64 vertices, u64 marks, int err, Ctl *ctl,
+                                            int bin) {
+  __shared__ u64 s_v[4][BLOCK / 64];
+  __shared__ int s_err[BLOCK / 64];
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    changed += shfl_xor_u64(changed, m);
+    scanned += shfl_xor_u64(scanned, m);
+    vertices += shfl_xor_u64(vertices, m);
+    marks += shfl_xor_u64(marks, m);
+    err |= __shfl_xor(err, m, 64);
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_v[0][wv] = changed;
+    s_v[1][wv] = scanned;
+    s_v[2][wv] = vertices;
+    s_v[3][wv] = marks;
+    s_err[wv] = err;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 t[4] = {0, 0, 0, 0};
+    int te = 0;
+    for (int k = 0; k < BLOCK / 64; ++k) {
+      for (int q = 0; q < 4; ++q) t[q] += s_v[q][k];
+      te |= s_err[k];
+    }
+    if (t[0]) {
+      atomicAdd((u64 *)&ctl->changed, t[0]);
+      atomicAdd((u64 *)&ctl->bin_changed[bin], t[0]);
+    }
+    if (t[1]) {
+      atomicAdd((u64 *)&ctl->scanned, t[1]);
+      atomicAdd((u64 *)&ctl->bin_edges[bin], t[1]);
+    }
+    if (t[2]) atomicAdd((u64 *)&ctl->bin_vertices[bin], t[2]);
+    if (t[3]) atomicAdd((u64 *)&ctl->bin_marks[bin], t[3]);
+    if (te) atomicOr(&ctl->error, te);
+  }
+}
+
+}  // namespace gvelpa

@@ -107,7 +107,7 @@ def test_random_small_graphs():
 def test_bins_do_not_change_results():
     g = gg.rmat(13, 16, seed=11)
     ref, _ = check_det(g)
-    for bins in ([2, 4, 16, 64, 256, 1024], [15, 63, 255, 1023, 4095, 8191], [0, 0, 0, 0, 0, 0]):
+    for bins in ([2, 8, 32, 128, 512, 2048], [7, 31, 127, 511, 2047, 8191], [0, 0, 0, 0, 0, 0]):
         r2, _ = check_det(g, bins=bins)
         assert np.array_equal(r2["labels"], ref["labels"])
 
@@ -199,6 +199,35 @@ def test_async_quality_and_invariants(seed):
     G.close()
 
 
+@pytest.mark.parametrize("mu", [0.2, 0.4])
+def test_async_quality_sbm_1m(mu):
+    """The gate's SBM workload: 10^6 vertices, 1,000 blocks, average degree 32."""
+    n, k, d = 1000000, 1000, 32.0
+    g = gg.sbm(n, k, d * (1 - mu) / 999, d * mu / (n - 1000), seed=3)
+    G = abi.LPAGraph(g)
+    lab_a, st_a = G.run(0.05, 20, ASYNC, True)
+    q_a = G.modularity(lab_a)
+    lab_d, _ = G.run(0.05, 20, DET, True)
+    q_d = G.modularity(lab_d)
+    say(f"mu={mu}: async Q={q_a:.5f} det Q={q_d:.5f}")
+    assert q_a >= q_d - 0.01
+    G.close()
+
+
+@pytest.mark.parametrize("phases,by_colour", [(1, 0), (8, 0), (4, 1)])
+def test_async_schedules_invariants(phases, by_colour):
+    """Every schedule gives a valid LPA state: labels inside components,
+    converged, and (phases = 1 aside) the clique partition exactly."""
+    g = gg.rmat(14, 16, seed=4)
+    G = abi.LPAGraph(g)
+    G.set_async_phases(phases, by_colour)
+    lab, st = G.run(0.05, 20, ASYNC, True)
+    comp = _components(g)
+    assert np.array_equal(comp[lab], comp)
+    assert st["converged"]
+    G.close()
+
+
 def test_async_disjoint_cliques_exact():
     g = cliques(50, 8)
     G = abi.LPAGraph(g)
@@ -207,3 +236,28 @@ def test_async_disjoint_cliques_exact():
     assert all(len(set(r)) == 1 for r in blocks.tolist())
     assert len(set(blocks[:, 0].tolist())) == 50
     G.close()
+
+
+def test_big_hubs_many_partitions():
+    """Stars and a hub joined to cliques: hub rows of 300,000 entries use 256
+    label partitions and 147 chunks."""
+    L = 300000
+    edges = [(0, i) for i in range(1, L + 1)]
+    edges += [(L + 1 + k, L + 1 + k + 1) for k in range(0, 2000, 2)]  # a few extra pairs
+    g = gg.from_edges(L + 2002, edges)
+    check_det(g)
+    # the hub sees many repeated labels: leaves first join 40 small cliques
+    rng = np.random.default_rng(5)
+    e2 = [(0, i) for i in range(1, 60001)]
+    for c in range(40):
+        members = rng.choice(np.arange(1, 60001), 12, replace=False)
+        e2 += list(itertools.combinations(members.tolist(), 2))
+    check_det(gg.from_edges(60001, e2, rng.integers(1, 9, len(e2))))
+
+
+def test_hub_partition_spill_path(monkeypatch):
+    """With partitions capped at 3 entries, almost every label spills to the
+    shared overflow area; results must not change."""
+    monkeypatch.setenv("GVELPA_HUB_PART_CAP", "3")
+    g = gg.rmat(15, 16, seed=12)
+    check_det(g)

@@ -341,7 +341,7 @@ def test_fmix32_vectors():
 @pytest.mark.parametrize("seed", [0, 7, 0xDEADBEEF])
 def test_colouring_is_greedy_in_priority_order(seed):
     """The oracle colouring equals networkx's greedy colouring when nodes are
-    offered in decreasing (fmix32(v ^ seed), v) order, and is proper."""
+    offered in decreasing (degree, fmix32(v ^ seed), v) order, and is proper."""
     import networkx as nx
     g = gg.rmat(10, 8, seed=2)
     colors, ncol = oracle.color(g, seed)
@@ -351,7 +351,8 @@ def test_colouring_is_greedy_in_priority_order(seed):
         for k in range(g.offsets[v], g.offsets[v + 1]):
             if int(g.indices[k]) != v:
                 G.add_edge(v, int(g.indices[k]))
-    prio = sorted(range(g.n), key=lambda v: (fmix32(v ^ seed), v), reverse=True)
+    deg = g.degrees()
+    prio = sorted(range(g.n), key=lambda v: (int(deg[v]), fmix32(v ^ seed), v), reverse=True)
     ref = nx.coloring.greedy_color(G, strategy=lambda G_, c: iter(prio))
     assert all(colors[v] == ref[v] for v in range(g.n))
     assert ncol == max(ref.values()) + 1
