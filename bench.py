@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--no-det", action="store_true", help="skip the deterministic-mode figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -73,6 +75,12 @@ def main():
     from paper_2312_08140_amd import abi, graphgen
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t = time.time()
     g = graphgen.rmat(args.scale, args.edge_factor, seed=args.seed, weighted=True)
     log(f"generated R-MAT scale {args.scale}: n={g.n} m={g.m} in {time.time() - t:.1f}s")

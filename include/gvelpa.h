@@ -60,7 +60,11 @@ enum {
   LPA_FLAG_KERNEL_TIMING = 16,  /* lpa_run: time every kernel with HIP events (implies LPA_FLAG_NO_GRAPH) */
   LPA_FLAG_VERIFY = 32,         /* lpa_run: after convergence, run one full unpruned sweep; if it changes more
                                    than tau * n labels, continue with plain pruning */
-  LPA_FLAG_TRACE = 64           /* lpa_run: record gate training samples (features, changed-next-sweep) */
+  LPA_FLAG_TRACE = 64,          /* lpa_run: record gate training samples (features, changed-next-sweep) */
+  LPA_FLAG_EXACT_MARKS = 128    /* lpa_run, async mode: always flag neighbours one by one.  By default a sweep
+                                   that follows one in which more than half of the vertices changed writes no
+                                   marks and flags every vertex at its end instead (the first sweep of a fresh
+                                   run counts as such); this only adds work that cannot change a label */
 };
 
 #define LPA_MAX_SWEEPS_RECORDED 64

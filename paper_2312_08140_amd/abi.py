@@ -39,6 +39,7 @@ LPA_FLAG_NO_GRAPH = 8
 LPA_FLAG_KERNEL_TIMING = 16
 LPA_FLAG_VERIFY = 32
 LPA_FLAG_TRACE = 64
+LPA_FLAG_EXACT_MARKS = 128
 
 MAX_SWEEPS_RECORDED = 64
 NUM_TIMED_KERNELS = 16

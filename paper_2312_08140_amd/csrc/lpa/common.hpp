@@ -98,6 +98,13 @@ struct Ctl {
   int32_t max_iters;
   int32_t verify_phase;  // 1 while a verification sweep runs
   int32_t gate_on;
+  // Dense sweeps (asynchronous mode): when most vertices change, every
+  // neighbour would be flagged anyway; the sweep then writes no marks and all
+  // flags are set once at its end (pruning is exact, so processing a vertex
+  // that would not have been flagged changes nothing).
+  int32_t dense_enabled, dense_cur, dense_prev, pad0;
+  double dense_frac;
+  int64_t n_active;
   double tau;
   int64_t n;
   u64 changed, processed, scanned, gated;  // current sweep

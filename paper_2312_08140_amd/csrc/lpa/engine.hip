@@ -572,6 +572,7 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune) {
   const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : g->nphase * NBINS;
   tk_begin(g, st);
   launch_end_sweep(g->ctl, g->fcount, nfc, g->host_done_dev, st);
+  if (mode == LPA_MODE_ASYNC && prune) launch_dense_fill(g->ctl, g->off, g->F, g->n, st);
   tk_end(g, st, TK_END_SWEEP);
 }
 
@@ -865,7 +866,9 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     g->ev_used = 0;
     HIP_OK(hipEventRecord(t0, g->stream));
     const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : g->nphase * NBINS;
-    launch_run_begin(g->ctl, tolerance, max_iters, g->n, g->fcount, nfc, g->host_done_dev, g->stream);
+    const int dense = mode == LPA_MODE_ASYNC && prune && !(flags & LPA_FLAG_EXACT_MARKS);
+    launch_run_begin(g->ctl, tolerance, max_iters, g->n, g->n_active, g->fcount, nfc, g->host_done_dev, dense,
+                     !init_labels && !init_flags, g->stream);
     for (int s = 0; s < max_iters; ++s) {
       if (exec) HIP_OK(hipGraphLaunch(exec, g->stream));
       else emit_sweep(g, g->stream, mode, prune);

@@ -244,6 +244,7 @@ __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
 // Neighbour marks of the hubs that changed, one workgroup per chunk.
 __global__ __launch_bounds__(256) void k_hub_mark(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
+  if (__atomic_load_n(&a.ctl->dense_cur, __ATOMIC_RELAXED)) return;  // dense sweep: flags are set at its end
   const u64 total = a.ctl->hub_chunks;
   u64 n_marks = 0;
   for (u64 c = blockIdx.x; c < total; c += gridDim.x) {

@@ -32,10 +32,15 @@ __global__ void k_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t
   }
 }
 
-__global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int32_t *fcount, int nfc,
-                            int32_t *host_done) {
+__global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount,
+                            int nfc, int32_t *host_done, int dense_enabled, int dense_first) {
   for (int k = threadIdx.x; k < nfc; k += blockDim.x) fcount[k] = 0;
   if (threadIdx.x == 0) {
+    ctl->dense_enabled = dense_enabled;
+    ctl->dense_cur = dense_enabled && dense_first;
+    ctl->dense_prev = 0;
+    ctl->dense_frac = 0.5;
+    ctl->n_active = n_active;
     ctl->done = max_iters <= 0 ? 1 : 0;
     ctl->sweep = 0;
     ctl->iterations = 0;
@@ -76,6 +81,8 @@ __global__ void k_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_do
     ctl->t_sweep[s] = wall_clock64();
   }
   ctl->total_changed += dn;
+  ctl->dense_prev = ctl->dense_cur;
+  ctl->dense_cur = ctl->dense_enabled && (double)dn > ctl->dense_frac * (double)ctl->n_active;
   ctl->iterations = s + 1;
   ctl->sweep = s + 1;
   // Algorithm 1: stop when dN / N <= tau (evaluated in double).
@@ -87,6 +94,13 @@ __global__ void k_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_do
     __atomic_store_n(host_done, ctl->done, __ATOMIC_RELAXED);
     __threadfence_system();
   }
+}
+
+// After a dense sweep every vertex with a stored entry is flagged.
+__global__ void k_dense_fill(const Ctl *ctl, const int64_t *off, uint8_t *F, int64_t n) {
+  if (!__atomic_load_n(&ctl->dense_prev, __ATOMIC_RELAXED)) return;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    if (off[v + 1] > off[v]) F[v] = 1;
 }
 
 // ---------------------------------------------------------------- compaction
@@ -194,33 +208,42 @@ struct RowStage {
 #pragma unroll
     for (int r = 0; r < U; ++r) lbl[r] = (j[r] >= 0 && j[r] != v) ? (uint32_t)a.C[j[r]] : 0xFFFFFFFFu;
   }
+  // Flags the neighbours held in registers; a flag already set is not
+  // written again (read first: redundant byte stores to random lines are what
+  // the marks would otherwise cost in write-back traffic).
   __device__ __forceinline__ u64 mark(const ScanArgs &a) const {
+    uint8_t f[U];
+#pragma unroll
+    for (int r = 0; r < U; ++r) f[r] = (j[r] >= 0 && j[r] != v) ? a.F[j[r]] : (uint8_t)1;
     u64 n = 0;
 #pragma unroll
-    for (int r = 0; r < U; ++r)
-      if (j[r] >= 0 && j[r] != v) {
-        a.F[j[r]] = 1;
-        ++n;
-      }
+    for (int r = 0; r < U; ++r) {
+      n += (j[r] >= 0 && j[r] != v) ? 1 : 0;
+      if (!f[r]) a.F[j[r]] = 1;
+    }
     return n;
   }
 };
 
-// GROUP lanes of one wave per vertex (64 / GROUP vertices per wave).  The
-// tables of a workgroup's GPB groups are interleaved (slot s of group g at
-// tab[s * GPB + g]).
+// GROUP lanes of one wave per vertex (64 / GROUP vertices per wave).  For
+// GROUP <= 2 the tables of a workgroup's GPB groups are interleaved (slot s of
+// group g at tab[s * GPB + g], so the lanes of a wave - mostly different
+// groups - hit different LDS banks); larger groups keep their table
+// contiguous (the lanes of one group then spread over the banks by hash).
 template <int GROUP, int SLOTS, int U, int WK>
 __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
   static_assert(GROUP <= 64 && (GROUP & (GROUP - 1)) == 0, "a group lives inside one wave");
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   constexpr int GPB = 256 / GROUP;
   constexpr int BITS = __builtin_ctz(SLOTS);
+  constexpr int TS = GROUP <= 2 ? GPB : 1;  // table stride
   __shared__ u64 tab[GPB * SLOTS];
   const int lane = threadIdx.x % GROUP;
   const int grp = threadIdx.x / GROUP;
-  u64 *T = tab + grp;
+  u64 *T = TS == 1 ? tab + grp * SLOTS : tab + grp;
   const int count = *a.fcount;
   const int stride = gridDim.x * GPB;
+  const bool mark_now = a.prune && !__atomic_load_n(&a.ctl->dense_cur, __ATOMIC_RELAXED);
   u64 n_changed = 0, n_scanned = 0, n_vert = 0, n_marks = 0;
   int overflow = 0;
   int i = blockIdx.x * GPB + grp;
@@ -234,17 +257,17 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
     const int vc = i + 2 * stride < count ? a.front[i + 2 * stride] : -1;
     // merge A
 #pragma unroll
-    for (int s = lane; s < SLOTS; s += GROUP) T[s * GPB] = EMPTY;
+    for (int s = lane; s < SLOTS; s += GROUP) T[s * TS] = EMPTY;
     wave_lds_sync();
 #pragma unroll
     for (int r = 0; r < U; ++r)
-      if (A.lbl[r] != 0xFFFFFFFFu) overflow |= !lds_insert<BITS, GPB>(T, A.lbl[r], A.w[r]);
+      if (A.lbl[r] != 0xFFFFFFFFu) overflow |= !lds_insert<BITS, TS>(T, A.lbl[r], A.w[r]);
     const bool one_pass = A.e - A.b <= (int64_t)GROUP * U;
     if (!one_pass)
       overflow |=
-          scan_row_strided<GROUP, U, BITS, GPB, WK>(a.idx, a.w, a.C, A.b + (int64_t)GROUP * U, A.e, A.v, lane, T);
+          scan_row_strided<GROUP, U, BITS, TS, WK>(a.idx, a.w, a.C, A.b + (int64_t)GROUP * U, A.e, A.v, lane, T);
     wave_lds_sync();
-    const u64 best = group_max<GROUP>(table_best<GROUP, SLOTS, GPB>(T, lane));
+    const u64 best = group_max<GROUP>(table_best<GROUP, SLOTS, TS>(T, lane));
     if (best != 0) {
       const int32_t cs = (int32_t)key_label(best);
       if (cs != A.cur) {
@@ -252,7 +275,7 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
           a.C[A.v] = cs;
           ++n_changed;
         }
-        if (a.prune) {
+        if (mark_now) {
           n_marks += A.mark(a);
           if (!one_pass) n_marks += mark_row<GROUP, U>(a.idx, a.F, A.b + (int64_t)GROUP * U, A.e, A.v, lane);
         }
@@ -279,6 +302,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
   __shared__ u64 red[BLOCK / 64];
   const int count = *a.fcount;
   const int stride = gridDim.x;
+  const bool mark_now = a.prune && !__atomic_load_n(&a.ctl->dense_cur, __ATOMIC_RELAXED);
   u64 n_changed = 0, n_scanned = 0, n_vert = 0, n_marks = 0;
   int overflow = 0;
   int i = blockIdx.x;
@@ -307,7 +331,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
           a.C[A.v] = cs;
           ++n_changed;
         }
-        if (a.prune) {
+        if (mark_now) {
           n_marks += A.mark(a);
           if (!one_pass) n_marks += mark_row<BLOCK, U>(a.idx, a.F, A.b + (int64_t)BLOCK * U, A.e, A.v, threadIdx.x);
         }
@@ -365,9 +389,16 @@ void launch_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, in
                      clear_isolated);
 }
 
-void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int32_t *fcount, int nfc, int32_t *host_done,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_run_begin, dim3(1), dim3(256), 0, st, ctl, tau, max_iters, n, fcount, nfc, host_done);
+void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount, int nfc,
+                      int32_t *host_done, int dense_enabled, int dense_first, hipStream_t st) {
+  hipLaunchKernelGGL(k_run_begin, dim3(1), dim3(256), 0, st, ctl, tau, max_iters, n, n_active, fcount, nfc, host_done,
+                     dense_enabled, dense_first);
+}
+
+void launch_dense_fill(const Ctl *ctl, const int64_t *off, uint8_t *F, int64_t n, hipStream_t st) {
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_dense_fill, dim3(blocks), dim3(256), 0, st, ctl, off, F, n);
 }
 
 void launch_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_done, hipStream_t st) {

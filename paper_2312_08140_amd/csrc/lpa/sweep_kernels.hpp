@@ -28,8 +28,9 @@ void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, hipStream_t 
                        const HubArgs &h);
 void launch_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, int set_labels, int set_flags,
                        int clear_isolated, hipStream_t st);
-void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int32_t *fcount, int nfc, int32_t *host_done,
-                      hipStream_t st);
+void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount, int nfc,
+                      int32_t *host_done, int dense_enabled, int dense_first, hipStream_t st);
+void launch_dense_fill(const Ctl *ctl, const int64_t *off, uint8_t *F, int64_t n, hipStream_t st);
 void launch_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_done, hipStream_t st);
 
 // setup_kernels.hip

@@ -97,12 +97,14 @@ __device__ __forceinline__ u64 mark_row(const int32_t *__restrict__ idx, uint8_t
       const int64_t k = base + (int64_t)r * G;
       j[r] = k < e ? idx[k] : -1;
     }
+    uint8_t f[U];
 #pragma unroll
-    for (int r = 0; r < U; ++r)
-      if (j[r] >= 0 && j[r] != v) {
-        F[j[r]] = 1;
-        ++marks;
-      }
+    for (int r = 0; r < U; ++r) f[r] = (j[r] >= 0 && j[r] != v) ? F[j[r]] : (uint8_t)1;
+#pragma unroll
+    for (int r = 0; r < U; ++r) {
+      marks += (j[r] >= 0 && j[r] != v) ? 1 : 0;
+      if (!f[r]) F[j[r]] = 1;  // a flag already set is not written again
+    }
   }
   return marks;
 }
