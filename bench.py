@@ -25,6 +25,32 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = ROOT / "profiles" / "rmat24_async_hbm_traffic.md"
+
+
+def library_digest():
+    """sha256[:16] of the HIP library sources (the state byte counters were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    src = ROOT / "paper_2312_08140_amd" / "csrc" / "lpa"
+    for f in sorted(list(src.glob("*.hip")) + list(src.glob("*.hpp")), key=lambda p: str(p)):
+        h.update(f.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
+    or None when the kernels changed since the counters were taken."""
+    try:
+        for line in TRAFFIC_PROFILE.read_text().splitlines():
+            if line.startswith("machine-readable: "):
+                d = json.loads(line[len("machine-readable: "):])
+                if d.get("sources") != library_digest():
+                    return None
+                return d["bytes_per_launch"].get(kernel)
+    except OSError:
+        return None
+    return None
 
 
 def log(*a):
@@ -133,7 +159,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "bytes_per_launch": int(dom_bytes / dom_launches), "avg_launch_ms": round(dom_ms, 5),
-                "traffic": None,
+                "traffic": measured_traffic(dominant),
                 "whole_sweep": {"bytes": int(total_bytes), "ms": round(sweep_ms, 3),
                                 "achieved": round(total_bytes / (sweep_ms * 1e-3) / 1e9, 1),
                                 "frac": round(total_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},

@@ -61,10 +61,12 @@ enum {
   LPA_FLAG_VERIFY = 32,         /* lpa_run: after convergence, run one full unpruned sweep; if it changes more
                                    than tau * n labels, continue with plain pruning */
   LPA_FLAG_TRACE = 64,          /* lpa_run: record gate training samples (features, changed-next-sweep) */
-  LPA_FLAG_EXACT_MARKS = 128    /* lpa_run, async mode: always flag neighbours one by one.  By default a sweep
+  LPA_FLAG_EXACT_MARKS = 128,   /* lpa_run, async mode: always flag neighbours one by one.  By default a sweep
                                    that follows one in which more than half of the vertices changed writes no
                                    marks and flags every vertex at its end instead (the first sweep of a fresh
                                    run counts as such); this only adds work that cannot change a label */
+  LPA_FLAG_ONE_LAUNCH = 256     /* lpa_run: replay all max_iters sweeps as one HIP graph launch (sweeps after
+                                   the stop test exit at once); batched handles always do */
 };
 
 #define LPA_MAX_SWEEPS_RECORDED 64
@@ -180,6 +182,26 @@ int lpa_set_async_phases(lpa_graph *g, int32_t phases, int32_t by_colour);
  * flags, may be NULL); *num_colors receives the class count.
  */
 int lpa_color(lpa_graph *g, uint32_t seed, int32_t *colors_out, unsigned flags, int32_t *num_colors);
+
+/*
+ * lpa_batch_create - many independent graphs in one handle: a block-diagonal
+ * CSR (no entry crosses graphs) where graph g owns vertices
+ * [graph_vptr[g], graph_vptr[g+1]).  lpa_run then applies Algorithm 1 to
+ * every graph separately - its own sweep count and its own stop test
+ * dN_g / N_g <= tolerance; a graph that stops keeps its labels and flags while
+ * the others go on, and the whole run is one HIP graph launch.  Labels are
+ * global vertex ids.  graph_vptr is int64[n_graphs+1] (host memory);
+ * an entry joining two graphs gives LPA_ERR_INVALID_CSR.
+ */
+int lpa_batch_create(lpa_graph **out, int32_t n_graphs, const int64_t *graph_vptr, int64_t n, int64_t m,
+                     const int64_t *offsets, const int32_t *indices, const float *weights, int device,
+                     void *hip_stream, unsigned flags);
+
+/*
+ * lpa_batch_stats - per-graph results of the last batched run:
+ * iterations[n_graphs] and converged[n_graphs] (host arrays, may be NULL).
+ */
+int lpa_batch_stats(const lpa_graph *g, int32_t *iterations, int32_t *converged);
 
 /* lpa_destroy - release the handle and all device memory it owns (NULL is a no-op). */
 void lpa_destroy(lpa_graph *g);

@@ -40,6 +40,7 @@ LPA_FLAG_KERNEL_TIMING = 16
 LPA_FLAG_VERIFY = 32
 LPA_FLAG_TRACE = 64
 LPA_FLAG_EXACT_MARKS = 128
+LPA_FLAG_ONE_LAUNCH = 256
 
 MAX_SWEEPS_RECORDED = 64
 NUM_TIMED_KERNELS = 16
@@ -105,6 +106,8 @@ SIGNATURES = {
     "lpa_color": (ctypes.c_int, [_vp, _u32, _vp, ctypes.c_uint, ctypes.POINTER(_i32)]),
     "lpa_set_bins": (ctypes.c_int, [_vp, _vp, _i32]),
     "lpa_set_async_phases": (ctypes.c_int, [_vp, _i32, _i32]),
+    "lpa_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_uint]),
+    "lpa_batch_stats": (ctypes.c_int, [_vp, _vp, _vp]),
     "lpa_destroy": (None, [_vp]),
     "lpa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -193,6 +196,17 @@ def lpa_set_bins(handle, max_degree=None):
 
 def lpa_set_async_phases(handle, phases, by_colour=0):
     return load().lpa_set_async_phases(handle, phases, int(by_colour))
+
+
+def lpa_batch_create(n_graphs, graph_vptr, n, m, offsets, indices, weights=None, device=0, hip_stream=None, flags=0):
+    h = ctypes.c_void_p()
+    rc = load().lpa_batch_create(ctypes.byref(h), n_graphs, _ptr(graph_vptr), n, m, _ptr(offsets), _ptr(indices),
+                                 _ptr(weights), device, hip_stream, flags)
+    return rc, h
+
+
+def lpa_batch_stats(handle, iterations=None, converged=None):
+    return load().lpa_batch_stats(handle, _ptr(iterations), _ptr(converged))
 
 
 def lpa_destroy(handle):
@@ -286,3 +300,29 @@ class LPAGraph:
 
     def set_async_phases(self, phases, by_colour=False):
         _check(lpa_set_async_phases(self.handle, phases, by_colour), "lpa_set_async_phases")
+
+
+class LPABatch(LPAGraph):
+    """Many independent graphs (block-diagonal CSR) in one handle; graph g owns
+    vertices [graph_vptr[g], graph_vptr[g+1])."""
+
+    def __init__(self, csr, graph_vptr, device: int = 0, stream=None):
+        self.n = int(csr.n)
+        self.device = device
+        self.vptr = np.ascontiguousarray(graph_vptr, dtype=np.int64)
+        self.ngraphs = len(self.vptr) - 1
+        off = np.ascontiguousarray(csr.offsets, dtype=np.int64)
+        idx = np.ascontiguousarray(csr.indices, dtype=np.int32)
+        w = None if csr.weights is None else np.ascontiguousarray(csr.weights, dtype=np.float32)
+        self._keep = None
+        self.m = int(idx.shape[0])
+        self.stream = _current_stream(device) if stream is None else stream
+        rc, h = lpa_batch_create(self.ngraphs, self.vptr, self.n, self.m, off, idx, w, device, self.stream, 0)
+        _check(rc, "lpa_batch_create")
+        self.handle = h
+
+    def graph_stats(self):
+        it = np.zeros(self.ngraphs, np.int32)
+        cv = np.zeros(self.ngraphs, np.int32)
+        _check(lpa_batch_stats(self.handle, it, cv), "lpa_batch_stats")
+        return it, cv.astype(bool)

@@ -103,6 +103,8 @@ struct Ctl {
   // flags are set once at its end (pruning is exact, so processing a vertex
   // that would not have been flagged changes nothing).
   int32_t dense_enabled, dense_cur, dense_prev, pad0;
+  // batched runs: graphs still running, and graphs stopped by the sweep cap
+  int32_t batch, batch_remaining, batch_capped, pad1;
   double dense_frac;
   int64_t n_active;
   double tau;
@@ -129,6 +131,7 @@ struct ScanArgs {
   Ctl *ctl;
   int prune;
   int bin;
+  uint8_t *chg;  // batched runs: set to 1 for every vertex that changes (per-graph dN)
 };
 
 // Hub metadata (per hub, sorted by id) and per-step scratch.

@@ -108,11 +108,17 @@ struct lpa_graph {
   void *scratch_small = nullptr;  // CsrCheck + sums, ModAcc, counters
   int wall_khz = 100000;
   // graphs
-  std::map<std::tuple<int, int>, hipGraphExec_t> graphs;
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (mode, prune, sweeps per launch)
   // memory
   std::vector<void *> owned;
   size_t budget = 0, used = 0;
   int cu_count = 256;
+  // batched handle (graph g owns vertices [bvptr[g], bvptr[g+1]))
+  int32_t ngraphs = 0;
+  int32_t nlive = 0;
+  int64_t *bvptr = nullptr;
+  int32_t *bgid = nullptr, *bgdone = nullptr, *bgiters = nullptr, *bgconv = nullptr;
+  uint8_t *bchg = nullptr;
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -497,8 +503,21 @@ void ensure_dlists(lpa_graph *g) {
 
 // ---------------------------------------------------------------- sweep emission
 
+BatchArgs batch_args(lpa_graph *g) {
+  BatchArgs b{};
+  b.ngraphs = g->ngraphs;
+  b.vptr = g->bvptr;
+  b.gid = g->bgid;
+  b.chg = g->bchg;
+  b.gdone = g->bgdone;
+  b.giters = g->bgiters;
+  b.gconv = g->bgconv;
+  return b;
+}
+
 ScanArgs base_args(lpa_graph *g, int prune) {
   ScanArgs a{};
+  a.chg = g->ngraphs ? g->bchg : nullptr;
   a.off = g->off;
   a.idx = g->idx;
   a.w = g->w;
@@ -525,6 +544,8 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
   ca.fcount = fcount;
   ca.ctl = g->ctl;
   ca.prune = prune;
+  ca.gid = g->ngraphs ? g->bgid : nullptr;
+  ca.gdone = g->ngraphs ? g->bgdone : nullptr;
   tk_begin(g, st);
   launch_compact(ca, grid_cap(len, 2048, 4096), st);
   tk_end(g, st, TK_COMPACT);
@@ -571,18 +592,21 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune) {
   }
   const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : g->nphase * NBINS;
   tk_begin(g, st);
+  if (g->ngraphs) launch_batch_end(g->ctl, batch_args(g), st);
   launch_end_sweep(g->ctl, g->fcount, nfc, g->host_done_dev, st);
   if (mode == LPA_MODE_ASYNC && prune) launch_dense_fill(g->ctl, g->off, g->F, g->n, st);
   tk_end(g, st, TK_END_SWEEP);
 }
 
-hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune) {
-  auto key = std::make_tuple(mode, prune);
+// One HIP graph holding `sweeps` consecutive sweeps (their kernels exit at
+// once after the stop test holds), captured once per (mode, prune, sweeps).
+hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps) {
+  auto key = std::make_tuple(mode, prune, sweeps);
   auto it = g->graphs.find(key);
   if (it != g->graphs.end()) return it->second;
   hipGraph_t graph = nullptr;
   HIP_OK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-  emit_sweep(g, g->cap_stream, mode, prune);
+  for (int s = 0; s < sweeps; ++s) emit_sweep(g, g->cap_stream, mode, prune);
   HIP_OK(hipStreamEndCapture(g->cap_stream, &graph));
   hipGraphExec_t exec = nullptr;
   hipError_t e = hipGraphInstantiateWithFlags(&exec, graph, 0);
@@ -771,6 +795,60 @@ int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, co
   return LPA_OK;
 }
 
+int lpa_batch_create(lpa_graph **out, int32_t n_graphs, const int64_t *graph_vptr, int64_t n, int64_t m,
+                     const int64_t *offsets, const int32_t *indices, const float *weights, int device,
+                     void *hip_stream, unsigned flags) {
+  if (!out) return LPA_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n_graphs < 1 || !graph_vptr || graph_vptr[0] != 0 || graph_vptr[n_graphs] != n) return LPA_ERR_INVALID_ARG;
+  int32_t live = 0;
+  for (int32_t k = 0; k < n_graphs; ++k) {
+    if (graph_vptr[k + 1] < graph_vptr[k]) return LPA_ERR_INVALID_ARG;
+    live += graph_vptr[k + 1] > graph_vptr[k];
+  }
+  lpa_graph *g = nullptr;
+  int rc = lpa_create(&g, n, m, offsets, indices, weights, device, hip_stream, flags);
+  if (rc != LPA_OK) return rc;
+  rc = run_guarded(g, [&]() -> int {
+    // entries may not cross graphs (checked on the host offsets copy and the indices)
+    g->ngraphs = n_graphs;
+    g->nlive = live;
+    g->bvptr = dalloc_n<int64_t>(g, n_graphs + 1);
+    g->bgid = dalloc_n<int32_t>(g, n);
+    g->bchg = dalloc_n<uint8_t>(g, n);
+    g->bgdone = dalloc_n<int32_t>(g, n_graphs);
+    g->bgiters = dalloc_n<int32_t>(g, n_graphs);
+    g->bgconv = dalloc_n<int32_t>(g, n_graphs);
+    HIP_OK(hipMemcpyAsync(g->bvptr, graph_vptr, sizeof(int64_t) * (n_graphs + 1), hipMemcpyHostToDevice,
+                          g->stream));
+    launch_batch_gid(batch_args(g), g->stream);
+    int32_t *bad = (int32_t *)((char *)g->scratch_small + 2048);
+    HIP_OK(hipMemsetAsync(bad, 0, sizeof(int32_t), g->stream));
+    launch_check_block_diagonal(g->off, g->idx, g->bgid, g->n, bad, g->stream);
+    int32_t hb = 0;
+    HIP_OK(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+    HIP_OK(hipStreamSynchronize(g->stream));
+    return hb ? LPA_ERR_INVALID_CSR : LPA_OK;
+  });
+  if (rc != LPA_OK) {
+    lpa_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return LPA_OK;
+}
+
+int lpa_batch_stats(const lpa_graph *gc, int32_t *iterations, int32_t *converged) {
+  lpa_graph *g = const_cast<lpa_graph *>(gc);
+  return run_guarded(g, [&]() -> int {
+    if (!g->ngraphs) return LPA_ERR_INVALID_ARG;
+    if (iterations)
+      HIP_OK(hipMemcpy(iterations, g->bgiters, sizeof(int32_t) * g->ngraphs, hipMemcpyDeviceToHost));
+    if (converged) HIP_OK(hipMemcpy(converged, g->bgconv, sizeof(int32_t) * g->ngraphs, hipMemcpyDeviceToHost));
+    return LPA_OK;
+  });
+}
+
 int lpa_set_bins(lpa_graph *g, const int32_t *max_degree, int32_t count) {
   return run_guarded(g, [&]() -> int {
     BinLimits lim{};
@@ -855,8 +933,11 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     if (g->n)
       launch_init_state(g->off, g->C, g->F, g->n, init_labels ? 0 : 1, init_flags ? 0 : 1, max_iters > 0 ? 1 : 0,
                         g->stream);
+    // A batched handle replays the whole run as one graph launch; otherwise
+    // one sweep per launch, with the stop test polled one sweep behind.
+    const bool one_launch = use_graph && (g->ngraphs > 0 || (flags & LPA_FLAG_ONE_LAUNCH));
     hipGraphExec_t exec = nullptr;
-    if (use_graph && max_iters > 0) exec = sweep_graph(g, mode, prune);
+    if (use_graph && max_iters > 0) exec = sweep_graph(g, mode, prune, one_launch ? max_iters : 1);
     HIP_OK(hipEventRecord(e1, g->stream));
     HIP_OK(hipEventSynchronize(e1));
     float setup_ms = 0;
@@ -869,6 +950,10 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     const int dense = mode == LPA_MODE_ASYNC && prune && !(flags & LPA_FLAG_EXACT_MARKS);
     launch_run_begin(g->ctl, tolerance, max_iters, g->n, g->n_active, g->fcount, nfc, g->host_done_dev, dense,
                      !init_labels && !init_flags, g->stream);
+    if (g->ngraphs) launch_batch_begin(g->ctl, batch_args(g), g->n, g->nlive, g->stream);
+    if (one_launch && exec) {
+      HIP_OK(hipGraphLaunch(exec, g->stream));
+    } else
     for (int s = 0; s < max_iters; ++s) {
       if (exec) HIP_OK(hipGraphLaunch(exec, g->stream));
       else emit_sweep(g, g->stream, mode, prune);

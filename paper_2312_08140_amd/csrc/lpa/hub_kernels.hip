@@ -229,6 +229,7 @@ __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
         if (lane == 0) {
           a.C[v] = cs;
           ++n_changed;
+          if (a.chg) a.chg[v] = 1;
         }
       }
     }

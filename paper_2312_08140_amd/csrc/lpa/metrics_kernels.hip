@@ -21,9 +21,39 @@ __global__ void k_check_labels(const int32_t *C, int64_t n, int32_t *bad) {
   if (b) atomicOr(bad, 1);
 }
 
-__global__ void k_mod_community_totals(const int32_t *C, const uint32_t *K, int64_t n, u64 *tot) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    if (K[v]) atomicAdd(&tot[C[v]], (u64)K[v]);
+// Sigma_c = sum of K_v over v in c.  Each workgroup first merges its
+// vertices in an LDS table (label -> partial sum), so a community that
+// spans the graph costs one global atomic per workgroup, not per vertex.
+constexpr int TOT_SLOTS = 2048;
+
+__global__ __launch_bounds__(256) void k_mod_community_totals(const int32_t *C, const uint32_t *K, int64_t n,
+                                                              u64 *tot) {
+  __shared__ uint32_t keys[TOT_SLOTS];
+  __shared__ u64 vals[TOT_SLOTS];
+  for (int s = threadIdx.x; s < TOT_SLOTS; s += 256) {
+    keys[s] = 0xFFFFFFFFu;
+    vals[s] = 0;
+  }
+  __syncthreads();
+  for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+    const uint32_t k = K[v];
+    if (!k) continue;
+    const uint32_t c = (uint32_t)C[v];
+    uint32_t h = slot_hash(c, 11);
+    bool done = false;
+    for (int probe = 0; probe < 16 && !done; ++probe, h = (h + 1) & (TOT_SLOTS - 1)) {
+      uint32_t cur = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+      if (cur == 0xFFFFFFFFu) cur = atomicCAS(&keys[h], 0xFFFFFFFFu, c) == 0xFFFFFFFFu ? c : keys[h];
+      if (cur == c) {
+        atomicAdd(&vals[h], (u64)k);
+        done = true;
+      }
+    }
+    if (!done) atomicAdd(&tot[c], (u64)k);  // table crowded: direct
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < TOT_SLOTS; s += 256)
+    if (keys[s] != 0xFFFFFFFFu) atomicAdd(&tot[keys[s]], vals[s]);
 }
 
 // Edge-parallel pass: every block takes a contiguous range of stored entries
@@ -101,7 +131,7 @@ void launch_check_labels(const int32_t *C, int64_t n, int32_t *bad, hipStream_t 
   hipLaunchKernelGGL(k_check_labels, dim3(grid_for(n, 256)), dim3(256), 0, st, C, n, bad);
 }
 void launch_mod_community_totals(const int32_t *C, const uint32_t *K, int64_t n, u64 *tot, hipStream_t st) {
-  hipLaunchKernelGGL(k_mod_community_totals, dim3(grid_for(n, 256)), dim3(256), 0, st, C, K, n, tot);
+  hipLaunchKernelGGL(k_mod_community_totals, dim3(grid_for(n, 256 * 16, 4096)), dim3(256), 0, st, C, K, n, tot);
 }
 void launch_mod_inside(const int64_t *off, const int32_t *idx, const void *w, int wk, const int32_t *C, int64_t n,
                        int64_t m, ModAcc *acc, hipStream_t st) {

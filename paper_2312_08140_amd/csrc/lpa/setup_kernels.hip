@@ -54,17 +54,46 @@ __global__ void k_convert_weights(const float *w, int64_t m, int wk, void *out) 
   }
 }
 
+// K_v = summed stored weights of row v.  A lane sums a short row by itself;
+// the rows of more than 64 entries in a wave's 64 vertices are summed by the
+// whole wave together (rows are heavily skewed).
 template <int WK>
-__global__ void k_weighted_degree(const int64_t *off, const void *w, int64_t n, uint32_t *K, CsrCheck *chk) {
+__global__ __launch_bounds__(256) void k_weighted_degree(const int64_t *off, const void *w, int64_t n, uint32_t *K,
+                                                         CsrCheck *chk) {
   int big = 0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; base < n; base += waves * 64) {
+    const int64_t v = base + lane;
+    int64_t b = 0, e = 0;
+    if (v < n) {
+      b = off[v];
+      e = off[v + 1];
+    }
+    const bool longrow = e - b > 64;
     u64 s = 0;
-    const int64_t b = off[v], e = off[v + 1];
-    if constexpr (WK == W_UNIT) s = (u64)(e - b);
-    else
-      for (int64_t k = b; k < e; ++k) s += load_w<WK>(w, k);
-    big |= s >= (1ull << 32);
-    K[v] = (uint32_t)s;
+    if (!longrow) {
+      if constexpr (WK == W_UNIT) s = (u64)(e - b);
+      else
+        for (int64_t k = b; k < e; ++k) s += load_w<WK>(w, k);
+    }
+    u64 mask = __ballot(longrow);
+    while (mask) {
+      const int src = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      const int64_t bb = __shfl(b, src, 64), ee = __shfl(e, src, 64);
+      u64 part = 0;
+      if constexpr (WK == W_UNIT) part = lane == 0 ? (u64)(ee - bb) : 0;
+      else
+        for (int64_t k = bb + lane; k < ee; k += 64) part += load_w<WK>(w, k);
+#pragma unroll
+      for (int m = 32; m > 0; m >>= 1) part += shfl_xor_u64(part, m);
+      if (lane == src) s = part;
+    }
+    if (v < n) {
+      big |= s >= (1ull << 32);
+      K[v] = (uint32_t)s;
+    }
   }
   if (big) atomicOr(&chk->big_degree, 1);
 }
@@ -95,6 +124,15 @@ __global__ void k_check_symmetric(const int64_t *off, const int32_t *idx, const 
 __global__ void k_fill_u64(u64 *p, int64_t count, u64 value) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = value;
+}
+
+// Batched handles: no stored entry may join two graphs.
+__global__ void k_check_block_diagonal(const int64_t *off, const int32_t *idx, const int32_t *gid, int64_t n,
+                                       int32_t *bad) {
+  int b = 0;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < n; v += (int64_t)gridDim.x * 4)
+    for (int64_t k = off[v] + (threadIdx.x & 63); k < off[v + 1]; k += 64) b |= gid[idx[k]] != gid[v];
+  if (b) atomicOr(bad, 1);
 }
 
 // ---------------------------------------------------------------- binning
@@ -271,7 +309,7 @@ void launch_convert_weights(const float *w, int64_t m, int wk, void *out, hipStr
 }
 void launch_weighted_degree(const int64_t *off, const void *w, int wk, int64_t n, uint32_t *K, CsrCheck *chk,
                             hipStream_t st) {
-  dim3 g(grid_for(n, 256)), b(256);
+  dim3 g(grid_for(n, 256, 4096)), b(256);
   if (wk == W_UNIT) hipLaunchKernelGGL(k_weighted_degree<W_UNIT>, g, b, 0, st, off, w, n, K, chk);
   else if (wk == W_U8) hipLaunchKernelGGL(k_weighted_degree<W_U8>, g, b, 0, st, off, w, n, K, chk);
   else hipLaunchKernelGGL(k_weighted_degree<W_U32>, g, b, 0, st, off, w, n, K, chk);
@@ -298,6 +336,11 @@ void launch_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, con
                      lim, cursor, list, nkeys);
 }
 uint32_t phase_seed() { return PHASE_SEED; }
+
+void launch_check_block_diagonal(const int64_t *off, const int32_t *idx, const int32_t *gid, int64_t n, int32_t *bad,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_check_block_diagonal, dim3(grid_for(n, 4, 16384)), dim3(256), 0, st, off, idx, gid, n, bad);
+}
 
 void launch_fill_u64(u64 *p, int64_t count, u64 value, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256)), dim3(256), 0, st, p, count, value);

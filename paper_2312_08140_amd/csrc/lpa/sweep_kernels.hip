@@ -41,6 +41,7 @@ __global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int6
     ctl->dense_prev = 0;
     ctl->dense_frac = 0.5;
     ctl->n_active = n_active;
+    ctl->batch = 0;
     ctl->done = max_iters <= 0 ? 1 : 0;
     ctl->sweep = 0;
     ctl->iterations = 0;
@@ -85,10 +86,18 @@ __global__ void k_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_do
   ctl->dense_cur = ctl->dense_enabled && (double)dn > ctl->dense_frac * (double)ctl->n_active;
   ctl->iterations = s + 1;
   ctl->sweep = s + 1;
-  // Algorithm 1: stop when dN / N <= tau (evaluated in double).
-  const bool conv = (double)dn / (double)(ctl->n > 0 ? ctl->n : 1) <= ctl->tau;
-  if (conv) ctl->converged = 1;
-  if (conv || s + 1 >= ctl->max_iters) ctl->done = 1;
+  if (ctl->batch) {
+    // every graph has its own stop test (k_batch_end); the run ends with the last
+    if (ctl->batch_remaining == 0 || s + 1 >= ctl->max_iters) {
+      ctl->done = 1;
+      ctl->converged = ctl->batch_remaining == 0 && ctl->batch_capped == 0;
+    }
+  } else {
+    // Algorithm 1: stop when dN / N <= tau (evaluated in double).
+    const bool conv = (double)dn / (double)(ctl->n > 0 ? ctl->n : 1) <= ctl->tau;
+    if (conv) ctl->converged = 1;
+    if (conv || s + 1 >= ctl->max_iters) ctl->done = 1;
+  }
   ctl->changed = ctl->processed = ctl->scanned = ctl->gated = 0;
   if (host_done) {
     __atomic_store_n(host_done, ctl->done, __ATOMIC_RELAXED);
@@ -101,6 +110,74 @@ __global__ void k_dense_fill(const Ctl *ctl, const int64_t *off, uint8_t *F, int
   if (!__atomic_load_n(&ctl->dense_prev, __ATOMIC_RELAXED)) return;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
     if (off[v + 1] > off[v]) F[v] = 1;
+}
+
+// ---------------------------------------------------------------- batched runs
+
+__global__ void k_batch_gid(BatchArgs b) {
+  for (int g = blockIdx.x; g < b.ngraphs; g += gridDim.x)
+    for (int64_t v = b.vptr[g] + threadIdx.x; v < b.vptr[g + 1]; v += blockDim.x) b.gid[v] = g;
+}
+
+__global__ void k_batch_begin(Ctl *ctl, BatchArgs b, int64_t n, int32_t live) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    b.chg[v] = 0;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < b.ngraphs; g += gridDim.x * blockDim.x) {
+    b.gdone[g] = b.vptr[g + 1] == b.vptr[g];  // an empty graph has nothing to do
+    b.giters[g] = 0;
+    b.gconv[g] = b.vptr[g + 1] == b.vptr[g];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->batch = 1;
+    ctl->batch_remaining = live;
+    ctl->batch_capped = 0;
+  }
+}
+
+// Per-graph stop test of the sweep just finished (Algorithm 1 applied to
+// every graph separately): dN_g counts the graph's changed vertices.
+__global__ __launch_bounds__(256) void k_batch_end(Ctl *ctl, BatchArgs b) {
+  if (__atomic_load_n(&ctl->done, __ATOMIC_RELAXED)) return;
+  __shared__ int s_sum[4];
+  const int s = ctl->sweep;
+  for (int g = blockIdx.x; g < b.ngraphs; g += gridDim.x) {
+    const int64_t v0 = b.vptr[g], v1 = b.vptr[g + 1];
+    int c = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) {
+      c += b.chg[v];
+      b.chg[v] = 0;
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) c += __shfl_xor(c, m, 64);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0 && !b.gdone[g]) {
+      const int64_t dn = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+      b.giters[g] = s + 1;
+      if ((double)dn / (double)(v1 - v0) <= ctl->tau) {
+        b.gdone[g] = 1;
+        b.gconv[g] = 1;
+        atomicSub(&ctl->batch_remaining, 1);
+      } else if (s + 1 >= ctl->max_iters) {
+        b.gdone[g] = 1;
+        atomicSub(&ctl->batch_remaining, 1);
+        atomicAdd(&ctl->batch_capped, 1);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void launch_batch_gid(const BatchArgs &b, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_gid, dim3(std::max(1, std::min(b.ngraphs, 8192))), dim3(256), 0, st, b);
+}
+
+void launch_batch_begin(Ctl *ctl, const BatchArgs &b, int64_t n, int32_t live, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_begin, dim3(4096), dim3(256), 0, st, ctl, b, n, live);
+}
+
+void launch_batch_end(Ctl *ctl, const BatchArgs &b, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_end, dim3(std::max(1, std::min(b.ngraphs, 8192))), dim3(256), 0, st, ctl, b);
 }
 
 // ---------------------------------------------------------------- compaction
@@ -127,6 +204,11 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
     }
 #pragma unroll
     for (int r = 0; r < CU; ++r) f[r] = v[r] >= 0 ? (a.prune ? a.F[v[r]] : (uint8_t)1) : (uint8_t)0;
+    if (a.gdone) {  // batched: a graph that has stopped keeps its state
+#pragma unroll
+      for (int r = 0; r < CU; ++r)
+        if (f[r] && a.gdone[a.gid[v[r]]]) f[r] = 0;
+    }
     __syncthreads();
     int bin[CU], slot[CU];
 #pragma unroll
@@ -274,6 +356,7 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
         if (lane == 0) {
           a.C[A.v] = cs;
           ++n_changed;
+          if (a.chg) a.chg[A.v] = 1;
         }
         if (mark_now) {
           n_marks += A.mark(a);
@@ -330,6 +413,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
         if (threadIdx.x == 0) {
           a.C[A.v] = cs;
           ++n_changed;
+          if (a.chg) a.chg[A.v] = 1;
         }
         if (mark_now) {
           n_marks += A.mark(a);

@@ -17,6 +17,8 @@ struct CompactArgs {
   int32_t *fcount;
   Ctl *ctl;
   int prune;
+  const int32_t *gid;    // batched runs: graph of every vertex (NULL otherwise)
+  const int32_t *gdone;  // batched runs: 1 for a graph that has stopped
 };
 
 void launch_compact(const CompactArgs &a, int blocks, hipStream_t st);
@@ -31,6 +33,20 @@ void launch_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, in
 void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount, int nfc,
                       int32_t *host_done, int dense_enabled, int dense_first, hipStream_t st);
 void launch_dense_fill(const Ctl *ctl, const int64_t *off, uint8_t *F, int64_t n, hipStream_t st);
+
+// batched runs (graph g owns vertices [vptr[g], vptr[g+1]))
+struct BatchArgs {
+  int32_t ngraphs;
+  const int64_t *vptr;
+  int32_t *gid;
+  uint8_t *chg;
+  int32_t *gdone, *giters, *gconv;
+};
+void launch_batch_gid(const BatchArgs &b, hipStream_t st);
+void launch_batch_begin(Ctl *ctl, const BatchArgs &b, int64_t n, int32_t live, hipStream_t st);
+void launch_batch_end(Ctl *ctl, const BatchArgs &b, hipStream_t st);
+void launch_check_block_diagonal(const int64_t *off, const int32_t *idx, const int32_t *gid, int64_t n, int32_t *bad,
+                                 hipStream_t st);
 void launch_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_done, hipStream_t st);
 
 // setup_kernels.hip

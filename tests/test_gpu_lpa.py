@@ -261,3 +261,51 @@ def test_hub_partition_spill_path(monkeypatch):
     monkeypatch.setenv("GVELPA_HUB_PART_CAP", "3")
     g = gg.rmat(15, 16, seed=12)
     check_det(g)
+
+
+# ---------------------------------------------------------------- batched runs
+
+def _small_batch(count, seed, n_range=(60, 1500)):
+    return gg.sbm_batch(count=count, master_seed=seed, seed_base=500 + seed, n_range=n_range)
+
+
+@pytest.mark.parametrize("count,seed", [(1, 1), (37, 2), (200, 3)])
+def test_batch_deterministic_equals_independent_runs(count, seed):
+    """Each graph of the batch follows its own stop test; deterministic mode
+    equals the oracle run graph by graph (colour order restricted to the graph)."""
+    g, vptr = _small_batch(count, seed)
+    say(f"batch of {count}: n={g.n} m={g.m}")
+    B = abi.LPABatch(g, vptr)
+    labels, st = B.run(0.05, 20, DET, True)
+    it, cv = B.graph_stats()
+    ref = oracle.lpa_batch(g, vptr, deterministic=True, tau=0.05, max_iters=20)
+    for k in range(count):
+        lo, hi = int(vptr[k]), int(vptr[k + 1])
+        assert np.array_equal(labels[lo:hi], ref[k]["labels"]), f"graph {k}"
+        assert it[k] == ref[k]["iterations"] and cv[k] == ref[k]["converged"], f"graph {k}"
+    assert st["iterations"] == max(r["iterations"] for r in ref)
+    B.close()
+
+
+def test_batch_cap_and_async():
+    g, vptr = _small_batch(50, 4)
+    B = abi.LPABatch(g, vptr)
+    labels, st = B.run(0.0, 3, DET, True)
+    it, cv = B.graph_stats()
+    ref = oracle.lpa_batch(g, vptr, deterministic=True, tau=0.0, max_iters=3)
+    for k in range(50):
+        lo, hi = int(vptr[k]), int(vptr[k + 1])
+        assert np.array_equal(labels[lo:hi], ref[k]["labels"])
+        assert it[k] == ref[k]["iterations"] and cv[k] == ref[k]["converged"]
+    labels, st = B.run(0.05, 20, ASYNC, True)
+    it, cv = B.graph_stats()
+    gid = np.searchsorted(vptr, np.arange(g.n), side="right") - 1
+    assert np.array_equal(gid[labels], gid)  # labels stay inside their graph
+    assert cv.all() and st["converged"]
+    B.close()
+
+
+def test_batch_rejects_cross_edges():
+    g = gg.from_edges(6, [(0, 1), (2, 3), (3, 4)])
+    rc, _ = abi.lpa_batch_create(2, np.array([0, 3, 6], np.int64), g.n, g.m, g.offsets, g.indices)
+    assert rc == abi.LPA_ERR_INVALID_CSR
