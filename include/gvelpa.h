@@ -203,6 +203,90 @@ int lpa_batch_create(lpa_graph **out, int32_t n_graphs, const int64_t *graph_vpt
  */
 int lpa_batch_stats(const lpa_graph *g, int32_t *iterations, int32_t *converged);
 
+/*
+ * Learned active-set gate.  Vertex pruning (Section 4.1.4) processes every
+ * flagged vertex; the gate additionally skips a flagged vertex whose
+ * predicted chance of changing its label is below a threshold, and keeps it
+ * flagged for later sweeps.  The predictor is a network 8-32-32-1 (ReLU,
+ * ReLU, sigmoid) over eight features that each processing of a vertex leaves
+ * behind: log2(1 + deg), (W1 - W2) / K, W(own label) / K, changed at its last
+ * processing, sweep / max_iters, W1 / K, distinct neighbour labels / deg and
+ * min(sweeps since last processed, 8) / 8, where W1 >= W2 are the two largest
+ * label weights among the neighbours and K the weighted degree.  Parameters
+ * are 1377 FP32 values, W1[32][8], b1[32], W2[32][32], b2[32], W3[32], b3
+ * (row-major); the GPU evaluates their bf16 rounding (to nearest, ties to
+ * even) with FP32 sums.  A gated run (LPA_FLAG_GATE) always ends with a full
+ * unpruned verification sweep; if that sweep changes more than
+ * tolerance * n labels the run continues with plain pruning.
+ */
+
+/*
+ * lpa_gate_load - install gate parameters (host float[1377], finite) and the
+ * threshold in [0, 1]: a flagged vertex is processed when p >= threshold
+ * (0: every flagged vertex, the plain method; 1: none before verification).
+ * Takes effect for the next lpa_run with LPA_FLAG_GATE.
+ */
+int lpa_gate_load(lpa_graph *g, const float *params, float threshold);
+
+/*
+ * lpa_set_trace - make runs with LPA_FLAG_TRACE record training samples: for
+ * a vertex processed in sweep s that was last processed in sweep s' < s, the
+ * features it had for the decision at sweep s and the target 1 if its label
+ * changed at s.  Each such event is kept with the given probability (a fixed
+ * hash of (vertex, sweep)); at most `capacity` samples are kept.  Resets the
+ * sample buffer (capacity 0 frees it).
+ */
+int lpa_set_trace(lpa_graph *g, int64_t capacity, double probability);
+
+/*
+ * lpa_gate_trace - the samples recorded since lpa_set_trace: *count receives
+ * their number; with features != NULL, copies float[count][8] features and
+ * uint8[count] targets (host or device per flags; capacity = their length in
+ * samples, which must be >= *count).
+ */
+int lpa_gate_trace(const lpa_graph *g, float *features, uint8_t *targets, int64_t capacity, int64_t *count,
+                   unsigned flags);
+
+/*
+ * lpa_gate_forward - probabilities float[count] of the gate network for the
+ * features float[count][8] (host or device per flags; params always host).
+ * Runs on `device`, enqueued on hip_stream, synchronised before returning.
+ */
+int lpa_gate_forward(const float *params, const float *features, int64_t count, float *probs, int device,
+                     void *hip_stream, unsigned flags);
+
+/*
+ * lpa_gate_backward - gradient (host float[1377]) and value (*loss, may be
+ * NULL) of the mean weighted binary cross-entropy
+ *   L = mean over samples of -(pos_weight * y * log p + (1 - y) * log(1 - p))
+ * at params, over features float[count][8] and targets uint8[count] (0 or not
+ * 0; host or device per flags).  pos_weight >= 0.
+ */
+int lpa_gate_backward(const float *params, const float *features, const uint8_t *targets, int64_t count,
+                      float pos_weight, float *grad, float *loss, int device, void *hip_stream, unsigned flags);
+
+/*
+ * lpa_gate_train - Adam (Kingma and Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected) on the loss of lpa_gate_backward, FP32 master parameters
+ * updated in place in params (host float[1377]).  Each epoch takes the samples
+ * in the order order[e * count .. (e+1) * count) (int64, each in [0, count);
+ * NULL: 0, 1, ...) in mini-batches of `batch`, one update per mini-batch (its
+ * mean loss).  epoch_loss (host float[epochs], may be NULL) receives each
+ * epoch's sample-weighted mean of the mini-batch losses, each taken before its
+ * update.  features, targets and order are host or device per flags.
+ */
+int lpa_gate_train(float *params, const float *features, const uint8_t *targets, int64_t count,
+                   const int64_t *order, int32_t epochs, int32_t batch, float lr, float pos_weight,
+                   float *epoch_loss, int device, void *hip_stream, unsigned flags);
+
+/*
+ * lpa_gate_threshold - the largest threshold t such that at least a fraction
+ * `recall` of the samples with target 1 have p >= t (1 when no target is 1);
+ * arrays as in lpa_gate_backward.
+ */
+int lpa_gate_threshold(const float *params, const float *features, const uint8_t *targets, int64_t count,
+                       double recall, float *threshold, int device, void *hip_stream, unsigned flags);
+
 /* lpa_destroy - release the handle and all device memory it owns (NULL is a no-op). */
 void lpa_destroy(lpa_graph *g);
 

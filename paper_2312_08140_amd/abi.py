@@ -42,6 +42,9 @@ LPA_FLAG_TRACE = 64
 LPA_FLAG_EXACT_MARKS = 128
 LPA_FLAG_ONE_LAUNCH = 256
 
+GATE_PARAMS = 1377
+GATE_FEATURES = 8
+
 MAX_SWEEPS_RECORDED = 64
 NUM_TIMED_KERNELS = 16
 KERNEL_NAMES = ["compact", "bin0", "bin1", "bin2", "bin3", "bin4", "bin5", "hub_plan", "hub_chunk", "hub_finish",
@@ -108,6 +111,16 @@ SIGNATURES = {
     "lpa_set_async_phases": (ctypes.c_int, [_vp, _i32, _i32]),
     "lpa_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_uint]),
     "lpa_batch_stats": (ctypes.c_int, [_vp, _vp, _vp]),
+    "lpa_gate_load": (ctypes.c_int, [_vp, _vp, _f32]),
+    "lpa_set_trace": (ctypes.c_int, [_vp, _i64, _f64]),
+    "lpa_gate_trace": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(_i64), ctypes.c_uint]),
+    "lpa_gate_forward": (ctypes.c_int, [_vp, _vp, _i64, _vp, ctypes.c_int, _vp, ctypes.c_uint]),
+    "lpa_gate_backward": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f32, _vp, ctypes.POINTER(_f32), ctypes.c_int, _vp,
+                                         ctypes.c_uint]),
+    "lpa_gate_train": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i32, _i32, _f32, _f32, _vp, ctypes.c_int, _vp,
+                                      ctypes.c_uint]),
+    "lpa_gate_threshold": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, ctypes.POINTER(_f32), ctypes.c_int, _vp,
+                                          ctypes.c_uint]),
     "lpa_destroy": (None, [_vp]),
     "lpa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -213,6 +226,44 @@ def lpa_destroy(handle):
     load().lpa_destroy(handle)
 
 
+def lpa_gate_load(handle, params, threshold):
+    return load().lpa_gate_load(handle, _ptr(params), threshold)
+
+
+def lpa_set_trace(handle, capacity, probability):
+    return load().lpa_set_trace(handle, capacity, probability)
+
+
+def lpa_gate_trace(handle, features=None, targets=None, capacity=0, flags=0):
+    c = ctypes.c_int64()
+    rc = load().lpa_gate_trace(handle, _ptr(features), _ptr(targets), capacity, ctypes.byref(c), flags)
+    return rc, c.value
+
+
+def lpa_gate_forward(params, features, count, probs, device=0, hip_stream=None, flags=0):
+    return load().lpa_gate_forward(_ptr(params), _ptr(features), count, _ptr(probs), device, hip_stream, flags)
+
+
+def lpa_gate_backward(params, features, targets, count, pos_weight, grad, device=0, hip_stream=None, flags=0):
+    loss = ctypes.c_float()
+    rc = load().lpa_gate_backward(_ptr(params), _ptr(features), _ptr(targets), count, pos_weight, _ptr(grad),
+                                  ctypes.byref(loss), device, hip_stream, flags)
+    return rc, loss.value
+
+
+def lpa_gate_train(params, features, targets, count, order, epochs, batch, lr, pos_weight, epoch_loss=None,
+                   device=0, hip_stream=None, flags=0):
+    return load().lpa_gate_train(_ptr(params), _ptr(features), _ptr(targets), count, _ptr(order), epochs, batch, lr,
+                                 pos_weight, _ptr(epoch_loss), device, hip_stream, flags)
+
+
+def lpa_gate_threshold(params, features, targets, count, recall, device=0, hip_stream=None, flags=0):
+    t = ctypes.c_float()
+    rc = load().lpa_gate_threshold(_ptr(params), _ptr(features), _ptr(targets), count, recall, ctypes.byref(t),
+                                   device, hip_stream, flags)
+    return rc, t.value
+
+
 def lpa_status_string(code):
     return status_string(code)
 
@@ -300,6 +351,88 @@ class LPAGraph:
 
     def set_async_phases(self, phases, by_colour=False):
         _check(lpa_set_async_phases(self.handle, phases, by_colour), "lpa_set_async_phases")
+
+    def gate_load(self, params, threshold):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (GATE_PARAMS,):
+            raise ValueError(f"gate parameters must be {GATE_PARAMS} float32 values")
+        _check(lpa_gate_load(self.handle, p, float(threshold)), "lpa_gate_load")
+
+    def set_trace(self, capacity, probability=1.0):
+        _check(lpa_set_trace(self.handle, int(capacity), float(probability)), "lpa_set_trace")
+
+    def gate_trace(self):
+        """(features float32[count][8], targets uint8[count]) recorded since set_trace."""
+        rc, c = lpa_gate_trace(self.handle)
+        _check(rc, "lpa_gate_trace")
+        x = np.empty((c, GATE_FEATURES), np.float32)
+        y = np.empty(c, np.uint8)
+        if c:
+            rc, c2 = lpa_gate_trace(self.handle, x, y, c)
+            _check(rc, "lpa_gate_trace")
+        return x, y
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _samples(features, targets):
+    """Host or device sample arrays -> (features, targets, count, flags)."""
+    if hasattr(features, "data_ptr"):
+        if targets is not None and not hasattr(targets, "data_ptr"):
+            raise ValueError("features and targets must both be host or both device arrays")
+        return features, targets, int(features.shape[0]), LPA_FLAG_DEVICE_PTRS
+    x = np.ascontiguousarray(features, dtype=np.float32).reshape(-1, GATE_FEATURES)
+    y = None if targets is None else np.ascontiguousarray(targets, dtype=np.uint8)
+    return x, y, int(x.shape[0]), 0
+
+
+def gate_forward(params, features, device=0):
+    """Gate probabilities of every sample (float32[count], where the features live)."""
+    p = _f32(params, (GATE_PARAMS,))
+    x, _, c, fl = _samples(features, None)
+    out = (torch.empty(c, dtype=torch.float32, device=features.device) if fl else np.empty(c, np.float32))
+    _check(lpa_gate_forward(p, x, c, out, device, _current_stream(device), fl), "lpa_gate_forward")
+    return out
+
+
+def gate_backward(params, features, targets, pos_weight=1.0, device=0):
+    """(gradient float32[1377], loss) of the mean weighted BCE."""
+    p = _f32(params, (GATE_PARAMS,))
+    x, y, c, fl = _samples(features, targets)
+    g = np.empty(GATE_PARAMS, np.float32)
+    rc, loss = lpa_gate_backward(p, x, y, c, float(pos_weight), g, device, _current_stream(device), fl)
+    _check(rc, "lpa_gate_backward")
+    return g, loss
+
+
+def gate_train(params, features, targets, epochs, batch, lr=1e-3, pos_weight=1.0, order=None, device=0):
+    """Adam training; returns (new parameters float32[1377], per-epoch loss float32[epochs])."""
+    p = _f32(params, (GATE_PARAMS,)).copy()
+    x, y, c, fl = _samples(features, targets)
+    if order is not None:
+        if fl:
+            if not hasattr(order, "data_ptr"):
+                raise ValueError("order must live where the samples live")
+        else:
+            order = np.ascontiguousarray(order, dtype=np.int64)
+    losses = np.zeros(max(epochs, 1), np.float32)
+    rc = lpa_gate_train(p, x, y, c, order, int(epochs), int(batch), float(lr), float(pos_weight), losses, device,
+                        _current_stream(device), fl)
+    _check(rc, "lpa_gate_train")
+    return p, losses[:epochs]
+
+
+def gate_threshold(params, features, targets, recall, device=0):
+    p = _f32(params, (GATE_PARAMS,))
+    x, y, c, fl = _samples(features, targets)
+    rc, t = lpa_gate_threshold(p, x, y, c, float(recall), device, _current_stream(device), fl)
+    _check(rc, "lpa_gate_threshold")
+    return t
 
 
 class LPABatch(LPAGraph):

@@ -97,7 +97,8 @@ struct Ctl {
   int32_t error;       // nonzero: a table overflowed (never expected)
   int32_t max_iters;
   int32_t verify_phase;  // 1 while a verification sweep runs
-  int32_t gate_on;
+  int32_t gate_on;       // 1: flagged vertices pass the gate before processing
+  int32_t verified;      // last verification sweep changed <= tau * n labels
   // Dense sweeps (asynchronous mode): when most vertices change, every
   // neighbour would be flagged anyway; the sweep then writes no marks and all
   // flags are set once at its end (pruning is exact, so processing a vertex
@@ -119,6 +120,45 @@ struct Ctl {
   u64 compact_listed, compact_taken;
 };
 
+// ---------------------------------------------------------------- gate
+// Learned active-set gate: an 8-32-32-1 network predicts whether a flagged
+// vertex will change label.  Its inputs, for vertex v at sweep s:
+//   x0 = log2(1 + deg v)            x4 = s / max_iters
+//   x1 = (W1 - W2) / K_v            x5 = W1 / K_v
+//   x2 = W(own label) / K_v         x6 = distinct labels / deg v
+//   x3 = 1 if v changed when last processed
+//   x7 = min(s - sweep of last processing, 8) / 8
+// with W1 >= W2 the two largest label weights of v's last scan and K_v its
+// weighted degree.  x0-x3, x5, x6 are stored per vertex when it is processed.
+constexpr int NFEAT = 8;
+constexpr int NSTORED = 6;
+constexpr int GATE_PARAMS = 32 * 8 + 32 + 32 * 32 + 32 + 32 + 1;  // 1377
+
+struct FeatArgs {
+  float *feat;         // [n][NSTORED]: x0 x1 x2 x3 x5 x6 of the last processing
+  int16_t *lastp;      // sweep of the last processing, -1 = never
+  const uint32_t *K;   // weighted degrees
+  float *tx;           // trace features [tcap][NFEAT]
+  uint8_t *ty;         // trace targets (1 = the vertex changed)
+  u64 *tcount;
+  u64 tcap;
+  uint32_t tthresh;    // a sample is kept when its hash is below this
+  int trace;
+  int max_iters;
+};
+
+__device__ __forceinline__ void decision_features(const float *st, int lastp, int s, int max_iters, float *x) {
+  x[0] = st[0];
+  x[1] = st[1];
+  x[2] = st[2];
+  x[3] = st[3];
+  x[4] = (float)s / (float)(max_iters > 0 ? max_iters : 1);
+  x[5] = st[4];
+  x[6] = st[5];
+  const int age = s - lastp;
+  x[7] = (float)(age < 8 ? age : 8) * 0.125f;
+}
+
 // Per-step arguments of the scan kernels.
 struct ScanArgs {
   const int64_t *off;
@@ -132,6 +172,7 @@ struct ScanArgs {
   int prune;
   int bin;
   uint8_t *chg;  // batched runs: set to 1 for every vertex that changes (per-graph dN)
+  FeatArgs f;    // gate features and traces (kernels built with FEAT)
 };
 
 // Hub metadata (per hub, sorted by id) and per-step scratch.
@@ -154,6 +195,9 @@ struct HubArgs {
   int32_t *chunk_owner;      // per chunk id of the step: frontier entry
   int32_t *part_owner;       // per partition id of the step: frontier entry
   int32_t *changed;          // per frontier entry: 1 if the hub took a new label
+  uint32_t *part_w2;         // FEAT: second largest label weight of each partition
+  int32_t *part_nd;          // FEAT: distinct labels of each partition
+  uint32_t *own_w;           // FEAT: per frontier entry, weight of the hub's own label
   int32_t max_pbits;         // largest pbits of any hub (sizes the chunk kernel's LDS)
 };
 

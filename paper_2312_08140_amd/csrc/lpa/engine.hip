@@ -100,6 +100,8 @@ struct lpa_graph {
   int32_t *hub_ord = nullptr;
   u64 *hub_cstart = nullptr, *hub_pstart = nullptr;
   int32_t *hub_chunk_owner = nullptr, *hub_part_owner = nullptr, *hub_changed = nullptr;
+  uint32_t *hub_part_w2 = nullptr, *hub_own_w = nullptr;
+  int32_t *hub_part_nd = nullptr;
   int32_t hub_max_pbits = 0;
   // control
   Ctl *ctl = nullptr;
@@ -108,7 +110,20 @@ struct lpa_graph {
   void *scratch_small = nullptr;  // CsrCheck + sums, ModAcc, counters
   int wall_khz = 100000;
   // graphs
-  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (mode, prune, sweeps per launch)
+  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (mode, prune, sweeps per launch, features)
+  // learned gate
+  bool feat_on = false;           // the sweeps being emitted write gate features
+  FeatArgs cur_feat{};
+  uint16_t *gate_w = nullptr;     // bf16 parameters
+  float gate_z = 0.0f;            // logit threshold
+  bool gate_loaded = false;
+  float *feat = nullptr;          // [n][NSTORED]
+  int16_t *lastp = nullptr;
+  float *tx = nullptr;            // trace
+  uint8_t *ty = nullptr;
+  u64 *tcount = nullptr;
+  int64_t tcap = 0;
+  uint32_t tthresh = 0xFFFFFFFFu;
   // memory
   std::vector<void *> owned;
   size_t budget = 0, used = 0;
@@ -297,7 +312,8 @@ void build_hubs(lpa_graph *g) {
                    (void **)&g->hub_pcnt, (void **)&g->hub_partbest, (void **)&g->hub_ovf,
                    (void **)&g->hub_ovf_count, (void **)&g->hub_ord, (void **)&g->hub_cstart,
                    (void **)&g->hub_pstart, (void **)&g->hub_chunk_owner, (void **)&g->hub_part_owner,
-                   (void **)&g->hub_changed};
+                   (void **)&g->hub_changed, (void **)&g->hub_part_w2, (void **)&g->hub_own_w,
+                   (void **)&g->hub_part_nd};
   for (void **b : bufs) {
     dfree(g, *b);
     *b = nullptr;
@@ -343,6 +359,9 @@ void build_hubs(lpa_graph *g) {
   g->hub_cstart = dalloc_n<u64>(g, n1);
   g->hub_pstart = dalloc_n<u64>(g, n1);
   g->hub_changed = dalloc_n<int32_t>(g, n1);
+  g->hub_own_w = dalloc_n<uint32_t>(g, n1);
+  g->hub_part_w2 = dalloc_n<uint32_t>(g, std::max<int64_t>(1, parts));
+  g->hub_part_nd = dalloc_n<int32_t>(g, std::max<int64_t>(1, parts));
   g->hub_pairs = dalloc_n<u64>(g, std::max<int64_t>(1, pairs));
   g->hub_pcnt = dalloc_n<int32_t>(g, std::max<int64_t>(1, parts));
   g->hub_partbest = dalloc_n<u64>(g, std::max<int64_t>(1, parts));
@@ -382,6 +401,9 @@ HubArgs hub_args(lpa_graph *g) {
   h.chunk_owner = g->hub_chunk_owner;
   h.part_owner = g->hub_part_owner;
   h.changed = g->hub_changed;
+  h.part_w2 = g->hub_part_w2;
+  h.part_nd = g->hub_part_nd;
+  h.own_w = g->hub_own_w;
   h.max_pbits = g->hub_max_pbits;
   return h;
 }
@@ -515,8 +537,24 @@ BatchArgs batch_args(lpa_graph *g) {
   return b;
 }
 
+FeatArgs feat_args(lpa_graph *g, int max_iters, bool trace) {
+  FeatArgs f{};
+  f.feat = g->feat;
+  f.lastp = g->lastp;
+  f.K = g->K;
+  f.tx = g->tx;
+  f.ty = g->ty;
+  f.tcount = g->tcount;
+  f.tcap = (u64)g->tcap;
+  f.tthresh = g->tthresh;
+  f.trace = trace && g->tcap > 0;
+  f.max_iters = max_iters;
+  return f;
+}
+
 ScanArgs base_args(lpa_graph *g, int prune) {
   ScanArgs a{};
+  a.f = g->cur_feat;
   a.chg = g->ngraphs ? g->bchg : nullptr;
   a.off = g->off;
   a.idx = g->idx;
@@ -546,6 +584,9 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
   ca.prune = prune;
   ca.gid = g->ngraphs ? g->bgid : nullptr;
   ca.gdone = g->ngraphs ? g->bgdone : nullptr;
+  ca.gate = g->feat_on && g->gate_loaded ? g->gate_w : nullptr;
+  ca.gate_z = g->gate_z;
+  ca.f = g->cur_feat;
   tk_begin(g, st);
   launch_compact(ca, grid_cap(len, 2048, 4096), st);
   tk_end(g, st, TK_COMPACT);
@@ -566,15 +607,16 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
       launch_hub_chunk(g->wk, grid_cap(hub_chunks, 1, max_blocks * 2), st, a, h);
       tk_end(g, st, TK_HUB_SCAN);
       tk_begin(g, st);
-      launch_hub_part(grid_cap(hub_parts, 1, max_blocks * 2), st, a, h);
+      launch_hub_part(grid_cap(hub_parts, 1, max_blocks * 2), g->feat_on, st, a, h);
       tk_end(g, st, TK_HUB_PART);
       tk_begin(g, st);
-      launch_hub_finish(grid_cap(seg, 4, max_blocks), grid_cap(hub_chunks, 1, max_blocks * 2), prune, st, a, h);
+      launch_hub_finish(grid_cap(seg, 4, max_blocks), grid_cap(hub_chunks, 1, max_blocks * 2), prune, g->feat_on, st,
+                        a, h);
       tk_end(g, st, TK_HUB_FINISH);
     } else {
       const int per_block = b <= 3 ? 256 / BIN_GROUP[b] : 1;
       tk_begin(g, st);
-      launch_scan_bin(b, g->wk, grid_cap(seg, per_block, max_blocks), st, a);
+      launch_scan_bin(b, g->wk, g->feat_on, grid_cap(seg, per_block, max_blocks), st, a);
       tk_end(g, st, TK_BIN0 + b);
     }
   }
@@ -601,7 +643,9 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune) {
 // One HIP graph holding `sweeps` consecutive sweeps (their kernels exit at
 // once after the stop test holds), captured once per (mode, prune, sweeps).
 hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps) {
-  auto key = std::make_tuple(mode, prune, sweeps);
+  // captured kernels embed the feature arguments (trace switch, sweep cap)
+  const int fcode = g->feat_on ? 1 + 2 * g->cur_feat.trace + 4 * g->cur_feat.max_iters : 0;
+  auto key = std::make_tuple(mode, prune, sweeps, fcode);
   auto it = g->graphs.find(key);
   if (it != g->graphs.end()) return it->second;
   hipGraph_t graph = nullptr;
@@ -849,6 +893,72 @@ int lpa_batch_stats(const lpa_graph *gc, int32_t *iterations, int32_t *converged
   });
 }
 
+int lpa_gate_load(lpa_graph *g, const float *params, float threshold) {
+  return run_guarded(g, [&]() -> int {
+    if (!params || !(threshold >= 0.0f) || !(threshold <= 1.0f)) return LPA_ERR_INVALID_ARG;
+    uint16_t bf[GATE_PARAMS];
+    for (int k = 0; k < GATE_PARAMS; ++k) {
+      if (!std::isfinite(params[k])) return LPA_ERR_INVALID_ARG;
+      uint32_t u;
+      std::memcpy(&u, &params[k], 4);
+      u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+      bf[k] = (uint16_t)(u >> 16);
+    }
+    if (!g->gate_w) g->gate_w = dalloc_n<uint16_t>(g, GATE_PARAMS);
+    HIP_OK(hipMemcpy(g->gate_w, bf, sizeof(bf), hipMemcpyHostToDevice));
+    // p >= threshold  <=>  logit >= log(threshold / (1 - threshold))
+    if (threshold <= 0.0f) g->gate_z = -INFINITY;
+    else if (threshold >= 1.0f) g->gate_z = INFINITY;
+    else g->gate_z = (float)std::log((double)threshold / (1.0 - (double)threshold));
+    g->gate_loaded = true;
+    drop_graphs(g);
+    return LPA_OK;
+  });
+}
+
+int lpa_set_trace(lpa_graph *g, int64_t capacity, double probability) {
+  return run_guarded(g, [&]() -> int {
+    if (capacity < 0 || !(probability >= 0.0) || !(probability <= 1.0)) return LPA_ERR_INVALID_ARG;
+    dfree(g, g->tx);
+    dfree(g, g->ty);
+    dfree(g, g->tcount);
+    g->tx = nullptr;
+    g->ty = nullptr;
+    g->tcount = nullptr;
+    g->tcap = capacity;
+    g->tthresh = probability >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(probability * 4294967296.0);
+    if (capacity > 0) {
+      g->tx = dalloc_n<float>(g, capacity * NFEAT);
+      g->ty = dalloc_n<uint8_t>(g, capacity);
+      g->tcount = dalloc_n<u64>(g, 1);
+      HIP_OK(hipMemsetAsync(g->tcount, 0, sizeof(u64), g->stream));
+      HIP_OK(hipStreamSynchronize(g->stream));
+    }
+    drop_graphs(g);
+    return LPA_OK;
+  });
+}
+
+int lpa_gate_trace(const lpa_graph *gc, float *features, uint8_t *targets, int64_t capacity, int64_t *count,
+                   unsigned flags) {
+  lpa_graph *g = const_cast<lpa_graph *>(gc);
+  return run_guarded(g, [&]() -> int {
+    if (!count) return LPA_ERR_INVALID_ARG;
+    u64 c = 0;
+    if (g->tcount) HIP_OK(hipMemcpy(&c, g->tcount, sizeof(u64), hipMemcpyDeviceToHost));
+    const int64_t have = std::min<int64_t>((int64_t)c, g->tcap);
+    *count = have;
+    if (!features) return LPA_OK;
+    if (!targets || capacity < have) return LPA_ERR_INVALID_ARG;
+    if (have) {
+      copy_out(g, features, g->tx, sizeof(float) * NFEAT * have, flags);
+      copy_out(g, targets, g->ty, have, flags);
+      HIP_OK(hipStreamSynchronize(g->stream));
+    }
+    return LPA_OK;
+  });
+}
+
 int lpa_set_bins(lpa_graph *g, const int32_t *max_degree, int32_t count) {
   return run_guarded(g, [&]() -> int {
     BinLimits lim{};
@@ -904,7 +1014,8 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
   if (!g || max_iters < 0 || max_iters > 1000 || (mode != LPA_MODE_ASYNC && mode != LPA_MODE_DETERMINISTIC) ||
       !(tolerance == tolerance))
     return LPA_ERR_INVALID_ARG;
-  if (flags & LPA_FLAG_GATE) return LPA_ERR_NO_GATE;
+  if ((flags & LPA_FLAG_GATE) && !g->gate_loaded) return LPA_ERR_NO_GATE;
+  if ((flags & (LPA_FLAG_GATE | LPA_FLAG_VERIFY)) && g->ngraphs) return LPA_ERR_INVALID_ARG;
   return run_guarded(g, [&]() -> int {
     Events ev;
     hipEvent_t e0 = ev.e[0], e1 = ev.e[1], t0 = ev.e[2], t1 = ev.e[3];
@@ -936,6 +1047,18 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     // A batched handle replays the whole run as one graph launch; otherwise
     // one sweep per launch, with the stop test polled one sweep behind.
     const bool one_launch = use_graph && (g->ngraphs > 0 || (flags & LPA_FLAG_ONE_LAUNCH));
+    // gate features: written while the gate is used or training traces are recorded
+    const bool gate = flags & LPA_FLAG_GATE;
+    const bool trace = flags & LPA_FLAG_TRACE;
+    g->feat_on = gate || trace;
+    if (g->feat_on) {
+      if (!g->feat) {
+        g->feat = dalloc_n<float>(g, g->n * NSTORED);
+        g->lastp = dalloc_n<int16_t>(g, g->n);
+      }
+      launch_fill_i16(g->lastp, g->n, (int16_t)-1, g->stream);
+    }
+    g->cur_feat = feat_args(g, max_iters, trace);
     hipGraphExec_t exec = nullptr;
     if (use_graph && max_iters > 0) exec = sweep_graph(g, mode, prune, one_launch ? max_iters : 1);
     HIP_OK(hipEventRecord(e1, g->stream));
@@ -949,7 +1072,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : g->nphase * NBINS;
     const int dense = mode == LPA_MODE_ASYNC && prune && !(flags & LPA_FLAG_EXACT_MARKS);
     launch_run_begin(g->ctl, tolerance, max_iters, g->n, g->n_active, g->fcount, nfc, g->host_done_dev, dense,
-                     !init_labels && !init_flags, g->stream);
+                     !init_labels && !init_flags, gate ? 1 : 0, g->stream);
     if (g->ngraphs) launch_batch_begin(g->ctl, batch_args(g), g->n, g->nlive, g->stream);
     if (one_launch && exec) {
       HIP_OK(hipGraphLaunch(exec, g->stream));
@@ -963,9 +1086,39 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
         if (__atomic_load_n(g->host_done, __ATOMIC_ACQUIRE)) break;
       }
     }
+    // Verification: one full sweep after convergence; if it changes more than
+    // tau * n labels the run goes on with plain pruning (gate off), then
+    // verifies once more.
+    auto sweep_loop = [&](int budget) {
+      for (int s = 0; s < budget; ++s) {
+        if (exec) HIP_OK(hipGraphLaunch(exec, g->stream));
+        else emit_sweep(g, g->stream, mode, prune);
+        HIP_OK(hipEventRecord(lag[s & 1], g->stream));
+        if (s >= 1) {
+          HIP_OK(hipEventSynchronize(lag[(s - 1) & 1]));
+          if (__atomic_load_n(g->host_done, __ATOMIC_ACQUIRE)) break;
+        }
+      }
+    };
+    int verified = -1;
+    if ((flags & (LPA_FLAG_VERIFY | LPA_FLAG_GATE)) && max_iters > 0 && !one_launch) {
+      for (int attempt = 0; attempt < 2; ++attempt) {
+        launch_set_phase(g->ctl, 1, 0, 0, g->host_done_dev, g->stream);
+        if (exec) HIP_OK(hipGraphLaunch(exec, g->stream));
+        else emit_sweep(g, g->stream, mode, prune);
+        int32_t vflag = 0;
+        HIP_OK(hipMemcpyAsync(&vflag, &g->ctl->verified, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+        HIP_OK(hipStreamSynchronize(g->stream));
+        verified = vflag;
+        if (vflag || attempt == 1) break;
+        launch_set_phase(g->ctl, 0, 0, max_iters, g->host_done_dev, g->stream);
+        sweep_loop(max_iters);
+      }
+    }
     HIP_OK(hipEventRecord(t1, g->stream));
     HIP_OK(hipStreamSynchronize(g->stream));
     g->timing = false;
+    g->feat_on = false;
     Ctl h;
     HIP_OK(hipMemcpy(&h, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
     float run_ms = 0;
@@ -979,6 +1132,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       std::memset(stats, 0, sizeof(*stats));
       stats->iterations = h.iterations;
       stats->converged = h.converged;
+      stats->verified = verified > 0;
       stats->num_colors = mode == LPA_MODE_DETERMINISTIC ? g->ncol : 0;
       u64 prev = h.t_start;
       for (int s = 0; s < std::min(h.iterations, MAX_REC); ++s) {

@@ -52,6 +52,7 @@ __global__ __launch_bounds__(1024) void k_hub_plan(ScanArgs a, HubArgs h) {
         kp = (u64)1 << h.pbits[lo];
       }
       h.ord[i] = lo;
+      if (h.own_w) h.own_w[i] = 0;
     }
     u64 xc = kc, xp = kp;
 #pragma unroll
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
   if (err) atomicOr(&a.ctl->error, err);
 }
 
+template <bool FEAT>
 __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   constexpr int BITS = __builtin_ctz(HUB_PART_SLOTS);
@@ -202,6 +204,19 @@ __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
       h.partbest[q] = best;
       *cnt = 0;  // partitions start empty at the next step
     }
+    if constexpr (FEAT) {
+      __shared__ TabStats tred[4];
+      const TabStats t = group_stats<64>(table_stats<256, HUB_PART_SLOTS>(T, threadIdx.x));
+      if ((threadIdx.x & 63) == 0) tred[threadIdx.x >> 6] = t;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const TabStats m = merge_stats(merge_stats(tred[0], tred[1]), merge_stats(tred[2], tred[3]));
+        h.part_w2[q] = m.w2;
+        h.part_nd[q] = m.nd;
+        const uint32_t cur = (uint32_t)a.C[a.front[i]];
+        if ((int)part_of(cur, h.pbits[k]) == p) h.own_w[i] = table_lookup<BITS>(T, cur);
+      }
+    }
     __syncthreads();
   }
   if (err) atomicOr(&a.ctl->error, 16);
@@ -209,10 +224,12 @@ __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
 
 // Strict argmax of each flagged hub over its partitions, and the update.
 // One wave per hub.
+template <bool FEAT>
 __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   const int count = *a.fcount;
   const int lane = threadIdx.x & 63;
+  const int sweep = FEAT ? a.ctl->sweep : 0;
   u64 n_changed = 0, n_scanned = 0, n_vert = 0;
   for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < count; i += gridDim.x * 4) {
     const int v = a.front[i];
@@ -222,9 +239,10 @@ __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
     for (int p = lane; p < P; p += 64) best = pb[p] > best ? pb[p] : best;
     best = group_max<64>(best);
     int changed = 0;
+    const int32_t cur = a.C[v];
     if (best != 0) {
       const int32_t cs = (int32_t)key_label(best);
-      if (cs != a.C[v]) {
+      if (cs != cur) {
         changed = 1;
         if (lane == 0) {
           a.C[v] = cs;
@@ -232,6 +250,20 @@ __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
           if (a.chg) a.chg[v] = 1;
         }
       }
+    }
+    if constexpr (FEAT) {
+      TabStats t{0u, 0u, 0};
+      const u64 q0 = h.pstart[i];
+      for (int p = lane; p < P; p += 64) {
+        const u64 key = pb[p];
+        TabStats o;
+        o.w1 = key ? (uint32_t)(key >> 32) : 0u;
+        o.w2 = h.part_w2[q0 + p];
+        o.nd = h.part_nd[q0 + p];
+        t = merge_stats(t, o);
+      }
+      t = group_stats<64>(t);
+      if (lane == 0) write_features(a.f, v, sweep, a.off[v + 1] - a.off[v], t, h.own_w[i], changed != 0);
     }
     if (lane == 0) {
       h.changed[i] = changed;
@@ -271,13 +303,15 @@ void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, con
   else hipLaunchKernelGGL(k_hub_chunk<W_U32>, dim3(blocks), dim3(256), lds, st, a, h);
 }
 
-void launch_hub_part(int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h) {
-  hipLaunchKernelGGL(k_hub_part, dim3(blocks), dim3(256), 0, st, a, h);
+void launch_hub_part(int blocks, bool feat, hipStream_t st, const ScanArgs &a, const HubArgs &h) {
+  if (feat) hipLaunchKernelGGL(k_hub_part<true>, dim3(blocks), dim3(256), 0, st, a, h);
+  else hipLaunchKernelGGL(k_hub_part<false>, dim3(blocks), dim3(256), 0, st, a, h);
 }
 
-void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, hipStream_t st, const ScanArgs &a,
+void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, bool feat, hipStream_t st, const ScanArgs &a,
                        const HubArgs &h) {
-  hipLaunchKernelGGL(k_hub_decide, dim3(hub_blocks), dim3(256), 0, st, a, h);
+  if (feat) hipLaunchKernelGGL(k_hub_decide<true>, dim3(hub_blocks), dim3(256), 0, st, a, h);
+  else hipLaunchKernelGGL(k_hub_decide<false>, dim3(hub_blocks), dim3(256), 0, st, a, h);
   if (prune) hipLaunchKernelGGL(k_hub_mark, dim3(chunk_blocks), dim3(256), 0, st, a, h);
 }
 

@@ -33,7 +33,7 @@ __global__ void k_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t
 }
 
 __global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount,
-                            int nfc, int32_t *host_done, int dense_enabled, int dense_first) {
+                            int nfc, int32_t *host_done, int dense_enabled, int dense_first, int gate_on) {
   for (int k = threadIdx.x; k < nfc; k += blockDim.x) fcount[k] = 0;
   if (threadIdx.x == 0) {
     ctl->dense_enabled = dense_enabled;
@@ -42,6 +42,8 @@ __global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int6
     ctl->dense_frac = 0.5;
     ctl->n_active = n_active;
     ctl->batch = 0;
+    ctl->gate_on = gate_on;
+    ctl->verified = 0;
     ctl->done = max_iters <= 0 ? 1 : 0;
     ctl->sweep = 0;
     ctl->iterations = 0;
@@ -74,17 +76,34 @@ __global__ void k_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_do
   if (threadIdx.x != 0) return;
   const int s = ctl->sweep;
   const u64 dn = ctl->changed;
-  if (s < MAX_REC) {
-    ctl->st_changed[s] = dn;
-    ctl->st_processed[s] = ctl->processed;
-    ctl->st_scanned[s] = ctl->scanned;
-    ctl->st_gated[s] = ctl->gated;
-    ctl->t_sweep[s] = wall_clock64();
+  if (ctl->verify_phase) {
+    // a verification sweep: one full sweep, judged by the same stop test
+    ctl->verify_changed += dn;
+    ctl->total_changed += dn;
+    ctl->verified = (double)dn / (double)(ctl->n > 0 ? ctl->n : 1) <= ctl->tau;
+    ctl->sweep = s + 1;
+    ctl->dense_prev = ctl->dense_cur;
+    ctl->dense_cur = ctl->dense_enabled && (double)dn > ctl->dense_frac * (double)ctl->n_active;
+    ctl->changed = ctl->processed = ctl->scanned = ctl->gated = 0;
+    ctl->done = 1;
+    if (host_done) {
+      __atomic_store_n(host_done, 1, __ATOMIC_RELAXED);
+      __threadfence_system();
+    }
+    return;
+  }
+  const int it = ctl->iterations;  // sweeps of the method so far (verification sweeps excluded)
+  if (it < MAX_REC) {
+    ctl->st_changed[it] = dn;
+    ctl->st_processed[it] = ctl->processed;
+    ctl->st_scanned[it] = ctl->scanned;
+    ctl->st_gated[it] = ctl->gated;
+    ctl->t_sweep[it] = wall_clock64();
   }
   ctl->total_changed += dn;
   ctl->dense_prev = ctl->dense_cur;
   ctl->dense_cur = ctl->dense_enabled && (double)dn > ctl->dense_frac * (double)ctl->n_active;
-  ctl->iterations = s + 1;
+  ctl->iterations = it + 1;
   ctl->sweep = s + 1;
   if (ctl->batch) {
     // every graph has its own stop test (k_batch_end); the run ends with the last
@@ -187,12 +206,45 @@ void launch_batch_end(Ctl *ctl, const BatchArgs &b, hipStream_t st) {
 // reserves the tile's range.
 constexpr int CU = 8;
 
+// Logit of the gate network (parameters already in LDS as fp32 values of
+// their bf16 rounding; W1[32][8], b1, W2[32][32], b2, W3[32], b3).
+__device__ __forceinline__ float gate_logit(const float *P, const float *x) {
+  const float *W1 = P, *b1 = P + 256, *W2 = P + 288, *b2 = P + 1312, *W3 = P + 1344;
+  float h1[32];
+#pragma unroll
+  for (int o = 0; o < 32; ++o) {
+    float acc = b1[o];
+#pragma unroll
+    for (int q = 0; q < NFEAT; ++q) acc = fmaf(W1[o * 8 + q], x[q], acc);
+    h1[o] = acc > 0.0f ? acc : 0.0f;
+  }
+  float z = P[1376];
+  for (int o = 0; o < 32; ++o) {
+    float acc = b2[o];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) acc = fmaf(W2[o * 32 + q], h1[q], acc);
+    z = fmaf(W3[o], acc > 0.0f ? acc : 0.0f, z);
+  }
+  return z;
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
 __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   __shared__ int lcount[NBINS];
   __shared__ int lbase[NBINS];
-  __shared__ int s_taken[4];
-  int taken_total = 0;
+  __shared__ int s_taken[4], s_gated[4];
+  __shared__ float gp[GATE_PARAMS];
+  // a verification sweep takes every vertex; the gate acts from sweep 1 on
+  const bool take_all = a.ctl->verify_phase != 0;
+  const int sweep = a.ctl->sweep;
+  const bool gate = a.gate && a.ctl->gate_on && !take_all && sweep >= 1;
+  if (gate) {
+    for (int k = threadIdx.x; k < GATE_PARAMS; k += 256) gp[k] = bf16_to_f32(a.gate[k]);
+    __syncthreads();
+  }
+  int taken_total = 0, gated_total = 0;
   for (int64_t tile = (int64_t)blockIdx.x * 256 * CU; tile < a.len; tile += (int64_t)gridDim.x * 256 * CU) {
     if (threadIdx.x < NBINS) lcount[threadIdx.x] = 0;
     int v[CU];
@@ -203,11 +255,25 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
       v[r] = p < a.len ? a.list[p] : -1;
     }
 #pragma unroll
-    for (int r = 0; r < CU; ++r) f[r] = v[r] >= 0 ? (a.prune ? a.F[v[r]] : (uint8_t)1) : (uint8_t)0;
+    for (int r = 0; r < CU; ++r)
+      f[r] = v[r] >= 0 ? ((a.prune && !take_all) ? a.F[v[r]] : (uint8_t)1) : (uint8_t)0;
     if (a.gdone) {  // batched: a graph that has stopped keeps its state
 #pragma unroll
       for (int r = 0; r < CU; ++r)
         if (f[r] && a.gdone[a.gid[v[r]]]) f[r] = 0;
+    }
+    if (gate) {  // a flagged vertex the network expects to keep its label stays flagged, unprocessed
+      for (int r = 0; r < CU; ++r) {
+        if (!f[r]) continue;
+        const int lp = a.f.lastp[v[r]];
+        if (lp < 0) continue;
+        float x[NFEAT];
+        decision_features(a.f.feat + (int64_t)v[r] * NSTORED, lp, sweep, a.f.max_iters, x);
+        if (gate_logit(gp, x) < a.gate_z) {
+          f[r] = 0;
+          ++gated_total;
+        }
+      }
     }
     __syncthreads();
     int bin[CU], slot[CU];
@@ -235,15 +301,23 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
     __syncthreads();
   }
 #pragma unroll
-  for (int m = 32; m > 0; m >>= 1) taken_total += __shfl_xor(taken_total, m, 64);
-  if ((threadIdx.x & 63) == 0) s_taken[threadIdx.x >> 6] = taken_total;
+  for (int m = 32; m > 0; m >>= 1) {
+    taken_total += __shfl_xor(taken_total, m, 64);
+    gated_total += __shfl_xor(gated_total, m, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_taken[threadIdx.x >> 6] = taken_total;
+    s_gated[threadIdx.x >> 6] = gated_total;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     const int t = s_taken[0] + s_taken[1] + s_taken[2] + s_taken[3];
+    const int gt = s_gated[0] + s_gated[1] + s_gated[2] + s_gated[3];
     if (t) {
       atomicAdd((u64 *)&a.ctl->processed, (u64)t);
       atomicAdd((u64 *)&a.ctl->compact_taken, (u64)t);
     }
+    if (gt) atomicAdd((u64 *)&a.ctl->gated, (u64)gt);
     int64_t listed = 0;
     for (int64_t tile = (int64_t)blockIdx.x * 256 * CU; tile < a.len; tile += (int64_t)gridDim.x * 256 * CU)
       listed += min((int64_t)256 * CU, a.len - tile);
@@ -312,7 +386,7 @@ struct RowStage {
 // group g at tab[s * GPB + g], so the lanes of a wave - mostly different
 // groups - hit different LDS banks); larger groups keep their table
 // contiguous (the lanes of one group then spread over the banks by hash).
-template <int GROUP, int SLOTS, int U, int WK>
+template <int GROUP, int SLOTS, int U, int WK, bool FEAT>
 __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
   static_assert(GROUP <= 64 && (GROUP & (GROUP - 1)) == 0, "a group lives inside one wave");
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
@@ -326,6 +400,7 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
   const int count = *a.fcount;
   const int stride = gridDim.x * GPB;
   const bool mark_now = a.prune && !__atomic_load_n(&a.ctl->dense_cur, __ATOMIC_RELAXED);
+  const int sweep = FEAT ? a.ctl->sweep : 0;
   u64 n_changed = 0, n_scanned = 0, n_vert = 0, n_marks = 0;
   int overflow = 0;
   int i = blockIdx.x * GPB + grp;
@@ -350,9 +425,11 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
           scan_row_strided<GROUP, U, BITS, TS, WK>(a.idx, a.w, a.C, A.b + (int64_t)GROUP * U, A.e, A.v, lane, T);
     wave_lds_sync();
     const u64 best = group_max<GROUP>(table_best<GROUP, SLOTS, TS>(T, lane));
+    bool changed = false;
     if (best != 0) {
       const int32_t cs = (int32_t)key_label(best);
       if (cs != A.cur) {
+        changed = true;
         if (lane == 0) {
           a.C[A.v] = cs;
           ++n_changed;
@@ -363,6 +440,11 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
           if (!one_pass) n_marks += mark_row<GROUP, U>(a.idx, a.F, A.b + (int64_t)GROUP * U, A.e, A.v, lane);
         }
       }
+    }
+    if constexpr (FEAT) {
+      const TabStats t = group_stats<GROUP>(table_stats<GROUP, SLOTS, TS>(T, lane));
+      if (lane == 0)
+        write_features(a.f, A.v, sweep, A.e - A.b, t, table_lookup<BITS, TS>(T, (uint32_t)A.cur), changed);
     }
     if (lane == 0) {
       n_scanned += (u64)(A.e - A.b);
@@ -377,15 +459,17 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
 }
 
 // One workgroup of BLOCK threads per vertex.
-template <int BLOCK, int SLOTS, int U, int WK>
+template <int BLOCK, int SLOTS, int U, int WK, bool FEAT>
 __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   constexpr int BITS = __builtin_ctz(SLOTS);
   __shared__ u64 T[SLOTS];
   __shared__ u64 red[BLOCK / 64];
+  __shared__ TabStats tred[FEAT ? BLOCK / 64 : 1];
   const int count = *a.fcount;
   const int stride = gridDim.x;
   const bool mark_now = a.prune && !__atomic_load_n(&a.ctl->dense_cur, __ATOMIC_RELAXED);
+  const int sweep = FEAT ? a.ctl->sweep : 0;
   u64 n_changed = 0, n_scanned = 0, n_vert = 0, n_marks = 0;
   int overflow = 0;
   int i = blockIdx.x;
@@ -407,9 +491,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
       overflow |= scan_row<BLOCK, U, BITS, WK>(a.idx, a.w, a.C, A.b + (int64_t)BLOCK * U, A.e, A.v, threadIdx.x, T);
     __syncthreads();
     const u64 best = block_max<BLOCK>(table_best<BLOCK, SLOTS>(T, threadIdx.x), red);
+    bool changed = false;
     if (best != 0) {
       const int32_t cs = (int32_t)key_label(best);
       if (cs != A.cur) {
+        changed = true;
         if (threadIdx.x == 0) {
           a.C[A.v] = cs;
           ++n_changed;
@@ -419,6 +505,16 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
           n_marks += A.mark(a);
           if (!one_pass) n_marks += mark_row<BLOCK, U>(a.idx, a.F, A.b + (int64_t)BLOCK * U, A.e, A.v, threadIdx.x);
         }
+      }
+    }
+    if constexpr (FEAT) {
+      const TabStats t = group_stats<64>(table_stats<BLOCK, SLOTS>(T, threadIdx.x));
+      if ((threadIdx.x & 63) == 0) tred[threadIdx.x >> 6] = t;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        TabStats m = tred[0];
+        for (int k = 1; k < BLOCK / 64; ++k) m = merge_stats(m, tred[k]);
+        write_features(a.f, A.v, sweep, A.e - A.b, m, table_lookup<BITS>(T, (uint32_t)A.cur), changed);
       }
     }
     if (threadIdx.x == 0) {
@@ -435,15 +531,15 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
 
 // ---------------------------------------------------------------- launchers
 
-template <int WK>
+template <int WK, bool FEAT>
 static void launch_bin_wk(int bin, dim3 grid, hipStream_t st, const ScanArgs &a) {
   switch (bin) {
-    case 0: hipLaunchKernelGGL((k_scan_group<1, 8, 4, WK>), grid, dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_scan_group<2, 32, 8, WK>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_scan_group<8, 128, 8, WK>), grid, dim3(256), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_scan_group<32, 512, 8, WK>), grid, dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_scan_block<128, 2048, 8, WK>), grid, dim3(128), 0, st, a); break;
-    case 5: hipLaunchKernelGGL((k_scan_block<256, 8192, 16, WK>), grid, dim3(256), 0, st, a); break;
+    case 0: hipLaunchKernelGGL((k_scan_group<1, 8, 4, WK, FEAT>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_scan_group<2, 32, 8, WK, FEAT>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_scan_group<8, 128, 8, WK, FEAT>), grid, dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_scan_group<32, 512, 8, WK, FEAT>), grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_scan_block<128, 2048, 8, WK, FEAT>), grid, dim3(128), 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_scan_block<256, 8192, 16, WK, FEAT>), grid, dim3(256), 0, st, a); break;
     default: break;
   }
 }
@@ -455,10 +551,16 @@ static_assert(BIN_GROUP[3] == 32 && BIN_SLOTS[3] == 512, "bin table and launcher
 static_assert(BIN_GROUP[4] == 128 && BIN_SLOTS[4] == 2048, "bin table and launcher disagree");
 static_assert(BIN_GROUP[5] == 256 && BIN_SLOTS[5] == 8192, "bin table and launcher disagree");
 
-void launch_scan_bin(int bin, int wk, int blocks, hipStream_t st, const ScanArgs &a) {
-  if (wk == W_UNIT) launch_bin_wk<W_UNIT>(bin, dim3(blocks), st, a);
-  else if (wk == W_U8) launch_bin_wk<W_U8>(bin, dim3(blocks), st, a);
-  else launch_bin_wk<W_U32>(bin, dim3(blocks), st, a);
+void launch_scan_bin(int bin, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a) {
+  if (feat) {
+    if (wk == W_UNIT) launch_bin_wk<W_UNIT, true>(bin, dim3(blocks), st, a);
+    else if (wk == W_U8) launch_bin_wk<W_U8, true>(bin, dim3(blocks), st, a);
+    else launch_bin_wk<W_U32, true>(bin, dim3(blocks), st, a);
+  } else {
+    if (wk == W_UNIT) launch_bin_wk<W_UNIT, false>(bin, dim3(blocks), st, a);
+    else if (wk == W_U8) launch_bin_wk<W_U8, false>(bin, dim3(blocks), st, a);
+    else launch_bin_wk<W_U32, false>(bin, dim3(blocks), st, a);
+  }
 }
 
 void launch_compact(const CompactArgs &a, int blocks, hipStream_t st) {
@@ -474,9 +576,34 @@ void launch_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, in
 }
 
 void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount, int nfc,
-                      int32_t *host_done, int dense_enabled, int dense_first, hipStream_t st) {
+                      int32_t *host_done, int dense_enabled, int dense_first, int gate_on, hipStream_t st) {
   hipLaunchKernelGGL(k_run_begin, dim3(1), dim3(256), 0, st, ctl, tau, max_iters, n, n_active, fcount, nfc, host_done,
-                     dense_enabled, dense_first);
+                     dense_enabled, dense_first, gate_on);
+}
+
+__global__ void k_set_phase(Ctl *ctl, int verify, int gate_on, int extra_iters, int32_t *host_done) {
+  ctl->verify_phase = verify;
+  ctl->gate_on = gate_on;
+  ctl->max_iters += extra_iters;
+  ctl->done = 0;
+  if (host_done) {
+    __atomic_store_n(host_done, 0, __ATOMIC_RELAXED);
+    __threadfence_system();
+  }
+}
+
+void launch_set_phase(Ctl *ctl, int verify, int gate_on, int extra_iters, int32_t *host_done, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(1), 0, st, ctl, verify, gate_on, extra_iters, host_done);
+}
+
+__global__ void k_fill_i16(int16_t *p, int64_t count, int16_t value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+void launch_fill_i16(int16_t *p, int64_t count, int16_t value, hipStream_t st) {
+  int blocks = (int)std::min<int64_t>((count + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill_i16, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, st, p, count, value);
 }
 
 void launch_dense_fill(const Ctl *ctl, const int64_t *off, uint8_t *F, int64_t n, hipStream_t st) {

@@ -19,20 +19,25 @@ struct CompactArgs {
   int prune;
   const int32_t *gid;    // batched runs: graph of every vertex (NULL otherwise)
   const int32_t *gdone;  // batched runs: 1 for a graph that has stopped
+  const uint16_t *gate;  // bf16 gate parameters (NULL: no gate)
+  float gate_z;          // process a vertex when the network's logit >= gate_z
+  FeatArgs f;
 };
 
 void launch_compact(const CompactArgs &a, int blocks, hipStream_t st);
-void launch_scan_bin(int bin, int wk, int blocks, hipStream_t st, const ScanArgs &a);
+void launch_scan_bin(int bin, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a);
 void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, hipStream_t st);
 void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
-void launch_hub_part(int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
-void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, hipStream_t st, const ScanArgs &a,
+void launch_hub_part(int blocks, bool feat, hipStream_t st, const ScanArgs &a, const HubArgs &h);
+void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, bool feat, hipStream_t st, const ScanArgs &a,
                        const HubArgs &h);
 void launch_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, int set_labels, int set_flags,
                        int clear_isolated, hipStream_t st);
 void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount, int nfc,
-                      int32_t *host_done, int dense_enabled, int dense_first, hipStream_t st);
+                      int32_t *host_done, int dense_enabled, int dense_first, int gate_on, hipStream_t st);
 void launch_dense_fill(const Ctl *ctl, const int64_t *off, uint8_t *F, int64_t n, hipStream_t st);
+void launch_set_phase(Ctl *ctl, int verify, int gate_on, int extra_iters, int32_t *host_done, hipStream_t st);
+void launch_fill_i16(int16_t *p, int64_t count, int16_t value, hipStream_t st);
 
 // batched runs (graph g owns vertices [vptr[g], vptr[g+1]))
 struct BatchArgs {
@@ -90,5 +95,18 @@ void launch_mod_inside(const int64_t *off, const int32_t *idx, const void *w, in
 int mod_square_blocks();
 void launch_mod_squares(const u64 *tot, int64_t n, u64 *partials /* 2 per block */, hipStream_t st);
 void launch_check_labels(const int32_t *C, int64_t n, int32_t *bad, hipStream_t st);
+
+// gate_kernels.hip: the gate network's forward pass, gradient of the weighted
+// BCE (per-workgroup partials of GATE_PARAMS + 1 floats, the last the loss,
+// summed into grad) and the Adam update of the FP32 master parameters.
+void launch_gate_forward(const float *master, const float *X, int64_t count, float *p, hipStream_t st);
+int gate_grad_blocks(int64_t nb);
+void launch_gate_grad(const float *master, const float *X, const uint8_t *Y, const int64_t *sel, int64_t base,
+                      int64_t nb, float pw, float denom, float *partial, float *grad, hipStream_t st);
+void launch_adam(float *theta, const float *grad, float *m, float *v, int t, float lr, float b1, float b2, float eps,
+                 float *loss_acc, float loss_scale, hipStream_t st);
+void launch_check_index(const int64_t *sel, int64_t len, int64_t limit, int32_t *bad, hipStream_t st);
+void launch_select_pos(const float *p, const uint8_t *Y, int64_t count, float *out, unsigned long long *npos,
+                       hipStream_t st);
 
 }  // namespace gvelpa

@@ -124,6 +124,101 @@ __device__ __forceinline__ u64 table_best(const u64 *T, int lane) {
   return best;
 }
 
+// ---------------------------------------------------------------- gate features
+
+// Top-2 label weights and distinct labels among the slots lane, lane+G, ...
+struct TabStats {
+  uint32_t w1, w2;
+  int nd;
+};
+
+template <int G, int SLOTS, int STRIDE = 1>
+__device__ __forceinline__ TabStats table_stats(const u64 *T, int lane) {
+  TabStats r{0u, 0u, 0};
+  for (int s = lane; s < SLOTS; s += G) {
+    const u64 x = T[s * STRIDE];
+    if (x != EMPTY) {
+      const uint32_t w = (uint32_t)x;
+      ++r.nd;
+      if (w > r.w1) {
+        r.w2 = r.w1;
+        r.w1 = w;
+      } else if (w > r.w2) {
+        r.w2 = w;
+      }
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ TabStats merge_stats(TabStats a, TabStats b) {
+  TabStats r;
+  r.w1 = a.w1 > b.w1 ? a.w1 : b.w1;
+  const uint32_t lo = a.w1 > b.w1 ? b.w1 : a.w1;
+  const uint32_t m2 = a.w2 > b.w2 ? a.w2 : b.w2;
+  r.w2 = lo > m2 ? lo : m2;
+  r.nd = a.nd + b.nd;
+  return r;
+}
+
+template <int WIDTH>
+__device__ __forceinline__ TabStats group_stats(TabStats t) {
+#pragma unroll
+  for (int m = WIDTH / 2; m > 0; m >>= 1) {
+    TabStats o;
+    o.w1 = __shfl_xor(t.w1, m, 64);
+    o.w2 = __shfl_xor(t.w2, m, 64);
+    o.nd = __shfl_xor(t.nd, m, 64);
+    t = merge_stats(t, o);
+  }
+  return t;
+}
+
+// Weight of label lbl in table T (0 if absent); read-only probe.
+template <int BITS, int STRIDE = 1>
+__device__ __forceinline__ uint32_t table_lookup(const u64 *T, uint32_t lbl) {
+  constexpr uint32_t MASK = (1u << BITS) - 1;
+  uint32_t h = slot_hash(lbl, BITS);
+  for (int probe = 0; probe <= (int)MASK; ++probe) {
+    const u64 x = T[h * STRIDE];
+    if (x == EMPTY) return 0u;
+    if ((uint32_t)(x >> 32) == lbl) return (uint32_t)x;
+    h = (h + 1) & MASK;
+  }
+  return 0u;
+}
+
+// Stores the features of processed vertex v (sweep s) and, when tracing,
+// records the decision-time features it had before this processing together
+// with whether it changed now.
+__device__ __forceinline__ void write_features(const FeatArgs &f, int v, int s, int64_t deg, TabStats t,
+                                               uint32_t wown, bool changed) {
+  float *st = f.feat + (int64_t)v * NSTORED;
+  const int lp = f.lastp[v];
+  if (f.trace && lp >= 0 && lp < s) {
+    const uint32_t hsh = fmix32((uint32_t)v * 0x9E3779B1u ^ (uint32_t)s * 0x85EBCA77u);
+    if (hsh < f.tthresh) {
+      const u64 pos = atomicAdd(f.tcount, (u64)1);
+      if (pos < f.tcap) {
+        float x[NFEAT];
+        decision_features(st, lp, s, f.max_iters, x);
+#pragma unroll
+        for (int q = 0; q < NFEAT; ++q) f.tx[pos * NFEAT + q] = x[q];
+        f.ty[pos] = changed ? 1 : 0;
+      }
+    }
+  }
+  const uint32_t K = f.K[v];
+  const float inv = K ? 1.0f / (float)K : 0.0f;
+  st[0] = log2f(1.0f + (float)deg);
+  st[1] = (float)(t.w1 - t.w2) * inv;
+  st[2] = (float)wown * inv;
+  st[3] = changed ? 1.0f : 0.0f;
+  st[4] = (float)t.w1 * inv;
+  st[5] = deg ? (float)t.nd / (float)deg : 0.0f;
+  f.lastp[v] = (int16_t)s;
+}
+
 // Block-wide maximum (every thread gets the result); red holds BLOCK/64 entries.
 template <int BLOCK>
 __device__ __forceinline__ u64 block_max(u64 x, u64 *red) {

@@ -87,3 +87,34 @@ def test_no_device_reports_device_error():
         pytest.skip("a GPU is present")
     g = gg.sbm(100, 2, 0.2, 0.01, seed=1)
     assert _create(g.n, g.offsets, g.indices) == abi.LPA_ERR_DEVICE
+
+
+def test_gate_argument_errors_on_host():
+    p = np.zeros(abi.GATE_PARAMS, np.float32)
+    x = np.zeros((4, 8), np.float32)
+    y = np.zeros(4, np.uint8)
+    out = np.zeros(4, np.float32)
+    g = np.zeros(abi.GATE_PARAMS, np.float32)
+    assert abi.lpa_gate_forward(None, x, 4, out) == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_gate_forward(p, None, 4, out) == abi.LPA_ERR_INVALID_ARG
+    bad = p.copy()
+    bad[7] = np.nan
+    assert abi.lpa_gate_forward(bad, x, 4, out) == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_gate_backward(p, x, y, 0, 1.0, g)[0] == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_gate_backward(p, x, y, 4, -1.0, g)[0] == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_gate_train(p, x, y, 4, None, 1, 0, 1e-3, 1.0) == abi.LPA_ERR_INVALID_ARG      # batch 0
+    assert abi.lpa_gate_train(p, x, y, 4, None, 1, 2, 0.0, 1.0) == abi.LPA_ERR_INVALID_ARG      # lr 0
+    order = np.array([0, 1, 2, 4], np.int64)                                                    # 4 out of range
+    assert abi.lpa_gate_train(p, x, y, 4, order, 1, 2, 1e-3, 1.0) == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_gate_threshold(p, x, y, 4, 1.5)[0] == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_gate_load(None, p, 0.5) == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_set_trace(None, 10, 0.5) == abi.LPA_ERR_INVALID_ARG
+
+
+def test_gate_no_device_reports_device_error():
+    from tests.conftest import gpu_available
+    if gpu_available():
+        pytest.skip("a GPU is present")
+    p = np.zeros(abi.GATE_PARAMS, np.float32)
+    x = np.zeros((4, 8), np.float32)
+    assert abi.lpa_gate_forward(p, x, 4, np.zeros(4, np.float32)) == abi.LPA_ERR_DEVICE

@@ -1,0 +1,256 @@
+"""GPU parity of the learned active-set gate.
+
+* the network's forward pass, gradient and Adam steps against the FP64
+  oracle of ``oracle/mlp.py`` evaluated at the same bf16-rounded weights;
+* the traced samples of a deterministic run against the sequential trace
+  oracle (same vertex order, so the same sample multiset);
+* gated runs: threshold 0 is the plain method followed by the verification
+  sweep, bit for bit in deterministic mode; threshold 1 skips every flagged
+  vertex and the verification sweep's fallback still reaches the plain
+  quality; a trained gate keeps modularity within 0.01 of the plain run.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from oracle.gate_trace import lpa_trace
+from paper_2312_08140_amd import abi, gate, graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+DET, ASYNC = abi.LPA_MODE_DETERMINISTIC, abi.LPA_MODE_ASYNC
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def random_samples(count, seed):
+    """Features in the ranges the sweep produces: f0 = log2(1 + deg), f3 0/1, the rest in [0, 1]."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0.0, 1.0, (count, 8)).astype(np.float32)
+    X[:, 0] = np.log2(1.0 + rng.integers(1, 5000, count)).astype(np.float32)
+    X[:, 3] = rng.integers(0, 2, count).astype(np.float32)
+    y = (rng.uniform(size=count) < 0.3).astype(np.uint8)
+    return X, y
+
+
+def random_params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(mlp.NPARAMS) * scale).astype(np.float32)
+
+
+def normwise(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("count", [1, 127, 10_000])
+def test_forward_matches_oracle(count):
+    say(f"gate forward count={count}")
+    X, _ = random_samples(count, 1)
+    p32 = random_params(2)
+    p = abi.gate_forward(p32, X)
+    ref, _ = mlp.forward(mlp.bf16_round(p32), X.astype(np.float64))
+    assert np.max(np.abs(p - ref) / np.maximum(ref, 1e-30)) <= 1e-5
+
+
+def test_forward_device_pointers():
+    import torch
+    X, _ = random_samples(3000, 3)
+    p32 = random_params(4)
+    host = abi.gate_forward(p32, X)
+    dev = abi.gate_forward(p32, torch.from_numpy(X).cuda())
+    assert np.array_equal(dev.cpu().numpy(), host)
+
+
+@pytest.mark.parametrize("count,pw", [(1, 1.0), (3000, 2.5), ((1 << 22) + 777, 4.0)])
+def test_backward_matches_oracle(count, pw):
+    """Gradient per tensor within 1e-3 normwise of the FP64 gradient at the
+    same bf16 weights; the loss within 1e-5.  The largest case spans two of
+    the library's 4 Mi-sample slices."""
+    say(f"gate backward count={count} pos_weight={pw}")
+    X, y = random_samples(count, 5)
+    p32 = random_params(6)
+    g, loss = abi.gate_backward(p32, X, y, pos_weight=pw)
+    pb = mlp.bf16_round(p32)
+    gref = mlp.backward(pb, X.astype(np.float64), y, pos_weight=pw)
+    lref = mlp.loss(pb, X.astype(np.float64), y, pos_weight=pw)
+    assert abs(loss - lref) <= 1e-5 * abs(lref)
+    gd, rd = mlp.unpack(g), mlp.unpack(gref)
+    for name, _ in mlp.SHAPES:
+        assert normwise(gd[name], rd[name]) <= 1e-3, name
+
+
+def test_train_matches_oracle_adam():
+    """Two epochs of mini-batch Adam (ragged last batch, shuffled order)
+    against the same steps in FP64 at the bf16 rounding of an FP32 master."""
+    count, batch, epochs, lr, pw = 1000, 256, 2, 1e-3, 2.0
+    X, y = random_samples(count, 7)
+    p32 = random_params(8)
+    rng = np.random.default_rng(9)
+    order = np.concatenate([rng.permutation(count) for _ in range(epochs)]).astype(np.int64)
+    got, losses = abi.gate_train(p32, X, y, epochs, batch, lr=lr, pos_weight=pw, order=order)
+    theta = p32.astype(np.float32)
+    m = np.zeros(mlp.NPARAMS)
+    v = np.zeros(mlp.NPARAMS)
+    t = 0
+    ref_losses = []
+    for e in range(epochs):
+        acc = 0.0
+        for b in range(0, count, batch):
+            sel = order[e * count + b:e * count + min(b + batch, count)]
+            pb = mlp.bf16_round(theta)
+            acc += mlp.loss(pb, X[sel].astype(np.float64), y[sel], pw) * len(sel) / count
+            gr = mlp.backward(pb, X[sel].astype(np.float64), y[sel], pos_weight=pw)
+            t += 1
+            th64, m, v = mlp.adam_step(theta.astype(np.float64), gr, m, v, t, lr=lr)
+            theta = th64.astype(np.float32)
+        ref_losses.append(acc)
+    assert np.allclose(losses, ref_losses, rtol=1e-4)
+    d_gpu = got.astype(np.float64) - p32
+    d_ref = theta.astype(np.float64) - p32
+    # Adam moves each weight by about lr per step; only a gradient within
+    # rounding of zero can flip a step's sign
+    assert normwise(d_gpu, d_ref) <= 2e-2
+    assert np.mean(np.abs(d_gpu - d_ref) > 1e-5) <= 0.01
+
+
+def test_train_learns_a_rule():
+    """A label that is a threshold rule of two features becomes predictable."""
+    X, _ = random_samples(20_000, 10)
+    y = ((X[:, 1] < 0.3) & (X[:, 3] > 0.5)).astype(np.uint8)
+    info = gate.train(X, y, epochs=20, batch=512, lr=3e-3, recall=0.98, seed=1)
+    assert info["losses"][-1] < 0.25 * info["losses"][0]
+    assert info["holdout_recall"] >= 0.98
+    # the positives are 15 % of the samples; a useful gate skips most of the rest
+    assert info["holdout_skip"] >= 0.7
+
+
+def test_threshold_keeps_recall():
+    X, y = random_samples(5000, 11)
+    p32 = random_params(12)
+    for r in (0.5, 0.9, 1.0):
+        t = abi.gate_threshold(p32, X, y, r)
+        p = abi.gate_forward(p32, X)
+        pos = p[y == 1]
+        assert np.mean(pos >= t) >= r
+        assert np.any(pos == t)        # the largest such threshold is a positive's probability
+
+
+# ---------------------------------------------------------------- traces
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_trace_matches_oracle(seed):
+    """Deterministic run, every re-processing traced: the sample multiset
+    equals the trace oracle's in (colour, id) order, compared per (sweep,
+    target) group column by column."""
+    g = gg.sbm(400 * seed, 4, 0.08, 0.01, seed=seed, weighted=seed == 2)
+    say(f"trace parity n={g.n} m={g.m} seed={seed}")
+    G = abi.LPAGraph(g)
+    colors, nc = G.color(0)
+    order = oracle.color_order(colors, nc)
+    G.set_trace(1 << 20, 1.0)
+    labels, st = G.run(0.0, 12, DET, True, flags=abi.LPA_FLAG_TRACE)
+    X, y = G.gate_trace()
+    G.close()
+    ref = lpa_trace(g, order=order, tau=0.0, max_iters=12)
+    assert np.array_equal(labels, ref["labels"])
+    assert len(y) == len(ref["y"])
+    sw = np.rint(X[:, 4] * 12).astype(np.int64)
+    for s in np.unique(ref["sweep"]):
+        for t in (0, 1):
+            a = X[(sw == s) & (y == t)]
+            b = ref["X"][(ref["sweep"] == s) & (ref["y"] == t)]
+            assert a.shape == b.shape, (s, t)
+            for q in range(8):
+                assert np.allclose(np.sort(a[:, q]), np.sort(b[:, q]), rtol=1e-6, atol=1e-6), (s, t, q)
+
+
+def test_trace_sampling_and_capacity():
+    g = gg.sbm(20_000, 20, 0.01, 0.0005, seed=4)
+    G = abi.LPAGraph(g)
+    G.set_trace(1 << 22, 1.0)
+    _, st = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_TRACE)
+    X, y = G.gate_trace()
+    full = len(y)
+    assert full == sum(st["frontier"][1:]) and int(y.sum()) == sum(st["changed"][1:])
+    G.set_trace(1 << 22, 0.25)
+    G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_TRACE)
+    _, y25 = G.gate_trace()
+    assert 0.15 * full <= len(y25) <= 0.35 * full
+    G.set_trace(100, 1.0)
+    G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_TRACE)
+    _, y100 = G.gate_trace()
+    assert len(y100) == 100
+    G.close()
+
+
+# ---------------------------------------------------------------- gated runs
+
+@pytest.mark.parametrize("kind", ["sbm", "rmat"])
+def test_threshold_zero_is_plain_with_verification(kind):
+    """Threshold 0 processes every flagged vertex: the gated deterministic run
+    equals the plain run with LPA_FLAG_VERIFY label for label, and both equal
+    the oracle's run followed by one unpruned sweep (and, if that sweep
+    changes more than tau * n labels, by plain pruning from its state)."""
+    g = gg.sbm(1000, 10, 0.1, 0.002, seed=3) if kind == "sbm" else gg.rmat(12, 8, seed=2, weighted=True)
+    say(f"gate threshold 0 {kind} n={g.n} m={g.m}")
+    G = abi.LPAGraph(g)
+    G.gate_load(random_params(13), 0.0)
+    a, sa = G.run(0.05, 20, DET, True, flags=abi.LPA_FLAG_GATE)
+    b, sb = G.run(0.05, 20, DET, True, flags=abi.LPA_FLAG_VERIFY)
+    assert np.array_equal(a, b)
+    assert sa["changed"] == sb["changed"] and sa["verify_changed"] == sb["verify_changed"]
+    assert sa["verified"] == sb["verified"] and sum(sa["gated_out"]) == 0
+    colors, nc = G.color(0)
+    order = oracle.color_order(colors, nc)
+    r1 = oracle.lpa(g, order=order, tau=0.05, max_iters=20)
+    r2 = oracle.lpa(g, order=order, tau=0.05, max_iters=1, prune=False, init_labels=r1["labels"])
+    assert sa["verify_changed"] == int(r2["changed"][0])
+    if r2["changed"][0] <= 0.05 * g.n:
+        assert sa["verified"] and np.array_equal(a, r2["labels"])
+    G.close()
+
+
+def test_threshold_one_falls_back():
+    """Threshold 1 gates out every re-processing: the run stalls after sweep 0,
+    the verification sweep sees the stall and plain pruning finishes the job."""
+    g = gg.sbm(20_000, 20, 0.01, 0.0005, seed=5)
+    G = abi.LPAGraph(g)
+    plain, sp = G.run(0.05, 20, ASYNC, True)
+    q_plain = G.modularity(plain)
+    G.gate_load(random_params(14), 1.0)
+    lab, st = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_GATE)
+    assert sum(st["gated_out"]) > 0 and st["frontier"][1] == 0
+    assert st["verified"]
+    assert G.modularity(lab) >= q_plain - 0.01
+    G.close()
+
+
+def test_trained_gate_quality():
+    """A gate trained on traces of other SBMs keeps modularity within 0.01
+    of the plain run on a fresh SBM, verified, with fewer vertices processed
+    after sweep 0."""
+    train_graphs = [gg.sbm(100_000, 100, 32 * (1 - mu) / 999, 32 * mu / (100_000 - 1000), seed=100 + i)
+                    for i, mu in enumerate((0.1, 0.2, 0.3, 0.4))]
+    X, y = gate.collect(train_graphs, probability=0.5)
+    say(f"gate samples {len(y)} positives {int(y.sum())}")
+    info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
+    assert info["holdout_recall"] >= 0.98
+    for mu in (0.2, 0.3):
+        g = gg.sbm(200_000, 200, 32 * (1 - mu) / 999, 32 * mu / (200_000 - 1000), seed=1)
+        G = abi.LPAGraph(g)
+        plain, sp = G.run(0.05, 20, ASYNC, True)
+        qp = G.modularity(plain)
+        G.gate_load(info["params"], info["threshold"])
+        lab, sg = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_GATE)
+        qg = G.modularity(lab)
+        say(f"mu={mu} plain Q={qp:.4f} frontier={sum(sp['frontier'][1:])} gated Q={qg:.4f} "
+            f"frontier={sum(sg['frontier'][1:])} gated_out={sum(sg['gated_out'])} verified={sg['verified']}")
+        assert sg["verified"] and qg >= qp - 0.01
+        assert sum(sg["gated_out"]) > 0
+        G.close()

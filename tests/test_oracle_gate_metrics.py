@@ -123,3 +123,44 @@ def test_nmi_matches_sklearn():
         y = np.where(rng.random(2000) < 0.7, x, rng.integers(0, 30, 2000))
         assert oracle.nmi(x, y) == pytest.approx(normalized_mutual_info_score(x, y, average_method="arithmetic"),
                                                  abs=1e-12)
+
+
+# ---------------------------------------------------------------- gate trace oracle
+
+def test_trace_triangle_by_hand():
+    """K3, id order, tau < 0: sweep 0 changes vertices 0 and 2 (to label 1);
+    sweep 1 re-processes 0 and 1 (flagged by 2's change) and nothing changes."""
+    from oracle.gate_trace import lpa_trace
+    from paper_2312_08140_amd import graphgen as gg
+    g = gg.from_edges(3, [(0, 1), (1, 2), (0, 2)])
+    r = lpa_trace(g, tau=-1.0, max_iters=3)
+    assert list(r["labels"]) == [1, 1, 1]
+    assert list(r["changed"]) == [2, 0, 0]
+    l3 = np.log2(3.0)
+    expect = np.array([[l3, 0.0, 0.0, 1.0, 1 / 3, 0.5, 1.0, 0.125],    # vertex 0: tie {1:1, 2:1}, changed 0 -> 1
+                       [l3, 0.0, 0.5, 0.0, 1 / 3, 0.5, 1.0, 0.125]])   # vertex 1: tie, kept its own label 1
+    assert np.allclose(r["X"], expect, atol=1e-15)
+    assert list(r["y"]) == [0, 0] and list(r["sweep"]) == [1, 1]
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_trace_lpa_equals_c_oracle(seed):
+    """The trace oracle's label process is the C oracle's, sweep for sweep, and
+    its samples count exactly the re-processings (y = the changes among them)."""
+    import oracle
+    from oracle.gate_trace import lpa_trace
+    from paper_2312_08140_amd import graphgen as gg
+    g = gg.sbm(400, 4, 0.08, 0.01, seed=seed)
+    order = oracle.color_order(*oracle.color(g, 0))
+    ref = oracle.lpa(g, order=order, tau=0.0, max_iters=12)
+    r = lpa_trace(g, order=order, tau=0.0, max_iters=12)
+    assert np.array_equal(r["labels"], ref["labels"])
+    assert np.array_equal(r["changed"], ref["changed"][:ref["iterations"]])
+    iso = np.diff(np.asarray(g.offsets)) == 0
+    for s in range(1, r["iterations"]):
+        sel = r["sweep"] == s
+        assert sel.sum() == ref["processed"][s]          # every vertex was processed in sweep 0
+        assert r["y"][sel].sum() == ref["changed"][s]
+    X = r["X"]
+    assert np.all((X[:, 1:] >= 0) & (X[:, 1:] <= 1)) and not iso.all()
+    assert np.all(X[:, 5] >= X[:, 1]) and np.all(X[:, 5] >= X[:, 2])  # W1 bounds W1 - W2 and W(own)
