@@ -58,15 +58,20 @@ enum {
   LPA_FLAG_GATE = 4,            /* lpa_run: use the learned active-set gate (needs lpa_gate_load) */
   LPA_FLAG_NO_GRAPH = 8,        /* lpa_run: launch kernels one by one instead of replaying a captured HIP graph */
   LPA_FLAG_KERNEL_TIMING = 16,  /* lpa_run: time every kernel with HIP events (implies LPA_FLAG_NO_GRAPH) */
-  LPA_FLAG_VERIFY = 32,         /* lpa_run: after convergence, run one full unpruned sweep; if it changes more
-                                   than tau * n labels, continue with plain pruning */
+  LPA_FLAG_VERIFY = 32,         /* lpa_run: after convergence, run one verification sweep with the gate off; if
+                                   it changes more than tau * n labels, continue with plain pruning.  The sweep
+                                   processes the flagged vertices: an unflagged vertex has had no neighbour
+                                   change since its last scan, so scanning it again returns its own label
+                                   (Section 4.1.4) and the sweep equals a full unpruned one in its result */
   LPA_FLAG_TRACE = 64,          /* lpa_run: record gate training samples (features, changed-next-sweep) */
   LPA_FLAG_EXACT_MARKS = 128,   /* lpa_run, async mode: always flag neighbours one by one.  By default a sweep
                                    that follows one in which more than half of the vertices changed writes no
                                    marks and flags every vertex at its end instead (the first sweep of a fresh
                                    run counts as such); this only adds work that cannot change a label */
-  LPA_FLAG_ONE_LAUNCH = 256     /* lpa_run: replay all max_iters sweeps as one HIP graph launch (sweeps after
+  LPA_FLAG_ONE_LAUNCH = 256,    /* lpa_run: replay all max_iters sweeps as one HIP graph launch (sweeps after
                                    the stop test exit at once); batched handles always do */
+  LPA_FLAG_VERIFY_FULL = 512    /* lpa_run: the verification sweep processes every vertex (same result as the
+                                   default, at the cost of a whole sweep) */
 };
 
 #define LPA_MAX_SWEEPS_RECORDED 64
@@ -88,7 +93,8 @@ typedef struct {
   double total_ms;                                /* device time from run start to final labels */
   double setup_ms;                                /* one-off work done by this call (colouring, capture) */
   /* LPA_FLAG_KERNEL_TIMING: summed HIP-event time and launch count per kernel kind:
-     0 compaction, 1..6 degree bins 0..5, 7..9 hub plan/scan/finish, 10 end of sweep */
+     0 compaction, 1..6 degree bins 0..5, 7..9 hub plan/scan/finish, 10 end of sweep,
+     11 hub partition merge, 12 other, 13 gate decisions */
   double kernel_ms[LPA_NUM_TIMED_KERNELS];
   int64_t kernel_launches[LPA_NUM_TIMED_KERNELS];
   /* run totals per degree bin (bin 6 = hubs): vertices processed, stored entries
@@ -100,6 +106,7 @@ typedef struct {
   int64_t compact_listed, compact_taken;
   int32_t weight_bytes;
   int32_t reserved;
+  int64_t verify_edges_scanned;  /* stored entries scanned by the verification sweep(s) */
 } lpa_stats;
 
 /*
@@ -215,8 +222,9 @@ int lpa_batch_stats(const lpa_graph *g, int32_t *iterations, int32_t *converged)
  * label weights among the neighbours and K the weighted degree.  Parameters
  * are 1377 FP32 values, W1[32][8], b1[32], W2[32][32], b2[32], W3[32], b3
  * (row-major); the GPU evaluates their bf16 rounding (to nearest, ties to
- * even) with FP32 sums.  A gated run (LPA_FLAG_GATE) always ends with a full
- * unpruned verification sweep; if that sweep changes more than
+ * even) with FP32 sums.  The decisions of a sweep are taken at its start for
+ * the vertices flagged then.  A gated run (LPA_FLAG_GATE) always ends with a
+ * verification sweep (LPA_FLAG_VERIFY); if that sweep changes more than
  * tolerance * n labels the run continues with plain pruning.
  */
 

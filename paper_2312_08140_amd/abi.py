@@ -41,6 +41,7 @@ LPA_FLAG_VERIFY = 32
 LPA_FLAG_TRACE = 64
 LPA_FLAG_EXACT_MARKS = 128
 LPA_FLAG_ONE_LAUNCH = 256
+LPA_FLAG_VERIFY_FULL = 512
 
 GATE_PARAMS = 1377
 GATE_FEATURES = 8
@@ -48,7 +49,7 @@ GATE_FEATURES = 8
 MAX_SWEEPS_RECORDED = 64
 NUM_TIMED_KERNELS = 16
 KERNEL_NAMES = ["compact", "bin0", "bin1", "bin2", "bin3", "bin4", "bin5", "hub_plan", "hub_chunk", "hub_finish",
-                "end_sweep", "hub_part", "other", "k13", "k14", "k15"]
+                "end_sweep", "hub_part", "other", "gate_pass", "k14", "k15"]
 
 
 class lpa_stats(ctypes.Structure):
@@ -76,6 +77,7 @@ class lpa_stats(ctypes.Structure):
         ("compact_taken", ctypes.c_int64),
         ("weight_bytes", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("verify_edges_scanned", ctypes.c_int64),
     ]
 
     def to_dict(self) -> dict:
@@ -92,6 +94,7 @@ class lpa_stats(ctypes.Structure):
             bin_vertices=list(self.bin_vertices[:7]), bin_edges=list(self.bin_edges[:7]),
             bin_changed=list(self.bin_changed[:7]), bin_marks=list(self.bin_marks[:7]),
             compact_listed=self.compact_listed, compact_taken=self.compact_taken, weight_bytes=self.weight_bytes,
+            verify_edges_scanned=self.verify_edges_scanned,
         )
 
 

@@ -89,6 +89,18 @@ constexpr int MAX_REC = 64;
 
 // Device-resident control block of a handle.  Accumulators are reset by the
 // run prologue and at the end of every sweep.
+// Sweep counters are added per workgroup into one of NSHARD copies (a
+// 64-byte line per copy and slot) rather than into one address: thousands of
+// workgroups adding to a single counter serialise on it.  Slots 0..NBINS-1
+// belong to the scan kernels of a bin (changed, scanned entries, vertices,
+// marks), slot NBINS to the compaction (processed, gated, listed, unused).
+// k_end_sweep folds and clears them.
+constexpr int NSHARD = 64;
+struct alignas(64) Shard {
+  u64 c[4];
+  u64 pad[4];
+};
+
 struct Ctl {
   int32_t done;        // stop test held or the sweep cap was reached
   int32_t sweep;       // index of the sweep in progress
@@ -96,7 +108,7 @@ struct Ctl {
   int32_t converged;
   int32_t error;       // nonzero: a table overflowed (never expected)
   int32_t max_iters;
-  int32_t verify_phase;  // 1 while a verification sweep runs
+  int32_t verify_phase;  // while a verification sweep runs: 1 over the flagged vertices, 2 over all
   int32_t gate_on;       // 1: flagged vertices pass the gate before processing
   int32_t verified;      // last verification sweep changed <= tau * n labels
   // Dense sweeps (asynchronous mode): when most vertices change, every
@@ -114,10 +126,11 @@ struct Ctl {
   u64 hub_chunks, hub_parts;               // hub work items of the current step
   u64 st_changed[MAX_REC], st_processed[MAX_REC], st_scanned[MAX_REC], st_gated[MAX_REC];
   u64 t_start, t_sweep[MAX_REC];
-  u64 verify_changed, total_changed;
+  u64 verify_changed, total_changed, verify_scanned;
   // run totals per bin (byte accounting of the kernels)
   u64 bin_vertices[NBINS], bin_edges[NBINS], bin_changed[NBINS], bin_marks[NBINS];
   u64 compact_listed, compact_taken;
+  Shard shard[NSHARD][NBINS + 1];
 };
 
 // ---------------------------------------------------------------- gate

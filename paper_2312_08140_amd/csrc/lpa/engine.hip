@@ -39,7 +39,8 @@ enum TimedKind {
   TK_HUB_FINISH = 9,
   TK_END_SWEEP = 10,
   TK_HUB_PART = 11,
-  TK_OTHER = 12
+  TK_OTHER = 12,
+  TK_GATE = 13
 };
 
 }  // namespace
@@ -114,9 +115,11 @@ struct lpa_graph {
   // learned gate
   bool feat_on = false;           // the sweeps being emitted write gate features
   FeatArgs cur_feat{};
-  uint16_t *gate_w = nullptr;     // bf16 parameters
+  float *gate_f = nullptr;        // parameters rounded to bf16, held as fp32
   float gate_z = 0.0f;            // logit threshold
   bool gate_loaded = false;
+  bool gate_active = false;       // the sweeps being emitted apply the gate
+  uint8_t *gskip = nullptr;       // per vertex: gated out in the current sweep
   float *feat = nullptr;          // [n][NSTORED]
   int16_t *lastp = nullptr;
   float *tx = nullptr;            // trace
@@ -584,8 +587,7 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
   ca.prune = prune;
   ca.gid = g->ngraphs ? g->bgid : nullptr;
   ca.gdone = g->ngraphs ? g->bgdone : nullptr;
-  ca.gate = g->feat_on && g->gate_loaded ? g->gate_w : nullptr;
-  ca.gate_z = g->gate_z;
+  ca.gskip = g->gate_active ? g->gskip : nullptr;
   ca.f = g->cur_feat;
   tk_begin(g, st);
   launch_compact(ca, grid_cap(len, 2048, 4096), st);
@@ -623,6 +625,11 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
 }
 
 void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune) {
+  if (g->gate_active) {
+    tk_begin(g, st);
+    launch_gate_pass(g->ctl, g->gate_f, g->gate_z, g->cur_feat, g->F, g->gskip, g->n, g->cu_count, st);
+    tk_end(g, st, TK_GATE);
+  }
   if (mode == LPA_MODE_DETERMINISTIC) {
     for (int c = 0; c < g->ncol; ++c)
       emit_step(g, st, g->dlist, &g->dstart[(size_t)c * NBINS], g->fcount + (size_t)c * NBINS, prune,
@@ -644,7 +651,7 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune) {
 // once after the stop test holds), captured once per (mode, prune, sweeps).
 hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps) {
   // captured kernels embed the feature arguments (trace switch, sweep cap)
-  const int fcode = g->feat_on ? 1 + 2 * g->cur_feat.trace + 4 * g->cur_feat.max_iters : 0;
+  const int fcode = g->feat_on ? 1 + 2 * g->cur_feat.trace + 4 * g->gate_active + 8 * g->cur_feat.max_iters : 0;
   auto key = std::make_tuple(mode, prune, sweeps, fcode);
   auto it = g->graphs.find(key);
   if (it != g->graphs.end()) return it->second;
@@ -896,16 +903,17 @@ int lpa_batch_stats(const lpa_graph *gc, int32_t *iterations, int32_t *converged
 int lpa_gate_load(lpa_graph *g, const float *params, float threshold) {
   return run_guarded(g, [&]() -> int {
     if (!params || !(threshold >= 0.0f) || !(threshold <= 1.0f)) return LPA_ERR_INVALID_ARG;
-    uint16_t bf[GATE_PARAMS];
+    float bf[GATE_PARAMS];
     for (int k = 0; k < GATE_PARAMS; ++k) {
       if (!std::isfinite(params[k])) return LPA_ERR_INVALID_ARG;
       uint32_t u;
       std::memcpy(&u, &params[k], 4);
       u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
-      bf[k] = (uint16_t)(u >> 16);
+      u &= 0xFFFF0000u;
+      std::memcpy(&bf[k], &u, 4);
     }
-    if (!g->gate_w) g->gate_w = dalloc_n<uint16_t>(g, GATE_PARAMS);
-    HIP_OK(hipMemcpy(g->gate_w, bf, sizeof(bf), hipMemcpyHostToDevice));
+    if (!g->gate_f) g->gate_f = dalloc_n<float>(g, GATE_PARAMS);
+    HIP_OK(hipMemcpy(g->gate_f, bf, sizeof(bf), hipMemcpyHostToDevice));
     // p >= threshold  <=>  logit >= log(threshold / (1 - threshold))
     if (threshold <= 0.0f) g->gate_z = -INFINITY;
     else if (threshold >= 1.0f) g->gate_z = INFINITY;
@@ -1015,7 +1023,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       !(tolerance == tolerance))
     return LPA_ERR_INVALID_ARG;
   if ((flags & LPA_FLAG_GATE) && !g->gate_loaded) return LPA_ERR_NO_GATE;
-  if ((flags & (LPA_FLAG_GATE | LPA_FLAG_VERIFY)) && g->ngraphs) return LPA_ERR_INVALID_ARG;
+  if ((flags & (LPA_FLAG_GATE | LPA_FLAG_VERIFY | LPA_FLAG_VERIFY_FULL)) && g->ngraphs) return LPA_ERR_INVALID_ARG;
   return run_guarded(g, [&]() -> int {
     Events ev;
     hipEvent_t e0 = ev.e[0], e1 = ev.e[1], t0 = ev.e[2], t1 = ev.e[3];
@@ -1046,11 +1054,15 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
                         g->stream);
     // A batched handle replays the whole run as one graph launch; otherwise
     // one sweep per launch, with the stop test polled one sweep behind.
-    const bool one_launch = use_graph && (g->ngraphs > 0 || (flags & LPA_FLAG_ONE_LAUNCH));
+    // (a run that ends with a verification sweep needs the host between sweeps)
+    const bool one_launch = use_graph && (g->ngraphs > 0 || (flags & LPA_FLAG_ONE_LAUNCH)) &&
+                            !(flags & (LPA_FLAG_GATE | LPA_FLAG_VERIFY | LPA_FLAG_VERIFY_FULL));
     // gate features: written while the gate is used or training traces are recorded
     const bool gate = flags & LPA_FLAG_GATE;
     const bool trace = flags & LPA_FLAG_TRACE;
     g->feat_on = gate || trace;
+    g->gate_active = gate;
+    if (gate && !g->gskip) g->gskip = dalloc_n<uint8_t>(g, g->n);
     if (g->feat_on) {
       if (!g->feat) {
         g->feat = dalloc_n<float>(g, g->n * NSTORED);
@@ -1101,9 +1113,9 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       }
     };
     int verified = -1;
-    if ((flags & (LPA_FLAG_VERIFY | LPA_FLAG_GATE)) && max_iters > 0 && !one_launch) {
+    if ((flags & (LPA_FLAG_VERIFY | LPA_FLAG_VERIFY_FULL | LPA_FLAG_GATE)) && max_iters > 0 && !one_launch) {
       for (int attempt = 0; attempt < 2; ++attempt) {
-        launch_set_phase(g->ctl, 1, 0, 0, g->host_done_dev, g->stream);
+        launch_set_phase(g->ctl, (flags & LPA_FLAG_VERIFY_FULL) ? 2 : 1, 0, 0, g->host_done_dev, g->stream);
         if (exec) HIP_OK(hipGraphLaunch(exec, g->stream));
         else emit_sweep(g, g->stream, mode, prune);
         int32_t vflag = 0;
@@ -1119,6 +1131,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     HIP_OK(hipStreamSynchronize(g->stream));
     g->timing = false;
     g->feat_on = false;
+    g->gate_active = false;
     Ctl h;
     HIP_OK(hipMemcpy(&h, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
     float run_ms = 0;
@@ -1145,6 +1158,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       }
       stats->total_changed = (int64_t)h.total_changed;
       stats->verify_changed = (int64_t)h.verify_changed;
+      stats->verify_edges_scanned = (int64_t)h.verify_scanned;
       stats->total_ms = run_ms;
       stats->setup_ms = setup_ms;
       for (int b = 0; b < NBINS; ++b) {

@@ -35,6 +35,8 @@ __global__ void k_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t
 __global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount,
                             int nfc, int32_t *host_done, int dense_enabled, int dense_first, int gate_on) {
   for (int k = threadIdx.x; k < nfc; k += blockDim.x) fcount[k] = 0;
+  for (int k = threadIdx.x; k < NSHARD * (NBINS + 1) * 4; k += blockDim.x)
+    ctl->shard[k / ((NBINS + 1) * 4)][(k >> 2) % (NBINS + 1)].c[k & 3] = 0;
   if (threadIdx.x == 0) {
     ctl->dense_enabled = dense_enabled;
     ctl->dense_cur = dense_enabled && dense_first;
@@ -55,7 +57,7 @@ __global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int6
     ctl->n = n;
     ctl->changed = ctl->processed = ctl->scanned = ctl->gated = 0;
     ctl->hub_chunks = ctl->hub_parts = 0;
-    ctl->verify_changed = ctl->total_changed = 0;
+    ctl->verify_changed = ctl->total_changed = ctl->verify_scanned = 0;
     for (int k = 0; k < MAX_REC; ++k)
       ctl->st_changed[k] = ctl->st_processed[k] = ctl->st_scanned[k] = ctl->st_gated[k] = ctl->t_sweep[k] = 0;
     for (int k = 0; k < NBINS; ++k)
@@ -69,16 +71,51 @@ __global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int6
   }
 }
 
+// Folds the sweep's counter shards into the sweep totals (ctl->changed,
+// processed, scanned, gated) and the run totals per bin, clearing them.
+__device__ void fold_shards(Ctl *ctl) {
+  __shared__ u64 red[NBINS + 1][4];
+  for (int k = threadIdx.x; k < (NBINS + 1) * 4; k += blockDim.x) red[k >> 2][k & 3] = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < NSHARD * (NBINS + 1) * 4; k += blockDim.x) {
+    const int q = k & 3, slot = (k >> 2) % (NBINS + 1), sh = k / ((NBINS + 1) * 4);
+    const u64 x = ctl->shard[sh][slot].c[q];
+    if (x) {
+      atomicAdd(&red[slot][q], x);
+      ctl->shard[sh][slot].c[q] = 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 changed = 0, scanned = 0;
+    for (int b = 0; b < NBINS; ++b) {
+      changed += red[b][0];
+      scanned += red[b][1];
+      ctl->bin_changed[b] += red[b][0];
+      ctl->bin_edges[b] += red[b][1];
+      ctl->bin_vertices[b] += red[b][2];
+      ctl->bin_marks[b] += red[b][3];
+    }
+    ctl->changed = changed;
+    ctl->scanned = scanned;
+    ctl->processed = red[NBINS][0];
+    ctl->gated = red[NBINS][1];
+    ctl->compact_taken += red[NBINS][0];
+    ctl->compact_listed += red[NBINS][2];
+  }
+}
+
 __global__ void k_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_done) {
   if (__atomic_load_n(&ctl->done, __ATOMIC_RELAXED)) return;
   for (int k = threadIdx.x; k < nfc; k += blockDim.x) fcount[k] = 0;
-  __syncthreads();
+  fold_shards(ctl);
   if (threadIdx.x != 0) return;
   const int s = ctl->sweep;
   const u64 dn = ctl->changed;
   if (ctl->verify_phase) {
     // a verification sweep: one full sweep, judged by the same stop test
     ctl->verify_changed += dn;
+    ctl->verify_scanned += ctl->scanned;
     ctl->total_changed += dn;
     ctl->verified = (double)dn / (double)(ctl->n > 0 ? ctl->n : 1) <= ctl->tau;
     ctl->sweep = s + 1;
@@ -230,20 +267,58 @@ __device__ __forceinline__ float gate_logit(const float *P, const float *x) {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// Gate decisions of a sweep, taken once at its start for every vertex that is
+// flagged then and has been processed before: skip[v] = 1 when the network's
+// logit is below z (the vertex keeps its flag and waits).  Vertices flagged
+// later in the sweep are not gated in it.
+// The same network with its parameters (fp32 values of their bf16 rounding)
+// read at wave-uniform addresses, so they arrive through scalar loads and
+// feed the FMAs as scalar operands; same order of operations as gate_logit.
+__device__ __forceinline__ float gate_logit_uniform(const float *__restrict__ P, const float *x) {
+  float h1[32];
+#pragma unroll
+  for (int o = 0; o < 32; ++o) {
+    float acc = P[256 + o];
+#pragma unroll
+    for (int q = 0; q < NFEAT; ++q) acc = fmaf(P[o * 8 + q], x[q], acc);
+    h1[o] = acc > 0.0f ? acc : 0.0f;
+  }
+  float z = P[1376];
+#pragma unroll 2
+  for (int o = 0; o < 32; ++o) {
+    float acc = P[1312 + o];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) acc = fmaf(P[288 + o * 32 + q], h1[q], acc);
+    z = fmaf(P[1344 + o], acc > 0.0f ? acc : 0.0f, z);
+  }
+  return z;
+}
+
+__global__ __launch_bounds__(256) void k_gate_pass(const Ctl *ctl, const float *__restrict__ gate, float z, FeatArgs f,
+                                                   const uint8_t *F, uint8_t *skip, int64_t n) {
+  if (__atomic_load_n(&ctl->done, __ATOMIC_RELAXED)) return;
+  const int sweep = ctl->sweep;
+  if (!ctl->gate_on || ctl->verify_phase || sweep < 1) return;
+  for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v - threadIdx.x < n; v += (int64_t)gridDim.x * 256) {
+    const int lp = v < n && F[v] ? (int)f.lastp[v] : -1;
+    float x[NFEAT] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (lp >= 0) decision_features(f.feat + v * NSTORED, lp, sweep, f.max_iters, x);
+    float logit = 0.0f;
+    if (__ballot(lp >= 0)) logit = gate_logit_uniform(gate, x);  // whole waves skip the network
+    if (v < n) skip[v] = lp >= 0 && logit < z ? 1 : 0;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   __shared__ int lcount[NBINS];
   __shared__ int lbase[NBINS];
   __shared__ int s_taken[4], s_gated[4];
-  __shared__ float gp[GATE_PARAMS];
-  // a verification sweep takes every vertex; the gate acts from sweep 1 on
-  const bool take_all = a.ctl->verify_phase != 0;
+  // a full verification sweep takes every vertex (a pruned one, the flagged
+  // vertices with the gate off); the gate acts from sweep 1 on
+  const bool take_all = a.ctl->verify_phase == 2;
   const int sweep = a.ctl->sweep;
-  const bool gate = a.gate && a.ctl->gate_on && !take_all && sweep >= 1;
-  if (gate) {
-    for (int k = threadIdx.x; k < GATE_PARAMS; k += 256) gp[k] = bf16_to_f32(a.gate[k]);
-    __syncthreads();
-  }
+  const bool gate = a.gskip && a.ctl->gate_on && !a.ctl->verify_phase && sweep >= 1;
   int taken_total = 0, gated_total = 0;
   for (int64_t tile = (int64_t)blockIdx.x * 256 * CU; tile < a.len; tile += (int64_t)gridDim.x * 256 * CU) {
     if (threadIdx.x < NBINS) lcount[threadIdx.x] = 0;
@@ -263,17 +338,12 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
         if (f[r] && a.gdone[a.gid[v[r]]]) f[r] = 0;
     }
     if (gate) {  // a flagged vertex the network expects to keep its label stays flagged, unprocessed
-      for (int r = 0; r < CU; ++r) {
-        if (!f[r]) continue;
-        const int lp = a.f.lastp[v[r]];
-        if (lp < 0) continue;
-        float x[NFEAT];
-        decision_features(a.f.feat + (int64_t)v[r] * NSTORED, lp, sweep, a.f.max_iters, x);
-        if (gate_logit(gp, x) < a.gate_z) {
+#pragma unroll
+      for (int r = 0; r < CU; ++r)
+        if (f[r] && a.gskip[v[r]]) {
           f[r] = 0;
           ++gated_total;
         }
-      }
     }
     __syncthreads();
     int bin[CU], slot[CU];
@@ -313,15 +383,13 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
   if (threadIdx.x == 0) {
     const int t = s_taken[0] + s_taken[1] + s_taken[2] + s_taken[3];
     const int gt = s_gated[0] + s_gated[1] + s_gated[2] + s_gated[3];
-    if (t) {
-      atomicAdd((u64 *)&a.ctl->processed, (u64)t);
-      atomicAdd((u64 *)&a.ctl->compact_taken, (u64)t);
-    }
-    if (gt) atomicAdd((u64 *)&a.ctl->gated, (u64)gt);
+    Shard &sh = a.ctl->shard[blockIdx.x & (NSHARD - 1)][NBINS];
+    if (t) atomicAdd(&sh.c[0], (u64)t);
+    if (gt) atomicAdd(&sh.c[1], (u64)gt);
     int64_t listed = 0;
     for (int64_t tile = (int64_t)blockIdx.x * 256 * CU; tile < a.len; tile += (int64_t)gridDim.x * 256 * CU)
       listed += min((int64_t)256 * CU, a.len - tile);
-    if (listed) atomicAdd((u64 *)&a.ctl->compact_listed, (u64)listed);
+    if (listed) atomicAdd(&sh.c[2], (u64)listed);
   }
 }
 
@@ -424,7 +492,11 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
       overflow |=
           scan_row_strided<GROUP, U, BITS, TS, WK>(a.idx, a.w, a.C, A.b + (int64_t)GROUP * U, A.e, A.v, lane, T);
     wave_lds_sync();
-    const u64 best = group_max<GROUP>(table_best<GROUP, SLOTS, TS>(T, lane));
+    TabStats ts{0u, 0u, 0};
+    u64 lbest;
+    if constexpr (FEAT) lbest = table_best_stats<GROUP, SLOTS, TS>(T, lane, ts);
+    else lbest = table_best<GROUP, SLOTS, TS>(T, lane);
+    const u64 best = group_max<GROUP>(lbest);
     bool changed = false;
     if (best != 0) {
       const int32_t cs = (int32_t)key_label(best);
@@ -442,7 +514,7 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
       }
     }
     if constexpr (FEAT) {
-      const TabStats t = group_stats<GROUP>(table_stats<GROUP, SLOTS, TS>(T, lane));
+      const TabStats t = group_stats<GROUP>(ts);
       if (lane == 0)
         write_features(a.f, A.v, sweep, A.e - A.b, t, table_lookup<BITS, TS>(T, (uint32_t)A.cur), changed);
     }
@@ -490,7 +562,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
     if (!one_pass)
       overflow |= scan_row<BLOCK, U, BITS, WK>(a.idx, a.w, a.C, A.b + (int64_t)BLOCK * U, A.e, A.v, threadIdx.x, T);
     __syncthreads();
-    const u64 best = block_max<BLOCK>(table_best<BLOCK, SLOTS>(T, threadIdx.x), red);
+    TabStats ts{0u, 0u, 0};
+    u64 lbest;
+    if constexpr (FEAT) lbest = table_best_stats<BLOCK, SLOTS>(T, threadIdx.x, ts);
+    else lbest = table_best<BLOCK, SLOTS>(T, threadIdx.x);
+    const u64 best = block_max<BLOCK>(lbest, red);
     bool changed = false;
     if (best != 0) {
       const int32_t cs = (int32_t)key_label(best);
@@ -508,7 +584,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
       }
     }
     if constexpr (FEAT) {
-      const TabStats t = group_stats<64>(table_stats<BLOCK, SLOTS>(T, threadIdx.x));
+      const TabStats t = group_stats<64>(ts);
       if ((threadIdx.x & 63) == 0) tred[threadIdx.x >> 6] = t;
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -561,6 +637,13 @@ void launch_scan_bin(int bin, int wk, bool feat, int blocks, hipStream_t st, con
     else if (wk == W_U8) launch_bin_wk<W_U8, false>(bin, dim3(blocks), st, a);
     else launch_bin_wk<W_U32, false>(bin, dim3(blocks), st, a);
   }
+}
+
+void launch_gate_pass(const Ctl *ctl, const float *gate, float z, const FeatArgs &f, const uint8_t *F,
+                      uint8_t *skip, int64_t n, int cu_count, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, (int64_t)cu_count * 16));
+  hipLaunchKernelGGL(k_gate_pass, dim3((unsigned)blocks), dim3(256), 0, st, ctl, gate, z, f, F, skip, n);
 }
 
 void launch_compact(const CompactArgs &a, int blocks, hipStream_t st) {

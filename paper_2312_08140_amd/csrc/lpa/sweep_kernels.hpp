@@ -19,12 +19,13 @@ struct CompactArgs {
   int prune;
   const int32_t *gid;    // batched runs: graph of every vertex (NULL otherwise)
   const int32_t *gdone;  // batched runs: 1 for a graph that has stopped
-  const uint16_t *gate;  // bf16 gate parameters (NULL: no gate)
-  float gate_z;          // process a vertex when the network's logit >= gate_z
+  const uint8_t *gskip;  // gate decisions of the sweep (k_gate_pass; NULL: no gate)
   FeatArgs f;
 };
 
 void launch_compact(const CompactArgs &a, int blocks, hipStream_t st);
+void launch_gate_pass(const Ctl *ctl, const float *gate, float z, const FeatArgs &f, const uint8_t *F,
+                      uint8_t *skip, int64_t n, int cu_count, hipStream_t st);
 void launch_scan_bin(int bin, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a);
 void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, hipStream_t st);
 void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);

@@ -151,6 +151,30 @@ __device__ __forceinline__ TabStats table_stats(const u64 *T, int lane) {
   return r;
 }
 
+// table_best and table_stats in one pass over the slots.
+template <int G, int SLOTS, int STRIDE = 1>
+__device__ __forceinline__ u64 table_best_stats(const u64 *T, int lane, TabStats &r) {
+  u64 best = 0;
+  r = TabStats{0u, 0u, 0};
+#pragma unroll 4
+  for (int s = lane; s < SLOTS; s += G) {
+    const u64 x = T[s * STRIDE];
+    if (x != EMPTY) {
+      const u64 kk = entry_key(x);
+      best = kk > best ? kk : best;
+      const uint32_t w = (uint32_t)x;
+      ++r.nd;
+      if (w > r.w1) {
+        r.w2 = r.w1;
+        r.w1 = w;
+      } else if (w > r.w2) {
+        r.w2 = w;
+      }
+    }
+  }
+  return best;
+}
+
 __device__ __forceinline__ TabStats merge_stats(TabStats a, TabStats b) {
   TabStats r;
   r.w1 = a.w1 > b.w1 ? a.w1 : b.w1;
@@ -231,8 +255,8 @@ __device__ __forceinline__ u64 block_max(u64 x, u64 *red) {
   return x;
 }
 
-// Block-wide sums of the per-thread counters, then one atomic per counter
-// and block: sweep totals (changed, scanned) and run totals of the bin.
+// Block-wide sums of the per-thread counters (changed, scanned, vertices,
+// marks), added to the block's shard of the bin's counters.
 template <int BLOCK>
 __device__ __forceinline__ void block_accum(u64 changed, u64 scanned, u64 vertices, u64 marks, int err, Ctl *ctl,
                                             int bin) {
@@ -255,23 +279,13 @@ __device__ __forceinline__ void block_accum(u64 changed, u64 scanned, u64 vertic
     s_err[wv] = err;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    u64 t[4] = {0, 0, 0, 0};
+  if (threadIdx.x < 4) {
+    u64 t = 0;
+    for (int k = 0; k < BLOCK / 64; ++k) t += s_v[threadIdx.x][k];
+    if (t) atomicAdd(&ctl->shard[blockIdx.x & (NSHARD - 1)][bin].c[threadIdx.x], t);
+  } else if (threadIdx.x == 4) {
     int te = 0;
-    for (int k = 0; k < BLOCK / 64; ++k) {
-      for (int q = 0; q < 4; ++q) t[q] += s_v[q][k];
-      te |= s_err[k];
-    }
-    if (t[0]) {
-      atomicAdd((u64 *)&ctl->changed, t[0]);
-      atomicAdd((u64 *)&ctl->bin_changed[bin], t[0]);
-    }
-    if (t[1]) {
-      atomicAdd((u64 *)&ctl->scanned, t[1]);
-      atomicAdd((u64 *)&ctl->bin_edges[bin], t[1]);
-    }
-    if (t[2]) atomicAdd((u64 *)&ctl->bin_vertices[bin], t[2]);
-    if (t[3]) atomicAdd((u64 *)&ctl->bin_marks[bin], t[3]);
+    for (int k = 0; k < BLOCK / 64; ++k) te |= s_err[k];
     if (te) atomicOr(&ctl->error, te);
   }
 }

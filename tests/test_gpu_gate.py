@@ -216,6 +216,25 @@ def test_threshold_zero_is_plain_with_verification(kind):
     G.close()
 
 
+@pytest.mark.parametrize("kind", ["sbm", "rmat"])
+def test_pruned_verification_equals_full(kind):
+    """The verification sweep over the flagged vertices gives the labels and
+    dN of the sweep over every vertex (deterministic mode, from the state a
+    gated run leaves, with many vertices still flagged)."""
+    g = gg.sbm(2000, 20, 0.05, 0.002, seed=6) if kind == "sbm" else gg.rmat(12, 8, seed=3, weighted=True)
+    G = abi.LPAGraph(g)
+    G.gate_load(random_params(15), 0.5)
+    a, sa = G.run(0.05, 20, DET, True, flags=abi.LPA_FLAG_GATE)
+    b, sb = G.run(0.05, 20, DET, True, flags=abi.LPA_FLAG_GATE | abi.LPA_FLAG_VERIFY_FULL)
+    say(f"verify {kind}: gated_out {sum(sa['gated_out'])} verify_changed {sa['verify_changed']} "
+        f"edges {sa['verify_edges_scanned']} vs full {sb['verify_edges_scanned']}")
+    assert np.array_equal(a, b)
+    assert sa["changed"] == sb["changed"] and sa["verify_changed"] == sb["verify_changed"]
+    assert sa["verified"] == sb["verified"]
+    assert sb["verify_edges_scanned"] >= sa["verify_edges_scanned"]
+    G.close()
+
+
 def test_threshold_one_falls_back():
     """Threshold 1 gates out every re-processing: the run stalls after sweep 0,
     the verification sweep sees the stall and plain pruning finishes the job."""
