@@ -76,6 +76,98 @@ def kernel_bytes(st):
     return out
 
 
+def _sbm1m(mu, seed, n=1_000_000, k=1000, d=32.0):
+    from paper_2312_08140_amd import graphgen
+    return graphgen.sbm(n, k, d * (1 - mu) / (n // k - 1), d * mu / (n - n // k), seed=seed)
+
+
+def _median_runs(G, tau, max_iters, flags, out, k):
+    from paper_2312_08140_amd import abi
+    G.run(tau, max_iters, abi.LPA_MODE_ASYNC, True, flags=flags, labels_out=out)
+    ms, st = [], None
+    for _ in range(k):
+        _, st = G.run(tau, max_iters, abi.LPA_MODE_ASYNC, True, flags=flags, labels_out=out)
+        ms.append(st["total_ms"])
+    return float(np.median(ms)), st
+
+
+def _compare(G, gate_info, tau, max_iters, out, truth=None, plain=None):
+    """Plain vs gated time-to-converge (median of 5 runs each) on one handle."""
+    import torch
+    from paper_2312_08140_amd import abi
+    if plain is None:
+        p_ms, sp = _median_runs(G, tau, max_iters, 0, out, 5)
+        lp = out.clone()
+        qp = G.modularity(lp)
+    else:
+        p_ms, sp, lp, qp = plain
+    G.gate_load(gate_info["params"], gate_info["threshold"])
+    g_ms, sg = _median_runs(G, tau, max_iters, abi.LPA_FLAG_GATE, out, 5)
+    lg = out.clone()
+    qg = G.modularity(lg)
+    r = {"plain_ms": round(p_ms, 3), "gated_ms": round(g_ms, 3), "speedup": round(p_ms / g_ms, 3),
+         "q_plain": round(qp, 6), "q_gated": round(qg, 6), "q_loss": round(qp - qg, 6),
+         "nmi_plain_vs_gated": round(abi.nmi(lp, lg), 6), "verified": bool(sg["verified"]),
+         "sweeps_plain": sp["iterations"], "sweeps_gated": sg["iterations"],
+         "processed_plain": int(sum(sp["frontier"])),
+         "processed_gated": int(sum(sg["frontier"])), "gated_out": int(sum(sg["gated_out"])),
+         "verify_changed": int(sg["verify_changed"]),
+         "entries_plain": int(sum(sp["edges_scanned"])),
+         "entries_gated": int(sum(sg["edges_scanned"]) + sg["verify_edges_scanned"])}
+    if truth is not None:
+        t = torch.from_numpy(truth.astype(np.int32)).cuda()
+        r["nmi_truth_plain"] = round(abi.nmi(lp, t), 6)
+        r["nmi_truth_gated"] = round(abi.nmi(lg, t), 6)
+    return r
+
+
+def gate_comparison(args, G, g, runs, q_async, out):
+    """Learned active-set gate vs plain pruning: SBM-1M (gate trained on traces
+    of other SBM-1M graphs) and the R-MAT graph of the headline (gate trained
+    on traces of smaller R-MAT graphs).  Training is outside every timed run."""
+    import torch
+    from paper_2312_08140_amd import abi, gate, graphgen
+    res = {}
+    t = time.time()
+    train = [_sbm1m(mu, 100 + i) for i, mu in enumerate((0.1, 0.2, 0.3, 0.4) * 2)]
+    X, y = gate.collect(train, probability=0.25)
+    del train
+    info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
+    res["sbm_gate"] = {"train_graphs": 8, "samples": int(len(y)), "positive_share": round(float(y.mean()), 4),
+                       "threshold": round(info["threshold"], 6), "holdout_recall": round(info["holdout_recall"], 4),
+                       "holdout_skip": round(info["holdout_skip"], 4),
+                       "loss": [round(float(v), 5) for v in info["losses"]], "seconds": round(time.time() - t, 2)}
+    log(f"sbm gate: {res['sbm_gate']}")
+    rows = []
+    for mu in (0.1, 0.2, 0.3, 0.4):
+        s = _sbm1m(mu, 1)
+        H = abi.LPAGraph(s)
+        o = torch.empty(s.n, dtype=torch.int32, device="cuda:0")
+        if not args.no_tune:
+            H.autotune(args.tau, args.max_iters, abi.LPA_MODE_ASYNC)
+        r = _compare(H, info, args.tau, args.max_iters, o, truth=graphgen.sbm_truth(s.n, 1000))
+        r["mu"] = mu
+        rows.append(r)
+        log(f"sbm1m mu={mu}: {r}")
+        H.close()
+    res["sbm1m"] = rows
+    t = time.time()
+    train = [graphgen.rmat(20, args.edge_factor, seed=100 + i, weighted=True) for i in range(4)]
+    X, y = gate.collect(train, probability=0.25)
+    del train
+    info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
+    res["rmat_gate"] = {"train_graphs": "R-MAT scale 20, seeds 100-103", "samples": int(len(y)),
+                        "threshold": round(info["threshold"], 6), "holdout_recall": round(info["holdout_recall"], 4),
+                        "holdout_skip": round(info["holdout_skip"], 4), "seconds": round(time.time() - t, 2)}
+    p_ms = float(np.median([r["total_ms"] for r in runs]))
+    lp = out.clone()
+    G.run(args.tau, args.max_iters, abi.LPA_MODE_ASYNC, True, labels_out=lp)
+    r = _compare(G, info, args.tau, args.max_iters, out, plain=(p_ms, runs[-1], lp, G.modularity(lp)))
+    res[f"rmat{args.scale}"] = r
+    log(f"rmat{args.scale} gated: {r}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +183,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default schedule and kernel shapes")
+    ap.add_argument("--no-gate", action="store_true", help="skip the plain-vs-gated comparison")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -116,6 +210,12 @@ def main():
     log(f"uploaded in {time.time() - t:.1f}s")
     A = abi.LPA_MODE_ASYNC
     out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    tuned = None
+    if not args.no_tune:
+        t = time.time()
+        variants, bin_ms, sched = G.autotune(args.tau, args.max_iters, A)
+        tuned = {"variants": [int(v) for v in variants], "schedule": list(sched), "seconds": round(time.time() - t, 2)}
+        log(f"autotune: {tuned}")
 
     for _ in range(args.warmup):
         G.run(args.tau, args.max_iters, A, True, labels_out=out)
@@ -178,6 +278,10 @@ def main():
                    sweep0_edges_per_s=round(g.m / (sd2["ms"][0] * 1e-3), 1) if sd2["iterations"] else None)
         log(f"det: {det} ({time.time() - t:.1f}s)")
 
+    gated = None
+    if not args.no_gate:
+        gated = gate_comparison(args, G, g, runs, q_async, out)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -200,7 +304,7 @@ def main():
         "time_to_converge_ms": {"median": round(float(np.median(ttc)), 3), "min": round(float(np.min(ttc)), 3)},
         "sweeps": runs[0]["iterations"], "modularity": round(q_async, 6),
         "m_over_time_to_converge": round(g.m / (np.median(ttc) * 1e-3), 1),
-        "deterministic": det, "roofline": roofline, "cpu_baseline": cpu,
+        "deterministic": det, "tuning": tuned, "gated": gated, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
     G.close()

@@ -169,15 +169,44 @@ int lpa_get_flags(const lpa_graph *g, uint8_t *flags_out, unsigned flags);
 int lpa_modularity(const lpa_graph *g, const int32_t *labels, unsigned flags, double *q_out);
 
 /*
- * lpa_set_async_phases - schedule of an asynchronous sweep (default: 16 steps
- * by colour).  The flagged
- * vertices of a sweep are split into `phases` steps processed one after the
- * other, every vertex of a step at once, so a step sees the labels earlier
- * steps wrote in place (Section 4.1).  by_colour = 0: steps by a fixed hash of
- * the vertex id; by_colour = 1: runs of consecutive colour classes of
- * lpa_color, about n / phases vertices each (vertices of one class are never
- * adjacent).  phases in [1, 1024]; takes effect for the next lpa_run.
+ * lpa_set_variants - kernel shape of each degree bin 0..5 (count must be 6;
+ * NULL restores the defaults): 0, 1 or 2, a choice of lanes per vertex and
+ * row entries in flight per lane at the bin's fixed table size.  Results do
+ * not depend on it (the deterministic mode stays label-for-label equal).
  */
+int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
+
+/*
+ * lpa_autotune - tunes the handle on its own graph with runs of the given
+ * tolerance, max_iters >= 1 and mode (pruning on).  Asynchronous mode first:
+ * among the schedules (early steps, early sweeps, late steps) = (16, 0, 16),
+ * (16, 2, 4), (16, 2, 8), (16, 3, 4), (16, 3, 8) it installs the fastest
+ * whose modularity stays within 0.002 of the first's (schedule_out: int32[3],
+ * may be NULL; batched handles keep theirs).  Then it times every kernel
+ * shape variant (per-kernel timing), keeps for each bin the fastest and
+ * returns it in variant_out (int32[6], may be NULL) with the chosen kernels'
+ * times in bin_ms_out (double[6], ms per run, 0 for an empty bin; may be
+ * NULL).  Leaves the labels of its last trial run.
+ */
+int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_t *variant_out, double *bin_ms_out,
+                 int32_t *schedule_out);
+
+/*
+ * lpa_set_async_schedule - schedule of the asynchronous mode.  The flagged
+ * vertices of a sweep are split into steps processed one after the other,
+ * every vertex of a step at once, so a step sees the labels earlier steps
+ * wrote in place (Section 4.1).  The first `early_sweeps` sweeps of a run use
+ * `early_phases` steps, later sweeps (and a verification sweep)
+ * `late_phases` steps; the default is 16 steps for 2 sweeps, then 4.
+ * by_colour = 1: steps are runs of consecutive colour classes of lpa_color,
+ * about n / phases vertices each (vertices of one class are never adjacent);
+ * 0: steps by a fixed hash of the vertex id.  Phases in [1, 1024],
+ * early_sweeps in [0, 1000]; takes effect for the next lpa_run.
+ */
+int lpa_set_async_schedule(lpa_graph *g, int32_t early_phases, int32_t early_sweeps, int32_t late_phases,
+                           int32_t by_colour);
+
+/* lpa_set_async_phases - the same number of steps in every sweep. */
 int lpa_set_async_phases(lpa_graph *g, int32_t phases, int32_t by_colour);
 
 /*
@@ -294,6 +323,16 @@ int lpa_gate_train(float *params, const float *features, const uint8_t *targets,
  */
 int lpa_gate_threshold(const float *params, const float *features, const uint8_t *targets, int64_t count,
                        double recall, float *threshold, int device, void *hip_stream, unsigned flags);
+
+/*
+ * lpa_nmi - normalised mutual information of two labelings a, b (int32[n],
+ * any values; host or device per flags): 2 I(X;Y) / (H(X) + H(Y)) with
+ * natural logarithms, the quality measure the paper names in Section 1
+ * (arithmetic normalisation); 1 when both have a single class or n = 0.
+ * Runs on `device`, enqueued on hip_stream, synchronised before returning.
+ */
+int lpa_nmi(const int32_t *a, const int32_t *b, int64_t n, double *nmi_out, int device, void *hip_stream,
+            unsigned flags);
 
 /* lpa_destroy - release the handle and all device memory it owns (NULL is a no-op). */
 void lpa_destroy(lpa_graph *g);

@@ -60,7 +60,7 @@ def build_lpa() -> Path:
     LIBDIR.mkdir(exist_ok=True)
     objdir = PKG / "_build"
     objdir.mkdir(exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in lpa_sources():
         obj = objdir / (src.name + ".o")
         flags = HIP_FLAGS if src.suffix == ".hip" else ["-O3", "-std=c++17", "-fPIC"]
@@ -68,8 +68,13 @@ def build_lpa() -> Path:
         if src.suffix == ".cpp":
             cmd = [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-O3", "-std=c++17", "-fPIC",
                    "-I", str(INCLUDE), "-I", str(CSRC / "lpa"), "-c", str(src), "-o", str(obj)]
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(str(obj))
+    # one compiler process per source file, a few at a time
+    from concurrent.futures import ThreadPoolExecutor
+    workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(_run, cmds))
     tmp = LPA_LIB.with_suffix(".so.tmp")
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", str(tmp)])
     os.replace(tmp, LPA_LIB)

@@ -112,6 +112,9 @@ SIGNATURES = {
     "lpa_color": (ctypes.c_int, [_vp, _u32, _vp, ctypes.c_uint, ctypes.POINTER(_i32)]),
     "lpa_set_bins": (ctypes.c_int, [_vp, _vp, _i32]),
     "lpa_set_async_phases": (ctypes.c_int, [_vp, _i32, _i32]),
+    "lpa_set_async_schedule": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32]),
+    "lpa_set_variants": (ctypes.c_int, [_vp, _vp, _i32]),
+    "lpa_autotune": (ctypes.c_int, [_vp, _f64, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "lpa_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_uint]),
     "lpa_batch_stats": (ctypes.c_int, [_vp, _vp, _vp]),
     "lpa_gate_load": (ctypes.c_int, [_vp, _vp, _f32]),
@@ -124,6 +127,7 @@ SIGNATURES = {
                                       ctypes.c_uint]),
     "lpa_gate_threshold": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, ctypes.POINTER(_f32), ctypes.c_int, _vp,
                                           ctypes.c_uint]),
+    "lpa_nmi": (ctypes.c_int, [_vp, _vp, _i64, ctypes.POINTER(_f64), ctypes.c_int, _vp, ctypes.c_uint]),
     "lpa_destroy": (None, [_vp]),
     "lpa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -214,6 +218,20 @@ def lpa_set_async_phases(handle, phases, by_colour=0):
     return load().lpa_set_async_phases(handle, phases, int(by_colour))
 
 
+def lpa_set_async_schedule(handle, early_phases, early_sweeps, late_phases, by_colour=1):
+    return load().lpa_set_async_schedule(handle, early_phases, early_sweeps, late_phases, int(by_colour))
+
+
+def lpa_set_variants(handle, variant=None):
+    arr = None if variant is None else np.ascontiguousarray(variant, dtype=np.int32)
+    return load().lpa_set_variants(handle, _ptr(arr), 0 if arr is None else len(arr))
+
+
+def lpa_autotune(handle, tolerance, max_iters, mode, variant_out=None, bin_ms_out=None, schedule_out=None):
+    return load().lpa_autotune(handle, tolerance, max_iters, mode, _ptr(variant_out), _ptr(bin_ms_out),
+                               _ptr(schedule_out))
+
+
 def lpa_batch_create(n_graphs, graph_vptr, n, m, offsets, indices, weights=None, device=0, hip_stream=None, flags=0):
     h = ctypes.c_void_p()
     rc = load().lpa_batch_create(ctypes.byref(h), n_graphs, _ptr(graph_vptr), n, m, _ptr(offsets), _ptr(indices),
@@ -227,6 +245,28 @@ def lpa_batch_stats(handle, iterations=None, converged=None):
 
 def lpa_destroy(handle):
     load().lpa_destroy(handle)
+
+
+def lpa_nmi(a, b, n, device=0, hip_stream=None, flags=0):
+    out = ctypes.c_double()
+    rc = load().lpa_nmi(_ptr(a), _ptr(b), n, ctypes.byref(out), device, hip_stream, flags)
+    return rc, out.value
+
+
+def nmi(a, b, device=0) -> float:
+    """NMI of two labelings (numpy arrays or device tensors of int32)."""
+    dev = hasattr(a, "data_ptr")
+    if dev != hasattr(b, "data_ptr"):
+        raise ValueError("both labelings must be host arrays or both device tensors")
+    if not dev:
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        b = np.ascontiguousarray(b, dtype=np.int32)
+    n = int(a.shape[0])
+    if int(b.shape[0]) != n:
+        raise ValueError("labelings differ in length")
+    rc, v = lpa_nmi(a, b, n, device, _current_stream(device), LPA_FLAG_DEVICE_PTRS if dev else 0)
+    _check(rc, "lpa_nmi")
+    return v
 
 
 def lpa_gate_load(handle, params, threshold):
@@ -354,6 +394,21 @@ class LPAGraph:
 
     def set_async_phases(self, phases, by_colour=False):
         _check(lpa_set_async_phases(self.handle, phases, by_colour), "lpa_set_async_phases")
+
+    def set_async_schedule(self, early_phases=16, early_sweeps=2, late_phases=4, by_colour=True):
+        _check(lpa_set_async_schedule(self.handle, early_phases, early_sweeps, late_phases, by_colour),
+               "lpa_set_async_schedule")
+
+    def set_variants(self, variant=None):
+        _check(lpa_set_variants(self.handle, variant), "lpa_set_variants")
+
+    def autotune(self, tolerance=0.05, max_iters=20, mode=LPA_MODE_ASYNC):
+        """Returns (variant per bin, ms per run of each chosen bin kernel, schedule)."""
+        v = np.zeros(6, np.int32)
+        ms = np.zeros(6, np.float64)
+        sch = np.zeros(3, np.int32)
+        _check(lpa_autotune(self.handle, tolerance, max_iters, mode, v, ms, sch), "lpa_autotune")
+        return v, ms, tuple(int(x) for x in sch)
 
     def gate_load(self, params, threshold):
         p = np.ascontiguousarray(params, dtype=np.float32)

@@ -17,9 +17,25 @@ typedef unsigned long long u64;
 // many workgroups (see the hub kernels).
 constexpr int NBINS = 7;
 constexpr int HUB_BIN = NBINS - 1;
-constexpr int BIN_GROUP[NBINS - 1] = {1, 2, 8, 32, 128, 256};
 constexpr int BIN_SLOTS[NBINS - 1] = {8, 32, 128, 512, 2048, 8192};
 constexpr int DEFAULT_BIN_MAXDEG[NBINS - 1] = {4, 16, 64, 256, 1024, 4096};
+
+// Kernel shapes of a bin: lanes per vertex (bins 0-3: lanes of one wave,
+// bins 4-5: a workgroup), table slots (fixed per bin: BIN_SLOTS) and row
+// entries in flight per lane.  Variant 0 is the default; the others are the
+// tuner's candidates.
+constexpr int NVARIANTS = 3;
+struct BinShape {
+  int group, slots, unroll;
+};
+constexpr BinShape BIN_SHAPES[NBINS - 1][NVARIANTS] = {
+    {{1, 8, 4}, {1, 8, 2}, {2, 8, 2}},
+    {{2, 32, 8}, {4, 32, 4}, {2, 32, 4}},
+    {{8, 128, 8}, {16, 128, 4}, {8, 128, 4}},
+    {{32, 512, 8}, {64, 512, 4}, {32, 512, 4}},
+    {{128, 2048, 8}, {256, 2048, 4}, {128, 2048, 4}},
+    {{256, 8192, 16}, {256, 8192, 8}, {512, 8192, 8}},
+};
 
 // Hub path: a hub's entries are cut into chunks of HUB_CHUNK; a chunk's labels
 // are merged in LDS and scattered into 2^pbits label partitions (by hash),

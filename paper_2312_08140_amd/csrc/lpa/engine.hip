@@ -64,13 +64,18 @@ struct lpa_graph {
   bool has_labels = false;
   // bins
   BinLimits lim{};
+  int32_t variant[NBINS - 1] = {0, 0, 0, 0, 0, 0};  // kernel shape of each bin (BIN_SHAPES)
   bool lists_ready = false;
-  int32_t *alist = nullptr;
-  int nphase = 16;                  // asynchronous mode: steps per sweep
+  // asynchronous mode: the first `early_sweeps` sweeps run in sched[0]'s
+  // steps, later sweeps (and verification) in sched[1]'s
+  struct AsyncSched {
+    int nphase = 16;                  // steps per sweep
+    int32_t *list = nullptr;          // vertices by (step, bin)
+    std::vector<int64_t> start;       // nphase * NBINS + 1 list bounds
+    std::vector<int64_t> hub_chunks, hub_parts;  // hub work per step
+  } sched[2];
+  int early_sweeps = 2;
   bool async_by_colour = true;      // steps made of consecutive colour classes (else a hash of the id)
-  std::vector<int32_t> h_async_group;  // per vertex step of the asynchronous schedule (host)
-  std::vector<int64_t> astart;      // nphase * NBINS + 1 list bounds
-  std::vector<int64_t> ph_hub_chunks, ph_hub_parts;
   // deterministic schedule
   int32_t *color = nullptr;
   int32_t ncol = 0;
@@ -111,7 +116,8 @@ struct lpa_graph {
   void *scratch_small = nullptr;  // CsrCheck + sums, ModAcc, counters
   int wall_khz = 100000;
   // graphs
-  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (mode, prune, sweeps per launch, features)
+  // (mode, prune, sweeps per launch, features, schedule)
+  std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
   // learned gate
   bool feat_on = false;           // the sweeps being emitted write gate features
   FeatArgs cur_feat{};
@@ -424,23 +430,18 @@ void ensure_colored(lpa_graph *g, uint32_t seed);
 // Asynchronous lists: every flagged vertex of a step is processed at once;
 // the steps of a sweep are either nphase groups by a hash of the id, or runs
 // of consecutive colour classes holding about n_active / nphase vertices each.
-void ensure_lists(lpa_graph *g) {
-  if (g->lists_ready) return;
-  drop_graphs(g);
-  if (!g->alist) g->alist = dalloc_n<int32_t>(g, g->n_active);
-  if (!g->front) g->front = dalloc_n<int32_t>(g, g->n_active);
-  build_hubs(g);
+void build_async(lpa_graph *g, lpa_graph::AsyncSched &sc) {
+  if (!sc.list) sc.list = dalloc_n<int32_t>(g, g->n_active);
   std::vector<int32_t> cmap;
   if (g->async_by_colour) {
-    ensure_colored(g, g->colored ? g->color_seed : 0u);
     std::vector<int64_t> csize(std::max(1, g->ncol), 0);
     for (int64_t v = 0; v < g->n; ++v)
       if (g->h_off[v + 1] > g->h_off[v]) csize[g->h_color[v]] += 1;
     cmap.assign(csize.size(), 0);
-    const double per = std::max(1.0, (double)g->n_active / g->nphase);
+    const double per = std::max(1.0, (double)g->n_active / sc.nphase);
     int64_t before = 0;
     for (size_t c = 0; c < csize.size(); ++c) {
-      cmap[c] = std::min(g->nphase - 1, (int)((double)before / per));
+      cmap[c] = std::min(sc.nphase - 1, (int)((double)before / per));
       before += csize[c];
     }
   }
@@ -449,21 +450,38 @@ void ensure_lists(lpa_graph *g) {
     d_cmap = dalloc_n<int32_t>(g, (int64_t)cmap.size());
     HIP_OK(hipMemcpyAsync(d_cmap, cmap.data(), sizeof(int32_t) * cmap.size(), hipMemcpyHostToDevice, g->stream));
   }
-  build_lists(g, g->async_by_colour ? g->color : nullptr, d_cmap, g->nphase, g->nphase * NBINS, g->alist, g->astart);
+  build_lists(g, g->async_by_colour ? g->color : nullptr, d_cmap, sc.nphase, sc.nphase * NBINS, sc.list, sc.start);
   dfree(g, d_cmap);
-  ensure_fcount(g, g->nphase * NBINS);
-  g->ph_hub_chunks.assign(g->nphase, 0);
-  g->ph_hub_parts.assign(g->nphase, 0);
+  ensure_fcount(g, sc.nphase * NBINS);
+  sc.hub_chunks.assign(sc.nphase, 0);
+  sc.hub_parts.assign(sc.nphase, 0);
   for (size_t k = 0; k < g->h_hub_ids.size(); ++k) {
     const uint32_t v = (uint32_t)g->h_hub_ids[k];
     int ph = 0;
     if (g->async_by_colour) ph = cmap[g->h_color[v]];
-    else if (g->nphase > 1) ph = (int)(fmix32(v ^ phase_seed()) % (uint32_t)g->nphase);
-    g->ph_hub_chunks[ph] += g->h_hub_chunks[k];
-    g->ph_hub_parts[ph] += g->h_hub_parts[k];
+    else if (sc.nphase > 1) ph = (int)(fmix32(v ^ phase_seed()) % (uint32_t)sc.nphase);
+    sc.hub_chunks[ph] += g->h_hub_chunks[k];
+    sc.hub_parts[ph] += g->h_hub_parts[k];
   }
+}
+
+void ensure_lists(lpa_graph *g) {
+  if (g->lists_ready) return;
+  drop_graphs(g);
+  if (!g->front) g->front = dalloc_n<int32_t>(g, g->n_active);
+  build_hubs(g);
+  if (g->async_by_colour) ensure_colored(g, g->colored ? g->color_seed : 0u);
+  build_async(g, g->sched[0]);
+  if (g->sched[1].nphase != g->sched[0].nphase) build_async(g, g->sched[1]);
   g->lists_ready = true;
 }
+
+// the schedule of asynchronous sweep s (0-based; verification counts as late)
+const lpa_graph::AsyncSched &async_sched(const lpa_graph *g, int late) {
+  return late && g->sched[1].nphase != g->sched[0].nphase ? g->sched[1] : g->sched[0];
+}
+
+int max_phases(const lpa_graph *g) { return std::max(g->sched[0].nphase, g->sched[1].nphase); }
 
 void ensure_colored(lpa_graph *g, uint32_t seed) {
   if (g->colored && g->color_seed == seed) return;
@@ -616,15 +634,15 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
                         a, h);
       tk_end(g, st, TK_HUB_FINISH);
     } else {
-      const int per_block = b <= 3 ? 256 / BIN_GROUP[b] : 1;
+      const int per_block = bin_vertices_per_block(b, g->variant[b]);
       tk_begin(g, st);
-      launch_scan_bin(b, g->wk, g->feat_on, grid_cap(seg, per_block, max_blocks), st, a);
+      launch_scan_bin(b, g->variant[b], g->wk, g->feat_on, grid_cap(seg, per_block, max_blocks), st, a);
       tk_end(g, st, TK_BIN0 + b);
     }
   }
 }
 
-void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune) {
+void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late) {
   if (g->gate_active) {
     tk_begin(g, st);
     launch_gate_pass(g->ctl, g->gate_f, g->gate_z, g->cur_feat, g->F, g->gskip, g->n, g->cu_count, st);
@@ -635,11 +653,12 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune) {
       emit_step(g, st, g->dlist, &g->dstart[(size_t)c * NBINS], g->fcount + (size_t)c * NBINS, prune,
                 g->col_hub_chunks[c], g->col_hub_parts[c]);
   } else {
-    for (int ph = 0; ph < g->nphase; ++ph)
-      emit_step(g, st, g->alist, &g->astart[(size_t)ph * NBINS], g->fcount + (size_t)ph * NBINS, prune,
-                g->ph_hub_chunks[ph], g->ph_hub_parts[ph]);
+    const lpa_graph::AsyncSched &sc = async_sched(g, late);
+    for (int ph = 0; ph < sc.nphase; ++ph)
+      emit_step(g, st, sc.list, &sc.start[(size_t)ph * NBINS], g->fcount + (size_t)ph * NBINS, prune,
+                sc.hub_chunks[ph], sc.hub_parts[ph]);
   }
-  const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : g->nphase * NBINS;
+  const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : max_phases(g) * NBINS;
   tk_begin(g, st);
   if (g->ngraphs) launch_batch_end(g->ctl, batch_args(g), st);
   launch_end_sweep(g->ctl, g->fcount, nfc, g->host_done_dev, st);
@@ -649,15 +668,21 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune) {
 
 // One HIP graph holding `sweeps` consecutive sweeps (their kernels exit at
 // once after the stop test holds), captured once per (mode, prune, sweeps).
-hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps) {
+// A graph of `sweeps` consecutive sweeps starting at sweep `first` (which
+// selects the asynchronous schedule of each).
+hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps, int first) {
   // captured kernels embed the feature arguments (trace switch, sweep cap)
   const int fcode = g->feat_on ? 1 + 2 * g->cur_feat.trace + 4 * g->gate_active + 8 * g->cur_feat.max_iters : 0;
-  auto key = std::make_tuple(mode, prune, sweeps, fcode);
+  // only the early/late split of the covered sweeps matters
+  const int fkey = mode == LPA_MODE_DETERMINISTIC ? 0
+                   : sweeps == 1                  ? (first >= g->early_sweeps ? 1 : 0)
+                                                  : 2 + std::min(first, g->early_sweeps);
+  auto key = std::make_tuple(mode, prune, sweeps, fcode, fkey);
   auto it = g->graphs.find(key);
   if (it != g->graphs.end()) return it->second;
   hipGraph_t graph = nullptr;
   HIP_OK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-  for (int s = 0; s < sweeps; ++s) emit_sweep(g, g->cap_stream, mode, prune);
+  for (int s = 0; s < sweeps; ++s) emit_sweep(g, g->cap_stream, mode, prune, first + s >= g->early_sweeps);
   HIP_OK(hipStreamEndCapture(g->cap_stream, &graph));
   hipGraphExec_t exec = nullptr;
   hipError_t e = hipGraphInstantiateWithFlags(&exec, graph, 0);
@@ -757,6 +782,11 @@ int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, co
   if (const char *c = std::getenv("GVELPA_HUB_PART_CAP"))  // testing: force the partition spill path
     g->hub_part_cap = (int32_t)std::max(1L, std::min((long)HUB_PART_CAP, std::strtol(c, nullptr, 10)));
   for (int b = 0; b < NBINS - 1; ++b) g->lim.maxdeg[b] = DEFAULT_BIN_MAXDEG[b];
+  // asynchronous schedule: 16 colour-grouped steps for the first two sweeps,
+  // 4 afterwards (late sweeps change few labels; fewer steps cost fewer launches)
+  g->sched[0].nphase = 16;
+  g->sched[1].nphase = 4;
+  g->early_sweeps = 2;
   int rc = run_guarded(g, [&]() -> int {
     hipDeviceProp_t prop;
     HIP_OK(hipGetDeviceProperties(&prop, device));
@@ -991,18 +1021,117 @@ int lpa_set_bins(lpa_graph *g, const int32_t *max_degree, int32_t count) {
   });
 }
 
-int lpa_set_async_phases(lpa_graph *g, int32_t phases, int32_t by_colour) {
+int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count) {
   return run_guarded(g, [&]() -> int {
-    if (phases < 1 || phases > 1024) return LPA_ERR_INVALID_ARG;
-    if (phases != g->nphase || (by_colour != 0) != g->async_by_colour) {
-      g->nphase = phases;
-      g->async_by_colour = by_colour != 0;
-      g->lists_ready = false;
-      g->dlists_ready = false;
+    int32_t v[NBINS - 1] = {0, 0, 0, 0, 0, 0};
+    if (variant) {
+      if (count != NBINS - 1) return LPA_ERR_INVALID_ARG;
+      for (int b = 0; b < NBINS - 1; ++b) {
+        if (variant[b] < 0 || variant[b] >= NVARIANTS) return LPA_ERR_INVALID_ARG;
+        v[b] = variant[b];
+      }
+    }
+    if (std::memcmp(v, g->variant, sizeof(v)) != 0) {
+      std::memcpy(g->variant, v, sizeof(v));
       drop_graphs(g);
     }
     return LPA_OK;
   });
+}
+
+int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_t *variant_out, double *bin_ms_out,
+                 int32_t *schedule_out) {
+  if (!g || max_iters < 1 || max_iters > 1000 || (mode != LPA_MODE_ASYNC && mode != LPA_MODE_DETERMINISTIC))
+    return LPA_ERR_INVALID_ARG;
+  int rc = LPA_OK;
+  // 1. Asynchronous schedule: the fastest candidate whose modularity stays
+  //    within 0.002 of the all-16-step schedule's.
+  if (mode == LPA_MODE_ASYNC && !g->ngraphs) {
+    static const int32_t cand[][3] = {{16, 0, 16}, {16, 2, 4}, {16, 2, 8}, {16, 3, 4}, {16, 3, 8}};
+    double q_ref = 0.0, best_ms = 1e300;
+    int best = 0;
+    for (int c = 0; c < (int)(sizeof(cand) / sizeof(cand[0])); ++c) {
+      rc = lpa_set_async_schedule(g, cand[c][0], cand[c][1], cand[c][2], g->async_by_colour ? 1 : 0);
+      if (rc != LPA_OK) return rc;
+      double ms = 1e300, q = 0.0;
+      for (int rep = 0; rep < 2; ++rep) {
+        lpa_stats st;
+        rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
+        if (rc != LPA_OK) return rc;
+        ms = std::min(ms, st.total_ms);
+      }
+      rc = lpa_modularity(g, nullptr, 0, &q);
+      if (rc != LPA_OK) return rc;
+      if (c == 0) q_ref = q;
+      if (q >= q_ref - 0.002 && ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    rc = lpa_set_async_schedule(g, cand[best][0], cand[best][1], cand[best][2], g->async_by_colour ? 1 : 0);
+    if (rc != LPA_OK) return rc;
+    if (schedule_out) std::memcpy(schedule_out, cand[best], sizeof(cand[best]));
+  } else if (schedule_out) {
+    schedule_out[0] = g->sched[0].nphase;
+    schedule_out[1] = g->early_sweeps;
+    schedule_out[2] = g->sched[1].nphase;
+  }
+  // 2. Kernel shapes: every bin is its own kernel, so one run per variant
+  //    times all bins at once; each run is repeated and the faster kept.
+  double best_ms[NBINS - 1];
+  int32_t best_v[NBINS - 1];
+  for (int b = 0; b < NBINS - 1; ++b) {
+    best_ms[b] = 1e300;
+    best_v[b] = 0;
+  }
+  for (int v = 0; v < NVARIANTS; ++v) {
+    int32_t all[NBINS - 1];
+    for (int b = 0; b < NBINS - 1; ++b) all[b] = v;
+    rc = lpa_set_variants(g, all, NBINS - 1);
+    if (rc != LPA_OK) return rc;
+    for (int rep = 0; rep < 2; ++rep) {
+      lpa_stats st;
+      rc = lpa_run(g, tolerance, max_iters, mode, 1, LPA_FLAG_KERNEL_TIMING, nullptr, nullptr, nullptr, &st);
+      if (rc != LPA_OK) return rc;
+      for (int b = 0; b < NBINS - 1; ++b) {
+        if (!st.kernel_launches[TK_BIN0 + b]) continue;
+        if (st.kernel_ms[TK_BIN0 + b] < best_ms[b]) {
+          best_ms[b] = st.kernel_ms[TK_BIN0 + b];
+          best_v[b] = v;
+        }
+      }
+    }
+  }
+  rc = lpa_set_variants(g, best_v, NBINS - 1);
+  if (rc != LPA_OK) return rc;
+  if (variant_out) std::memcpy(variant_out, best_v, sizeof(best_v));
+  if (bin_ms_out)
+    for (int b = 0; b < NBINS - 1; ++b) bin_ms_out[b] = best_ms[b] < 1e299 ? best_ms[b] : 0.0;
+  return LPA_OK;
+}
+
+int lpa_set_async_schedule(lpa_graph *g, int32_t early_phases, int32_t early_sweeps, int32_t late_phases,
+                           int32_t by_colour) {
+  return run_guarded(g, [&]() -> int {
+    if (early_phases < 1 || early_phases > 1024 || late_phases < 1 || late_phases > 1024 || early_sweeps < 0 ||
+        early_sweeps > 1000)
+      return LPA_ERR_INVALID_ARG;
+    if (early_phases != g->sched[0].nphase || late_phases != g->sched[1].nphase ||
+        (by_colour != 0) != g->async_by_colour) {
+      g->sched[0].nphase = early_phases;
+      g->sched[1].nphase = late_phases;
+      g->async_by_colour = by_colour != 0;
+      g->lists_ready = false;
+      g->dlists_ready = false;
+    }
+    g->early_sweeps = early_sweeps;
+    drop_graphs(g);
+    return LPA_OK;
+  });
+}
+
+int lpa_set_async_phases(lpa_graph *g, int32_t phases, int32_t by_colour) {
+  return lpa_set_async_schedule(g, phases, 0, phases, by_colour);
 }
 
 int lpa_color(lpa_graph *g, uint32_t seed, int32_t *colors_out, unsigned flags, int32_t *num_colors) {
@@ -1071,8 +1200,17 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       launch_fill_i16(g->lastp, g->n, (int16_t)-1, g->stream);
     }
     g->cur_feat = feat_args(g, max_iters, trace);
-    hipGraphExec_t exec = nullptr;
-    if (use_graph && max_iters > 0) exec = sweep_graph(g, mode, prune, one_launch ? max_iters : 1);
+    // per-sweep graphs of the early and the late asynchronous schedule
+    hipGraphExec_t exec = nullptr, exec_late = nullptr;
+    if (use_graph && max_iters > 0) {
+      exec = sweep_graph(g, mode, prune, one_launch ? max_iters : 1, 0);
+      exec_late = one_launch ? exec : sweep_graph(g, mode, prune, 1, g->early_sweeps);
+    }
+    auto launch_sweep = [&](int s) {
+      const int late = s >= g->early_sweeps;
+      if (exec) HIP_OK(hipGraphLaunch(late ? exec_late : exec, g->stream));
+      else emit_sweep(g, g->stream, mode, prune, late);
+    };
     HIP_OK(hipEventRecord(e1, g->stream));
     HIP_OK(hipEventSynchronize(e1));
     float setup_ms = 0;
@@ -1081,7 +1219,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     g->timing = timing;
     g->ev_used = 0;
     HIP_OK(hipEventRecord(t0, g->stream));
-    const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : g->nphase * NBINS;
+    const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : max_phases(g) * NBINS;
     const int dense = mode == LPA_MODE_ASYNC && prune && !(flags & LPA_FLAG_EXACT_MARKS);
     launch_run_begin(g->ctl, tolerance, max_iters, g->n, g->n_active, g->fcount, nfc, g->host_done_dev, dense,
                      !init_labels && !init_flags, gate ? 1 : 0, g->stream);
@@ -1090,8 +1228,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       HIP_OK(hipGraphLaunch(exec, g->stream));
     } else
     for (int s = 0; s < max_iters; ++s) {
-      if (exec) HIP_OK(hipGraphLaunch(exec, g->stream));
-      else emit_sweep(g, g->stream, mode, prune);
+      launch_sweep(s);
       HIP_OK(hipEventRecord(lag[s & 1], g->stream));
       if (s >= 1) {
         HIP_OK(hipEventSynchronize(lag[(s - 1) & 1]));
@@ -1103,8 +1240,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     // verifies once more.
     auto sweep_loop = [&](int budget) {
       for (int s = 0; s < budget; ++s) {
-        if (exec) HIP_OK(hipGraphLaunch(exec, g->stream));
-        else emit_sweep(g, g->stream, mode, prune);
+        launch_sweep(max_iters + s);  // sweeps after a verification run in the late schedule
         HIP_OK(hipEventRecord(lag[s & 1], g->stream));
         if (s >= 1) {
           HIP_OK(hipEventSynchronize(lag[(s - 1) & 1]));
@@ -1116,8 +1252,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     if ((flags & (LPA_FLAG_VERIFY | LPA_FLAG_VERIFY_FULL | LPA_FLAG_GATE)) && max_iters > 0 && !one_launch) {
       for (int attempt = 0; attempt < 2; ++attempt) {
         launch_set_phase(g->ctl, (flags & LPA_FLAG_VERIFY_FULL) ? 2 : 1, 0, 0, g->host_done_dev, g->stream);
-        if (exec) HIP_OK(hipGraphLaunch(exec, g->stream));
-        else emit_sweep(g, g->stream, mode, prune);
+        launch_sweep(max_iters);
         int32_t vflag = 0;
         HIP_OK(hipMemcpyAsync(&vflag, &g->ctl->verified, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
         HIP_OK(hipStreamSynchronize(g->stream));

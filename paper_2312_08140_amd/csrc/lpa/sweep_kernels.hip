@@ -466,6 +466,7 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
   const int grp = threadIdx.x / GROUP;
   u64 *T = TS == 1 ? tab + grp * SLOTS : tab + grp;
   const int count = *a.fcount;
+  if ((int)blockIdx.x * GPB >= count) return;  // grids are sized for the whole list; most of a sparse step idles
   const int stride = gridDim.x * GPB;
   const bool mark_now = a.prune && !__atomic_load_n(&a.ctl->dense_cur, __ATOMIC_RELAXED);
   const int sweep = FEAT ? a.ctl->sweep : 0;
@@ -539,6 +540,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
   __shared__ u64 red[BLOCK / 64];
   __shared__ TabStats tred[FEAT ? BLOCK / 64 : 1];
   const int count = *a.fcount;
+  if ((int)blockIdx.x >= count) return;
   const int stride = gridDim.x;
   const bool mark_now = a.prune && !__atomic_load_n(&a.ctl->dense_cur, __ATOMIC_RELAXED);
   const int sweep = FEAT ? a.ctl->sweep : 0;
@@ -607,35 +609,54 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
 
 // ---------------------------------------------------------------- launchers
 
+template <int B, int V, int WK, bool FEAT>
+static void launch_shape(dim3 grid, hipStream_t st, const ScanArgs &a) {
+  constexpr BinShape sh = BIN_SHAPES[B][V];
+  static_assert(sh.slots == BIN_SLOTS[B], "a bin's variants share its table size");
+  if constexpr (B <= 3) {
+    static_assert(sh.group <= 64, "group bins keep a vertex inside one wave");
+    hipLaunchKernelGGL((k_scan_group<sh.group, sh.slots, sh.unroll, WK, FEAT>), grid, dim3(256), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_scan_block<sh.group, sh.slots, sh.unroll, WK, FEAT>), grid, dim3(sh.group), 0, st, a);
+  }
+}
+
+template <int B, int WK, bool FEAT>
+static void launch_bin_v(int variant, dim3 grid, hipStream_t st, const ScanArgs &a) {
+  switch (variant) {
+    case 1: launch_shape<B, 1, WK, FEAT>(grid, st, a); break;
+    case 2: launch_shape<B, 2, WK, FEAT>(grid, st, a); break;
+    default: launch_shape<B, 0, WK, FEAT>(grid, st, a); break;
+  }
+}
+
 template <int WK, bool FEAT>
-static void launch_bin_wk(int bin, dim3 grid, hipStream_t st, const ScanArgs &a) {
+static void launch_bin_wk(int bin, int variant, dim3 grid, hipStream_t st, const ScanArgs &a) {
   switch (bin) {
-    case 0: hipLaunchKernelGGL((k_scan_group<1, 8, 4, WK, FEAT>), grid, dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_scan_group<2, 32, 8, WK, FEAT>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_scan_group<8, 128, 8, WK, FEAT>), grid, dim3(256), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_scan_group<32, 512, 8, WK, FEAT>), grid, dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_scan_block<128, 2048, 8, WK, FEAT>), grid, dim3(128), 0, st, a); break;
-    case 5: hipLaunchKernelGGL((k_scan_block<256, 8192, 16, WK, FEAT>), grid, dim3(256), 0, st, a); break;
+    case 0: launch_bin_v<0, WK, FEAT>(variant, grid, st, a); break;
+    case 1: launch_bin_v<1, WK, FEAT>(variant, grid, st, a); break;
+    case 2: launch_bin_v<2, WK, FEAT>(variant, grid, st, a); break;
+    case 3: launch_bin_v<3, WK, FEAT>(variant, grid, st, a); break;
+    case 4: launch_bin_v<4, WK, FEAT>(variant, grid, st, a); break;
+    case 5: launch_bin_v<5, WK, FEAT>(variant, grid, st, a); break;
     default: break;
   }
 }
 
-static_assert(BIN_GROUP[0] == 1 && BIN_SLOTS[0] == 8, "bin table and launcher disagree");
-static_assert(BIN_GROUP[1] == 2 && BIN_SLOTS[1] == 32, "bin table and launcher disagree");
-static_assert(BIN_GROUP[2] == 8 && BIN_SLOTS[2] == 128, "bin table and launcher disagree");
-static_assert(BIN_GROUP[3] == 32 && BIN_SLOTS[3] == 512, "bin table and launcher disagree");
-static_assert(BIN_GROUP[4] == 128 && BIN_SLOTS[4] == 2048, "bin table and launcher disagree");
-static_assert(BIN_GROUP[5] == 256 && BIN_SLOTS[5] == 8192, "bin table and launcher disagree");
+int bin_vertices_per_block(int bin, int variant) {
+  const BinShape sh = BIN_SHAPES[bin][variant];
+  return bin <= 3 ? 256 / sh.group : 1;
+}
 
-void launch_scan_bin(int bin, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a) {
+void launch_scan_bin(int bin, int variant, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a) {
   if (feat) {
-    if (wk == W_UNIT) launch_bin_wk<W_UNIT, true>(bin, dim3(blocks), st, a);
-    else if (wk == W_U8) launch_bin_wk<W_U8, true>(bin, dim3(blocks), st, a);
-    else launch_bin_wk<W_U32, true>(bin, dim3(blocks), st, a);
+    if (wk == W_UNIT) launch_bin_wk<W_UNIT, true>(bin, variant, dim3(blocks), st, a);
+    else if (wk == W_U8) launch_bin_wk<W_U8, true>(bin, variant, dim3(blocks), st, a);
+    else launch_bin_wk<W_U32, true>(bin, variant, dim3(blocks), st, a);
   } else {
-    if (wk == W_UNIT) launch_bin_wk<W_UNIT, false>(bin, dim3(blocks), st, a);
-    else if (wk == W_U8) launch_bin_wk<W_U8, false>(bin, dim3(blocks), st, a);
-    else launch_bin_wk<W_U32, false>(bin, dim3(blocks), st, a);
+    if (wk == W_UNIT) launch_bin_wk<W_UNIT, false>(bin, variant, dim3(blocks), st, a);
+    else if (wk == W_U8) launch_bin_wk<W_U8, false>(bin, variant, dim3(blocks), st, a);
+    else launch_bin_wk<W_U32, false>(bin, variant, dim3(blocks), st, a);
   }
 }
 

@@ -26,7 +26,8 @@ struct CompactArgs {
 void launch_compact(const CompactArgs &a, int blocks, hipStream_t st);
 void launch_gate_pass(const Ctl *ctl, const float *gate, float z, const FeatArgs &f, const uint8_t *F,
                       uint8_t *skip, int64_t n, int cu_count, hipStream_t st);
-void launch_scan_bin(int bin, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a);
+void launch_scan_bin(int bin, int variant, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a);
+int bin_vertices_per_block(int bin, int variant);
 void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, hipStream_t st);
 void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
 void launch_hub_part(int blocks, bool feat, hipStream_t st, const ScanArgs &a, const HubArgs &h);

@@ -118,3 +118,10 @@ def test_gate_no_device_reports_device_error():
     p = np.zeros(abi.GATE_PARAMS, np.float32)
     x = np.zeros((4, 8), np.float32)
     assert abi.lpa_gate_forward(p, x, 4, np.zeros(4, np.float32)) == abi.LPA_ERR_DEVICE
+
+
+def test_nmi_argument_errors_on_host():
+    a = np.zeros(4, np.int32)
+    assert abi.lpa_nmi(a, None, 4)[0] == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_nmi(a, a, -1)[0] == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_nmi(None, None, 0) == (abi.LPA_OK, 1.0)   # empty labelings need no device

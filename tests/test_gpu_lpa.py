@@ -35,11 +35,14 @@ def star(L):
     return gg.from_edges(L + 1, [(0, i) for i in range(1, L + 1)])
 
 
-def check_det(g, tau=0.05, max_iters=20, prune=True, seed=0, bins=None, flags=0):
-    say(f"det parity n={g.n} m={g.m} tau={tau} iters={max_iters} prune={prune} bins={bins} flags={flags}")
+def check_det(g, tau=0.05, max_iters=20, prune=True, seed=0, bins=None, flags=0, variants=None):
+    say(f"det parity n={g.n} m={g.m} tau={tau} iters={max_iters} prune={prune} bins={bins} flags={flags} "
+        f"variants={variants}")
     G = abi.LPAGraph(g)
     if bins is not None:
         G.set_bins(bins)
+    if variants is not None:
+        G.set_variants(variants)
     colors, nc = G.color(seed)
     ocol, onc = oracle.color(g, seed)
     assert nc == onc and np.array_equal(colors, ocol), "colouring differs from the greedy oracle"
@@ -110,6 +113,36 @@ def test_bins_do_not_change_results():
     for bins in ([2, 8, 32, 128, 512, 2048], [7, 31, 127, 511, 2047, 8191], [0, 0, 0, 0, 0, 0]):
         r2, _ = check_det(g, bins=bins)
         assert np.array_equal(r2["labels"], ref["labels"])
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_kernel_shapes_do_not_change_results(variant):
+    """Every bin's alternative kernel shapes (lanes per vertex, entries in
+    flight) give the oracle's labels; a tail of long rows takes the kernels'
+    second pass with the shrunken bins."""
+    g = gg.rmat(14, 16, seed=12)
+    check_det(g, variants=[variant] * 6)
+    check_det(g, variants=[variant] * 6, bins=[7, 31, 127, 511, 2047, 8191])
+
+
+def test_autotune_installs_a_valid_choice():
+    g = gg.rmat(14, 16, seed=13)
+    G = abi.LPAGraph(g)
+    v, ms, sch = G.autotune(0.05, 20, ASYNC)
+    assert v.shape == (6,) and np.all((v >= 0) & (v < 3)) and np.all(ms >= 0)
+    assert sch in [(16, 0, 16), (16, 2, 4), (16, 2, 8), (16, 3, 4), (16, 3, 8)]
+    colors, nc = G.color(0)
+    labels, st = G.run(0.05, 20, DET, True)
+    ref = oracle.lpa(g, order=oracle.color_order(colors, nc), tau=0.05, max_iters=20)
+    assert np.array_equal(labels, ref["labels"])
+    G.set_variants(None)
+    G.close()
+    with pytest.raises(abi.LPAError):
+        G2 = abi.LPAGraph(g)
+        try:
+            G2.set_variants([3] * 6)
+        finally:
+            G2.close()
 
 
 def test_graph_and_eager_launches_agree():
@@ -214,18 +247,30 @@ def test_async_quality_sbm_1m(mu):
     G.close()
 
 
-@pytest.mark.parametrize("phases,by_colour", [(1, 0), (8, 0), (4, 1)])
-def test_async_schedules_invariants(phases, by_colour):
+@pytest.mark.parametrize("early,sweeps,late,by_colour", [(1, 0, 1, 0), (8, 0, 8, 0), (4, 0, 4, 1), (16, 1, 1, 1),
+                                                         (3, 5, 7, 0)])
+def test_async_schedules_invariants(early, sweeps, late, by_colour):
     """Every schedule gives a valid LPA state: labels inside components,
-    converged, and (phases = 1 aside) the clique partition exactly."""
+    converged; the step count of a sweep follows the schedule."""
     g = gg.rmat(14, 16, seed=4)
     G = abi.LPAGraph(g)
-    G.set_async_phases(phases, by_colour)
-    lab, st = G.run(0.05, 20, ASYNC, True)
+    G.set_async_schedule(early, sweeps, late, by_colour)
+    lab, st = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_KERNEL_TIMING)
     comp = _components(g)
     assert np.array_equal(comp[lab], comp)
     assert st["converged"]
+    it = st["iterations"]
+    # the host polls the stop flag one sweep behind, so one more sweep is
+    # launched (its kernels find the run done and return at once)
+    steps = min(it + 1, sweeps) * early + max(0, it + 1 - sweeps) * late
+    assert it <= st["kernel_launches"]["compact"] <= steps  # one compaction per non-empty step
     G.close()
+    with pytest.raises(abi.LPAError):
+        G2 = abi.LPAGraph(g)
+        try:
+            G2.set_async_schedule(0, 2, 4)
+        finally:
+            G2.close()
 
 
 def test_async_disjoint_cliques_exact():
