@@ -25,7 +25,6 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_PROFILE = ROOT / "profiles" / "rmat24_async_hbm_traffic.md"
 
 
 def library_digest():
@@ -38,14 +37,16 @@ def library_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, tuned, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
-    or None when the kernels changed since the counters were taken."""
+    or None when the kernels or their configuration changed since the counters were taken."""
     try:
-        for line in TRAFFIC_PROFILE.read_text().splitlines():
+        for line in (ROOT / "profiles" / f"{workload}_async_hbm_traffic.md").read_text().splitlines():
             if line.startswith("machine-readable: "):
                 d = json.loads(line[len("machine-readable: "):])
                 if d.get("sources") != library_digest():
+                    return None
+                if tuned is None or d.get("variants") != tuned["variants"] or d.get("schedule") != tuned["schedule"]:
                     return None
                 return d["bytes_per_launch"].get(kernel)
     except OSError:
@@ -184,6 +185,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default schedule and kernel shapes")
+    ap.add_argument("--variants", default=None,
+                    help="kernel shape per degree bin, e.g. 2,1,1,2,2,1 (instead of autotuning; with --schedule)")
+    ap.add_argument("--schedule", default=None,
+                    help="asynchronous schedule early_steps,early_sweeps,late_steps (instead of autotuning)")
     ap.add_argument("--no-gate", action="store_true", help="skip the plain-vs-gated comparison")
     args = ap.parse_args()
 
@@ -211,7 +216,13 @@ def main():
     A = abi.LPA_MODE_ASYNC
     out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
     tuned = None
-    if not args.no_tune:
+    if args.variants or args.schedule:
+        v = [int(x) for x in args.variants.split(",")] if args.variants else [0] * 6
+        s = [int(x) for x in args.schedule.split(",")] if args.schedule else [16, 2, 4]
+        G.set_variants(v)
+        G.set_async_schedule(*s)
+        tuned = {"variants": v, "schedule": s, "seconds": 0.0, "given": True}
+    elif not args.no_tune:
         t = time.time()
         variants, bin_ms, sched = G.autotune(args.tau, args.max_iters, A)
         tuned = {"variants": [int(v) for v in variants], "schedule": list(sched), "seconds": round(time.time() - t, 2)}
@@ -259,7 +270,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "bytes_per_launch": int(dom_bytes / dom_launches), "avg_launch_ms": round(dom_ms, 5),
-                "traffic": measured_traffic(dominant),
+                "traffic": measured_traffic(dominant, tuned, f"rmat{args.scale}"),
                 "whole_sweep": {"bytes": int(total_bytes), "ms": round(sweep_ms, 3),
                                 "achieved": round(total_bytes / (sweep_ms * 1e-3) / 1e9, 1),
                                 "frac": round(total_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},

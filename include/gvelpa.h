@@ -186,7 +186,9 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
  * shape variant (per-kernel timing), keeps for each bin the fastest and
  * returns it in variant_out (int32[6], may be NULL) with the chosen kernels'
  * times in bin_ms_out (double[6], ms per run, 0 for an empty bin; may be
- * NULL).  Leaves the labels of its last trial run.
+ * NULL).  A later candidate replaces an earlier one only when it is at least
+ * 3 % faster, so near-ties keep the earlier (default) choice.  Leaves the
+ * labels of its last trial run.
  */
 int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_t *variant_out, double *bin_ms_out,
                  int32_t *schedule_out);

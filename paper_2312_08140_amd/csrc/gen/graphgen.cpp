@@ -18,6 +18,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 #include <omp.h>
@@ -49,6 +50,11 @@ typedef void *(*alloc_fn)(int kind, int64_t count);  // kind: 0 offsets i64, 1 i
 template <class Src>
 int build_csr(int64_t n, int64_t n_edges, Src src, int weighted, uint64_t wkey, alloc_fn alloc,
               int64_t *m_out) {
+  // builds of over 2^30 edges report each pass on stderr (they take minutes)
+  const bool verbose = n_edges > ((int64_t)1 << 30);
+  auto pass_done = [&](const char *what) {
+    if (verbose) std::fprintf(stderr, "graphgen: %s done (%lld edges)\n", what, (long long)n_edges);
+  };
   std::vector<int64_t> deg(n + 1, 0);
   // pass 1: degree count (each kept edge contributes to both endpoints)
 #pragma omp parallel for schedule(static, 1 << 16)
@@ -58,6 +64,7 @@ int build_csr(int64_t n, int64_t n_edges, Src src, int weighted, uint64_t wkey, 
     __atomic_fetch_add(&deg[u], 1, __ATOMIC_RELAXED);
     __atomic_fetch_add(&deg[v], 1, __ATOMIC_RELAXED);
   }
+  pass_done("degree count");
   std::vector<int64_t> off0(n + 1, 0);
   for (int64_t i = 0; i < n; ++i) off0[i + 1] = off0[i] + deg[i];
   int64_t total = off0[n];
@@ -73,6 +80,7 @@ int build_csr(int64_t n, int64_t n_edges, Src src, int weighted, uint64_t wkey, 
     scratch[pu] = (int32_t)v;
     scratch[pv] = (int32_t)u;
   }
+  pass_done("scatter");
   // pass 3: sort and dedupe every row in place
 #pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t i = 0; i < n; ++i) {
@@ -80,6 +88,7 @@ int build_csr(int64_t n, int64_t n_edges, Src src, int weighted, uint64_t wkey, 
     std::sort(b, e);
     deg[i] = std::unique(b, e) - b;
   }
+  pass_done("row sort and dedupe");
   int64_t *off = (int64_t *)alloc(0, n + 1);
   if (!off) return -1;
   off[0] = 0;
@@ -179,7 +188,7 @@ int gg_rmat(int scale, int64_t edge_factor, double a, double b, double c, uint64
             alloc_fn alloc, int64_t *n_out, int64_t *m_out) {
   if (scale < 1 || scale > 30 || edge_factor < 1 || a < 0 || b < 0 || c < 0 || a + b + c > 1.0) return -2;
   const int64_t n = (int64_t)1 << scale;
-  const int64_t n_edges = edge_factor << scale;
+  const int64_t n_edges = (int64_t)edge_factor << scale;
   const uint64_t ta = (uint64_t)std::llround(a * 4294967296.0);
   const uint64_t tb = (uint64_t)std::llround((a + b) * 4294967296.0);
   const uint64_t tc = (uint64_t)std::llround((a + b + c) * 4294967296.0);
