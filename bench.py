@@ -169,6 +169,45 @@ def gate_comparison(args, G, g, runs, q_async, out):
     return res
 
 
+def batch_workload(args):
+    """Many independent SBMs of uneven size in one handle (block-diagonal CSR,
+    each graph with its own stop test, every run one HIP graph launch):
+    default tuning vs autotuned, asynchronous and deterministic."""
+    import torch
+    from paper_2312_08140_amd import abi, graphgen
+    t = time.time()
+    csr, vptr = graphgen.sbm_batch(args.batch, master_seed=7, seed_base=10000)
+    log(f"batch of {args.batch} SBMs: n={csr.n} m={csr.m} in {time.time() - t:.1f}s")
+    B = abi.LPABatch(csr, vptr)
+    out = torch.empty(csr.n, dtype=torch.int32, device="cuda:0")
+    res = {"workload": f"sbm_batch{args.batch}_seed7", "graphs": args.batch, "n": csr.n, "m": csr.m}
+
+    def timed(mode, label):
+        B.run(args.tau, args.max_iters, mode, True, labels_out=out)
+        ms, st = [], None
+        for _ in range(5):
+            _, st = B.run(args.tau, args.max_iters, mode, True, labels_out=out)
+            ms.append(st["total_ms"])
+        it, conv = B.graph_stats()
+        med = float(np.median(ms))
+        r = {"time_ms": round(med, 3), "entries_per_s": round(sum(st["edges_scanned"]) / (med * 1e-3), 1),
+             "m_over_time": round(csr.m / (med * 1e-3), 1), "sweeps_max": int(it.max()),
+             "sweeps_mean": round(float(it.mean()), 3), "graphs_converged": int(conv.sum()),
+             "modularity_union": round(B.modularity(out), 6)}
+        log(f"batch {label}: {r}")
+        return r
+    res["async_default"] = timed(abi.LPA_MODE_ASYNC, "async default")
+    res["det_default"] = timed(abi.LPA_MODE_DETERMINISTIC, "det default")
+    if not args.no_tune:
+        t = time.time()
+        v, _, sch = B.autotune(args.tau, args.max_iters, abi.LPA_MODE_ASYNC)
+        res["tuning"] = {"variants": [int(x) for x in v], "schedule": list(sch), "seconds": round(time.time() - t, 2)}
+        res["async_tuned"] = timed(abi.LPA_MODE_ASYNC, "async tuned")
+        res["det_tuned"] = timed(abi.LPA_MODE_DETERMINISTIC, "det tuned")
+    B.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +229,8 @@ def main():
     ap.add_argument("--schedule", default=None,
                     help="asynchronous schedule early_steps,early_sweeps,late_steps (instead of autotuning)")
     ap.add_argument("--no-gate", action="store_true", help="skip the plain-vs-gated comparison")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="also run the batched workload of this many SBMs (4096 = the uneven SBM batch)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -289,6 +330,8 @@ def main():
                    sweep0_edges_per_s=round(g.m / (sd2["ms"][0] * 1e-3), 1) if sd2["iterations"] else None)
         log(f"det: {det} ({time.time() - t:.1f}s)")
 
+    batch = batch_workload(args) if args.batch else None
+
     gated = None
     if not args.no_gate:
         gated = gate_comparison(args, G, g, runs, q_async, out)
@@ -315,7 +358,7 @@ def main():
         "time_to_converge_ms": {"median": round(float(np.median(ttc)), 3), "min": round(float(np.min(ttc)), 3)},
         "sweeps": runs[0]["iterations"], "modularity": round(q_async, 6),
         "m_over_time_to_converge": round(g.m / (np.median(ttc) * 1e-3), 1),
-        "deterministic": det, "tuning": tuned, "gated": gated, "roofline": roofline, "cpu_baseline": cpu,
+        "deterministic": det, "tuning": tuned, "gated": gated, "batch": batch, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
     G.close()

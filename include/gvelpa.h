@@ -70,8 +70,13 @@ enum {
                                    run counts as such); this only adds work that cannot change a label */
   LPA_FLAG_ONE_LAUNCH = 256,    /* lpa_run: replay all max_iters sweeps as one HIP graph launch (sweeps after
                                    the stop test exit at once); batched handles always do */
-  LPA_FLAG_VERIFY_FULL = 512    /* lpa_run: the verification sweep processes every vertex (same result as the
+  LPA_FLAG_VERIFY_FULL = 512,   /* lpa_run: the verification sweep processes every vertex (same result as the
                                    default, at the cost of a whole sweep) */
+  LPA_FLAG_NO_REORDER = 1024    /* lpa_create, lpa_batch_create: keep vertices in id order inside the library.
+                                   By default they are stored in decreasing degree order (within each graph of
+                                   a batch) so that frequently gathered labels share cache lines; labels keep
+                                   their values and every array crosses the boundary in id order, so results
+                                   are the same */
 };
 
 #define LPA_MAX_SWEEPS_RECORDED 64
@@ -182,7 +187,7 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
  * among the schedules (early steps, early sweeps, late steps) = (16, 0, 16),
  * (16, 2, 4), (16, 2, 8), (16, 3, 4), (16, 3, 8) it installs the fastest
  * whose modularity stays within 0.002 of the first's (schedule_out: int32[3],
- * may be NULL; batched handles keep theirs).  Then it times every kernel
+ * may be NULL).  Then it times every kernel
  * shape variant (per-kernel timing), keeps for each bin the fastest and
  * returns it in variant_out (int32[6], may be NULL) with the chosen kernels'
  * times in bin_ms_out (double[6], ms per run, 0 for an empty bin; may be
@@ -341,6 +346,11 @@ void lpa_destroy(lpa_graph *g);
 
 /* lpa_status_string - static message for a status code. */
 const char *lpa_status_string(int status);
+
+/* lpa_last_error_detail - for the last LPA_ERR_DEVICE returned on this
+ * thread, the HIP error and the call that failed ("" if none); valid until
+ * the next failing call on the thread. */
+const char *lpa_last_error_detail(void);
 
 #ifdef __cplusplus
 }

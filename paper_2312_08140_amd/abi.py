@@ -42,6 +42,7 @@ LPA_FLAG_TRACE = 64
 LPA_FLAG_EXACT_MARKS = 128
 LPA_FLAG_ONE_LAUNCH = 256
 LPA_FLAG_VERIFY_FULL = 512
+LPA_FLAG_NO_REORDER = 1024
 
 GATE_PARAMS = 1377
 GATE_FEATURES = 8
@@ -130,6 +131,7 @@ SIGNATURES = {
     "lpa_nmi": (ctypes.c_int, [_vp, _vp, _i64, ctypes.POINTER(_f64), ctypes.c_int, _vp, ctypes.c_uint]),
     "lpa_destroy": (None, [_vp]),
     "lpa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "lpa_last_error_detail": (ctypes.c_char_p, []),
 }
 
 _lib = None
@@ -153,7 +155,11 @@ def load():
 class LPAError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         self.code = code
-        super().__init__(f"{what}: {status_string(code)} ({code})")
+        detail = ""
+        if code == LPA_ERR_DEVICE:
+            d = load().lpa_last_error_detail().decode()
+            detail = f" [{d}]" if d else ""
+        super().__init__(f"{what}: {status_string(code)} ({code}){detail}")
 
 
 def status_string(code: int) -> str:
@@ -321,13 +327,14 @@ class LPAGraph:
     """Owns one library handle for a CSR graph (numpy host arrays or torch device tensors)."""
 
     def __init__(self, csr=None, *, n=None, offsets=None, indices=None, weights=None, device: int = 0,
-                 stream=None, check_symmetric: bool = False):
+                 stream=None, check_symmetric: bool = False, reorder: bool = True):
         if csr is not None:
             n, offsets, indices, weights = csr.n, csr.offsets, csr.indices, csr.weights
         self.n = int(n)
         self.device = device
         on_device = hasattr(offsets, "data_ptr")
         flags = (LPA_FLAG_DEVICE_PTRS if on_device else 0) | (LPA_FLAG_CHECK_SYMMETRIC if check_symmetric else 0)
+        flags |= 0 if reorder else LPA_FLAG_NO_REORDER
         if not on_device:
             offsets = np.ascontiguousarray(offsets, dtype=np.int64)
             indices = np.ascontiguousarray(indices, dtype=np.int32)
@@ -497,7 +504,7 @@ class LPABatch(LPAGraph):
     """Many independent graphs (block-diagonal CSR) in one handle; graph g owns
     vertices [graph_vptr[g], graph_vptr[g+1])."""
 
-    def __init__(self, csr, graph_vptr, device: int = 0, stream=None):
+    def __init__(self, csr, graph_vptr, device: int = 0, stream=None, reorder: bool = True):
         self.n = int(csr.n)
         self.device = device
         self.vptr = np.ascontiguousarray(graph_vptr, dtype=np.int64)
@@ -508,7 +515,8 @@ class LPABatch(LPAGraph):
         self._keep = None
         self.m = int(idx.shape[0])
         self.stream = _current_stream(device) if stream is None else stream
-        rc, h = lpa_batch_create(self.ngraphs, self.vptr, self.n, self.m, off, idx, w, device, self.stream, 0)
+        rc, h = lpa_batch_create(self.ngraphs, self.vptr, self.n, self.m, off, idx, w, device, self.stream,
+                                 0 if reorder else LPA_FLAG_NO_REORDER)
         _check(rc, "lpa_batch_create")
         self.handle = h
 

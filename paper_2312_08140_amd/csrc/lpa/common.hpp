@@ -158,14 +158,17 @@ struct Ctl {
 //   x3 = 1 if v changed when last processed
 //   x7 = min(s - sweep of last processing, 8) / 8
 // with W1 >= W2 the two largest label weights of v's last scan and K_v its
-// weighted degree.  x0-x3, x5, x6 are stored per vertex when it is processed.
+// weighted degree.  x0-x3, x5, x6 are stored per vertex when it is processed,
+// in a 32-byte record with the sweep of that processing (written with two
+// 16-byte stores): {x0, x1, x2, x3}, {x5, x6, last sweep (int bits, -1 =
+// never), 0}.
 constexpr int NFEAT = 8;
-constexpr int NSTORED = 6;
+constexpr int FEAT_STRIDE = 8;  // floats per vertex record
+constexpr int FEAT_LASTP = 6;   // slot of the last sweep
 constexpr int GATE_PARAMS = 32 * 8 + 32 + 32 * 32 + 32 + 32 + 1;  // 1377
 
 struct FeatArgs {
-  float *feat;         // [n][NSTORED]: x0 x1 x2 x3 x5 x6 of the last processing
-  int16_t *lastp;      // sweep of the last processing, -1 = never
+  float *feat;         // [n][FEAT_STRIDE] records of the last processing
   const uint32_t *K;   // weighted degrees
   float *tx;           // trace features [tcap][NFEAT]
   uint8_t *ty;         // trace targets (1 = the vertex changed)
@@ -175,6 +178,8 @@ struct FeatArgs {
   int trace;
   int max_iters;
 };
+
+__device__ __forceinline__ int record_lastp(const float *rec) { return __float_as_int(rec[FEAT_LASTP]); }
 
 __device__ __forceinline__ void decision_features(const float *st, int lastp, int s, int max_iters, float *x) {
   x[0] = st[0];

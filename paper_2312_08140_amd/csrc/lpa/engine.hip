@@ -19,16 +19,26 @@
 
 using namespace gvelpa;
 
+namespace gvelpa {
+// The failing HIP call behind the last LPA_ERR_DEVICE of this thread.
+void note_hip_error(int err, const char *what, const char *file, int line);
+}  // namespace gvelpa
+
 namespace {
 
 struct Status {
   int code;
 };
 
+thread_local std::string last_error;
+
 #define HIP_OK(expr)                                      \
   do {                                                    \
     hipError_t _e = (expr);                               \
-    if (_e != hipSuccess) throw Status{LPA_ERR_DEVICE};   \
+    if (_e != hipSuccess) {                               \
+      note_hip_error(_e, #expr, __FILE__, __LINE__);      \
+      throw Status{LPA_ERR_DEVICE};                       \
+    }                                                     \
   } while (0)
 
 enum TimedKind {
@@ -73,7 +83,7 @@ struct lpa_graph {
     int32_t *list = nullptr;          // vertices by (step, bin)
     std::vector<int64_t> start;       // nphase * NBINS + 1 list bounds
     std::vector<int64_t> hub_chunks, hub_parts;  // hub work per step
-  } sched[2];
+  } sched[3];  // early, late, verification (one step: it changes few labels)
   int early_sweeps = 2;
   bool async_by_colour = true;      // steps made of consecutive colour classes (else a hash of the id)
   // deterministic schedule
@@ -126,8 +136,10 @@ struct lpa_graph {
   bool gate_loaded = false;
   bool gate_active = false;       // the sweeps being emitted apply the gate
   uint8_t *gskip = nullptr;       // per vertex: gated out in the current sweep
-  float *feat = nullptr;          // [n][NSTORED]
-  int16_t *lastp = nullptr;
+  float *feat = nullptr;          // [n][FEAT_STRIDE] records
+  // storage order (reorder.hip): position p holds vertex orig[p]; vertex v sits at pos[v]
+  int32_t *orig = nullptr, *pos = nullptr;
+  int32_t *perm_tmp = nullptr;    // staging of permuted copies in and out
   float *tx = nullptr;            // trace
   uint8_t *ty = nullptr;
   u64 *tcount = nullptr;
@@ -473,12 +485,19 @@ void ensure_lists(lpa_graph *g) {
   if (g->async_by_colour) ensure_colored(g, g->colored ? g->color_seed : 0u);
   build_async(g, g->sched[0]);
   if (g->sched[1].nphase != g->sched[0].nphase) build_async(g, g->sched[1]);
+  g->sched[2].nphase = 1;
+  if (g->sched[0].nphase != 1 && g->sched[1].nphase != 1) build_async(g, g->sched[2]);
   g->lists_ready = true;
 }
 
-// the schedule of asynchronous sweep s (0-based; verification counts as late)
-const lpa_graph::AsyncSched &async_sched(const lpa_graph *g, int late) {
-  return late && g->sched[1].nphase != g->sched[0].nphase ? g->sched[1] : g->sched[0];
+// the schedule of an asynchronous sweep: 0 early, 1 late, 2 verification
+const lpa_graph::AsyncSched &async_sched(const lpa_graph *g, int which) {
+  const lpa_graph::AsyncSched &e = g->sched[0], &l = g->sched[1];
+  if (which == 0) return e;
+  if (which == 1) return l.nphase == e.nphase ? e : l;
+  if (e.nphase == 1) return e;  // verification: a single step
+  if (l.nphase == 1) return l;
+  return g->sched[2];
 }
 
 int max_phases(const lpa_graph *g) { return std::max(g->sched[0].nphase, g->sched[1].nphase); }
@@ -493,13 +512,14 @@ void ensure_colored(lpa_graph *g, uint32_t seed) {
   constexpr int MAX_ROUNDS = 1 << 22, BATCH = 64;
   int32_t *counts = dalloc_n<int32_t>(g, MAX_ROUNDS + 2);
   HIP_OK(hipMemsetAsync(counts, 0, sizeof(int32_t) * (MAX_ROUNDS + 2), g->stream));
-  launch_color_init(g->off, g->idx, g->color, pk, pending, work[0], counts, g->n, seed, g->stream);
+  launch_color_init(g->off, g->idx, g->color, pk, pending, work[0], counts, g->n, seed, g->orig, g->stream);
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + 3) / 4, (int64_t)g->cu_count * 16));
   int r = 0;
   for (;;) {
     // rounds are queued in batches; a round with an empty list exits at once
     for (int k = 0; k < BATCH && r < MAX_ROUNDS; ++k, ++r)
       launch_color_round(g->off, g->idx, g->color, pk, pending, work[r & 1], work[(r + 1) & 1], counts, r, blocks,
+                         g->orig,
                          g->stream);
     int32_t left = 0;
     HIP_OK(hipMemcpyAsync(&left, counts + r, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
@@ -561,7 +581,6 @@ BatchArgs batch_args(lpa_graph *g) {
 FeatArgs feat_args(lpa_graph *g, int max_iters, bool trace) {
   FeatArgs f{};
   f.feat = g->feat;
-  f.lastp = g->lastp;
   f.K = g->K;
   f.tx = g->tx;
   f.ty = g->ty;
@@ -670,19 +689,21 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late) {
 // once after the stop test holds), captured once per (mode, prune, sweeps).
 // A graph of `sweeps` consecutive sweeps starting at sweep `first` (which
 // selects the asynchronous schedule of each).
-hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps, int first) {
+hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps, int first, int verify = 0) {
   // captured kernels embed the feature arguments (trace switch, sweep cap)
   const int fcode = g->feat_on ? 1 + 2 * g->cur_feat.trace + 4 * g->gate_active + 8 * g->cur_feat.max_iters : 0;
   // only the early/late split of the covered sweeps matters
   const int fkey = mode == LPA_MODE_DETERMINISTIC ? 0
+                   : verify                       ? 2
                    : sweeps == 1                  ? (first >= g->early_sweeps ? 1 : 0)
-                                                  : 2 + std::min(first, g->early_sweeps);
+                                                  : 3 + std::min(first, g->early_sweeps);
   auto key = std::make_tuple(mode, prune, sweeps, fcode, fkey);
   auto it = g->graphs.find(key);
   if (it != g->graphs.end()) return it->second;
   hipGraph_t graph = nullptr;
   HIP_OK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-  for (int s = 0; s < sweeps; ++s) emit_sweep(g, g->cap_stream, mode, prune, first + s >= g->early_sweeps);
+  for (int s = 0; s < sweeps; ++s)
+    emit_sweep(g, g->cap_stream, mode, prune, verify ? 2 : (first + s >= g->early_sweeps ? 1 : 0));
   HIP_OK(hipStreamEndCapture(g->cap_stream, &graph));
   hipGraphExec_t exec = nullptr;
   hipError_t e = hipGraphInstantiateWithFlags(&exec, graph, 0);
@@ -702,6 +723,51 @@ void copy_out(lpa_graph *g, void *dst, const void *src, size_t bytes, unsigned f
                                                                          : hipMemcpyDeviceToHost, g->stream));
 }
 
+// Vertex arrays cross the boundary in vertex-id order; inside they are kept in
+// storage order (position p holds vertex orig[p]).
+int32_t *perm_stage(lpa_graph *g) {
+  if (!g->perm_tmp) g->perm_tmp = dalloc_n<int32_t>(g, g->n);
+  return g->perm_tmp;
+}
+
+template <class T>
+void gather_dev(T *dst, const T *src, const int32_t *index, int64_t n, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) launch_gather_i32((int32_t *)dst, (const int32_t *)src, index, n, st);
+  else launch_gather_u8((uint8_t *)dst, (const uint8_t *)src, index, n, st);
+}
+
+// dst[p] = src[orig[p]] (src: caller order, host or device per flags)
+template <class T>
+void vertex_in(lpa_graph *g, T *dst, const T *src, unsigned flags) {
+  if (!g->orig) {
+    copy_in(g, dst, src, sizeof(T) * g->n, flags);
+    return;
+  }
+  const T *from = src;
+  if (!(flags & LPA_FLAG_DEVICE_PTRS)) {
+    T *stage = (T *)perm_stage(g);
+    HIP_OK(hipMemcpyAsync(stage, src, sizeof(T) * g->n, hipMemcpyHostToDevice, g->stream));
+    from = stage;
+  }
+  gather_dev<T>(dst, from, g->orig, g->n, g->stream);
+}
+
+// dst[v] = src[pos[v]] (dst: caller order, host or device per flags)
+template <class T>
+void vertex_out(lpa_graph *g, T *dst, const T *src, unsigned flags) {
+  if (!g->orig) {
+    copy_out(g, dst, src, sizeof(T) * g->n, flags);
+    return;
+  }
+  if (flags & LPA_FLAG_DEVICE_PTRS) {
+    gather_dev<T>(dst, src, g->pos, g->n, g->stream);
+  } else {
+    T *stage = (T *)perm_stage(g);
+    gather_dev<T>(stage, src, g->pos, g->n, g->stream);
+    HIP_OK(hipMemcpyAsync(dst, stage, sizeof(T) * g->n, hipMemcpyDeviceToHost, g->stream));
+  }
+}
+
 template <class Fn>
 int run_guarded(lpa_graph *g, Fn &&fn) {
   if (!g) return LPA_ERR_INVALID_ARG;
@@ -717,9 +783,17 @@ int run_guarded(lpa_graph *g, Fn &&fn) {
 
 }  // namespace
 
+void gvelpa::note_hip_error(int err, const char *what, const char *file, int line) {
+  const char *base = std::strrchr(file, '/');
+  last_error = std::string(hipGetErrorString((hipError_t)err)) + " in " + what + " (" + (base ? base + 1 : file) +
+               ":" + std::to_string(line) + ")";
+}
+
 // ======================================================================== ABI
 
 extern "C" {
+
+const char *lpa_last_error_detail(void) { return last_error.c_str(); }
 
 const char *lpa_status_string(int status) {
   switch (status) {
@@ -751,8 +825,11 @@ void lpa_destroy(lpa_graph *g) {
   delete g;
 }
 
-int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, const int32_t *indices,
-               const float *weights, int device, void *hip_stream, unsigned flags) {
+// lpa_create, with the graph ranges of a batch (n_graphs = 0: one graph):
+// the storage order keeps every graph's vertices inside its range.
+static int create_graph(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, const int32_t *indices,
+                        const float *weights, int device, void *hip_stream, unsigned flags, int32_t n_graphs,
+                        const int64_t *graph_vptr) {
   if (!out) return LPA_ERR_INVALID_ARG;
   *out = nullptr;
   if (n < 0 || m < 0 || !offsets || (m > 0 && !indices)) return LPA_ERR_INVALID_ARG;
@@ -847,6 +924,47 @@ int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, co
       HIP_OK(hipStreamSynchronize(g->stream));
       dfree(g, wtmp);
     }
+    // storage order: decreasing degree (within each graph of a batch)
+    if (!(flags & LPA_FLAG_NO_REORDER) && n > 1 && m > 0 && n < ((int64_t)1 << 31) - 1) {
+      int32_t *gid = nullptr;
+      int64_t *dvptr = nullptr;
+      if (n_graphs > 0) {
+        dvptr = dalloc_n<int64_t>(g, n_graphs + 1);
+        gid = dalloc_n<int32_t>(g, n);
+        HIP_OK(hipMemcpyAsync(dvptr, graph_vptr, sizeof(int64_t) * (n_graphs + 1), hipMemcpyHostToDevice,
+                              g->stream));
+        BatchArgs ba{};
+        ba.ngraphs = n_graphs;
+        ba.vptr = dvptr;
+        ba.gid = gid;
+        launch_batch_gid(ba, g->stream);
+      }
+      g->orig = dalloc_n<int32_t>(g, n);
+      g->pos = dalloc_n<int32_t>(g, n);
+      int64_t *noff = dalloc_n<int64_t>(g, n + 1);
+      u64 *keys = dalloc_n<u64>(g, 2 * n + 1);
+      const int64_t tb = order_temp_bytes(n);
+      void *scr = dalloc(g, (size_t)std::max<int64_t>(tb, 1));
+      HIP_OK(build_order(g->off, gid, n, g->orig, g->pos, noff, keys, scr, tb, g->stream));
+      int32_t *nidx = dalloc_n<int32_t>(g, m);
+      void *nw = g->wk == W_UNIT ? nullptr : dalloc(g, (size_t)m * (g->wk == W_U8 ? 1 : 4));
+      launch_permute_rows(g->off, g->idx, g->w, g->wk, g->orig, g->pos, noff, nidx, nw, n, g->stream);
+      HIP_OK(hipGetLastError());
+      HIP_OK(hipStreamSynchronize(g->stream));
+      dfree(g, scr);
+      dfree(g, keys);
+      dfree(g, gid);
+      dfree(g, dvptr);
+      if (!dev) {  // borrowed arrays stay with the caller
+        dfree(g, g->off);
+        dfree(g, g->idx);
+      }
+      dfree(g, g->w);
+      g->off = noff;
+      g->idx = nidx;
+      g->w = nw;
+      HIP_OK(hipMemcpy(g->h_off.data(), noff, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    }
     g->K = dalloc_n<uint32_t>(g, n);
     launch_weighted_degree(g->off, g->w, g->wk, n, g->K, chk, g->stream);
     const bool dev_sym = dev && (flags & LPA_FLAG_CHECK_SYMMETRIC);
@@ -864,7 +982,7 @@ int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, co
     g->F = dalloc_n<uint8_t>(g, n);
     g->ctl = dalloc_n<Ctl>(g, 1);
     HIP_OK(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream));
-    launch_init_state(g->off, g->C, g->F, n, 1, 1, 0, g->stream);
+    launch_init_state(g->off, g->C, g->F, n, 1, 1, 0, g->orig, g->stream);
     HIP_OK(hipStreamSynchronize(g->stream));
     return LPA_OK;
   });
@@ -874,6 +992,11 @@ int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, co
   }
   *out = g;
   return LPA_OK;
+}
+
+int lpa_create(lpa_graph **out, int64_t n, int64_t m, const int64_t *offsets, const int32_t *indices,
+               const float *weights, int device, void *hip_stream, unsigned flags) {
+  return create_graph(out, n, m, offsets, indices, weights, device, hip_stream, flags, 0, nullptr);
 }
 
 int lpa_batch_create(lpa_graph **out, int32_t n_graphs, const int64_t *graph_vptr, int64_t n, int64_t m,
@@ -888,7 +1011,7 @@ int lpa_batch_create(lpa_graph **out, int32_t n_graphs, const int64_t *graph_vpt
     live += graph_vptr[k + 1] > graph_vptr[k];
   }
   lpa_graph *g = nullptr;
-  int rc = lpa_create(&g, n, m, offsets, indices, weights, device, hip_stream, flags);
+  int rc = create_graph(&g, n, m, offsets, indices, weights, device, hip_stream, flags, n_graphs, graph_vptr);
   if (rc != LPA_OK) return rc;
   rc = run_guarded(g, [&]() -> int {
     // entries may not cross graphs (checked on the host offsets copy and the indices)
@@ -1046,7 +1169,7 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
   int rc = LPA_OK;
   // 1. Asynchronous schedule: the fastest candidate whose modularity stays
   //    within 0.002 of the all-16-step schedule's.
-  if (mode == LPA_MODE_ASYNC && !g->ngraphs) {
+  if (mode == LPA_MODE_ASYNC) {
     static const int32_t cand[][3] = {{16, 0, 16}, {16, 2, 4}, {16, 2, 8}, {16, 3, 4}, {16, 3, 8}};
     double q_ref = 0.0, best_ms = 1e300;
     int best = 0;
@@ -1142,7 +1265,7 @@ int lpa_color(lpa_graph *g, uint32_t seed, int32_t *colors_out, unsigned flags, 
   return run_guarded(g, [&]() -> int {
     ensure_colored(g, seed);
     if (colors_out && g->n) {
-      copy_out(g, colors_out, g->color, sizeof(int32_t) * g->n, flags);
+      vertex_out<int32_t>(g, colors_out, g->color, flags);
       HIP_OK(hipStreamSynchronize(g->stream));
     }
     if (num_colors) *num_colors = g->ncol;
@@ -1172,7 +1295,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     }
     if (init_labels && g->n) {
       // labels must be vertex ids
-      copy_in(g, g->C, init_labels, sizeof(int32_t) * g->n, flags);
+      vertex_in<int32_t>(g, g->C, init_labels, flags);
       int32_t *bad = (int32_t *)((char *)g->scratch_small + 2048);
       HIP_OK(hipMemsetAsync(bad, 0, sizeof(int32_t), g->stream));
       launch_check_labels(g->C, g->n, bad, g->stream);
@@ -1181,9 +1304,10 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       HIP_OK(hipStreamSynchronize(g->stream));
       if (hb) return LPA_ERR_INVALID_ARG;
     }
-    if (init_flags && g->n) copy_in(g, g->F, init_flags, g->n, flags);
+    if (init_flags && g->n) vertex_in<uint8_t>(g, g->F, init_flags, flags);
     if (g->n)
       launch_init_state(g->off, g->C, g->F, g->n, init_labels ? 0 : 1, init_flags ? 0 : 1, max_iters > 0 ? 1 : 0,
+                        g->orig,
                         g->stream);
     // A batched handle replays the whole run as one graph launch; otherwise
     // one sweep per launch, with the stop test polled one sweep behind.
@@ -1198,10 +1322,9 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     if (gate && !g->gskip) g->gskip = dalloc_n<uint8_t>(g, g->n);
     if (g->feat_on) {
       if (!g->feat) {
-        g->feat = dalloc_n<float>(g, g->n * NSTORED);
-        g->lastp = dalloc_n<int16_t>(g, g->n);
+        g->feat = dalloc_n<float>(g, g->n * FEAT_STRIDE);
       }
-      launch_fill_i16(g->lastp, g->n, (int16_t)-1, g->stream);
+      launch_feat_reset(g->feat, g->n, g->stream);
     }
     g->cur_feat = feat_args(g, max_iters, trace);
     // per-sweep graphs of the early and the late asynchronous schedule
@@ -1213,7 +1336,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     auto launch_sweep = [&](int s) {
       const int late = s >= g->early_sweeps;
       if (exec) HIP_OK(hipGraphLaunch(late ? exec_late : exec, g->stream));
-      else emit_sweep(g, g->stream, mode, prune, late);
+      else emit_sweep(g, g->stream, mode, prune, late ? 1 : 0);
     };
     HIP_OK(hipEventRecord(e1, g->stream));
     HIP_OK(hipEventSynchronize(e1));
@@ -1258,10 +1381,15 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       // fallback sweeps run the plain kernels (the plain late-sweep graph)
       g->feat_on = false;
       g->gate_active = false;
-      if (use_graph) exec_late = sweep_graph(g, mode, prune, 1, g->early_sweeps);
+      hipGraphExec_t exec_verify = nullptr;
+      if (use_graph) {
+        exec_late = sweep_graph(g, mode, prune, 1, g->early_sweeps);
+        exec_verify = sweep_graph(g, mode, prune, 1, g->early_sweeps, 1);
+      }
       for (int attempt = 0; attempt < 2; ++attempt) {
         launch_set_phase(g->ctl, (flags & LPA_FLAG_VERIFY_FULL) ? 2 : 1, 0, 0, g->host_done_dev, g->stream);
-        launch_sweep(max_iters);
+        if (exec_verify) HIP_OK(hipGraphLaunch(exec_verify, g->stream));
+        else emit_sweep(g, g->stream, mode, prune, 2);
         int32_t vflag = 0;
         HIP_OK(hipMemcpyAsync(&vflag, &g->ctl->verified, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
         HIP_OK(hipStreamSynchronize(g->stream));
@@ -1282,7 +1410,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     HIP_OK(hipEventElapsedTime(&run_ms, t0, t1));
     g->has_labels = true;
     if (labels_out && g->n) {
-      copy_out(g, labels_out, g->C, sizeof(int32_t) * g->n, flags);
+      vertex_out<int32_t>(g, labels_out, g->C, flags);
       HIP_OK(hipStreamSynchronize(g->stream));
     }
     if (stats) {
@@ -1339,7 +1467,7 @@ int lpa_get_flags(const lpa_graph *gc, uint8_t *flags_out, unsigned flags) {
   return run_guarded(g, [&]() -> int {
     if (!flags_out) return LPA_ERR_INVALID_ARG;
     if (g->n) {
-      copy_out(g, flags_out, g->F, g->n, flags);
+      vertex_out<uint8_t>(g, flags_out, g->F, flags);
       HIP_OK(hipStreamSynchronize(g->stream));
     }
     return LPA_OK;
@@ -1357,10 +1485,10 @@ int lpa_modularity(const lpa_graph *gc, const int32_t *labels, unsigned flags, d
     const int32_t *C = g->C;
     int32_t *tmp = nullptr;
     if (labels) {
-      if (flags & LPA_FLAG_DEVICE_PTRS) C = labels;
+      if ((flags & LPA_FLAG_DEVICE_PTRS) && !g->orig) C = labels;
       else {
         tmp = dalloc_n<int32_t>(g, g->n);
-        HIP_OK(hipMemcpyAsync(tmp, labels, sizeof(int32_t) * g->n, hipMemcpyHostToDevice, g->stream));
+        vertex_in<int32_t>(g, tmp, labels, flags);
         C = tmp;
       }
     }

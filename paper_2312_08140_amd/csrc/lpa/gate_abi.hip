@@ -20,9 +20,13 @@ struct Fail {
   int code;
 };
 
-#define GATE_HIP(expr)                                  \
-  do {                                                  \
-    if ((expr) != hipSuccess) throw Fail{LPA_ERR_DEVICE}; \
+#define GATE_HIP(expr)                                       \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) {                                  \
+      note_hip_error(_e, #expr, __FILE__, __LINE__);         \
+      throw Fail{LPA_ERR_DEVICE};                            \
+    }                                                        \
   } while (0)
 
 // Device buffers of one call, freed on every exit path.

@@ -263,7 +263,9 @@ __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
         t = merge_stats(t, o);
       }
       t = group_stats<64>(t);
-      if (lane == 0) write_features(a.f, v, sweep, a.off[v + 1] - a.off[v], t, h.own_w[i], changed != 0);
+      if (lane == 0)
+        write_features(a.f, v, sweep, a.off[v + 1] - a.off[v], t, h.own_w[i], changed != 0, a.f.K[v],
+                       record_lastp(a.f.feat + (int64_t)v * FEAT_STRIDE));
     }
     if (lane == 0) {
       h.changed[i] = changed;

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "gvelpa.h"
+#include "sweep_kernels.hpp"
 
 namespace {
 
@@ -22,9 +23,13 @@ struct Fail {
   int code;
 };
 
-#define NMI_HIP(expr)                                     \
-  do {                                                    \
-    if ((expr) != hipSuccess) throw Fail{LPA_ERR_DEVICE}; \
+#define NMI_HIP(expr)                                        \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) {                                  \
+      gvelpa::note_hip_error(_e, #expr, __FILE__, __LINE__); \
+      throw Fail{LPA_ERR_DEVICE};                            \
+    }                                                        \
   } while (0)
 
 constexpr int RED_BLOCKS = 1024;

@@ -1,0 +1,106 @@
+// Storage order of the vertices.  The library keeps vertices in decreasing
+// degree order (within each graph of a batch), so that the labels gathered
+// most often - those of high-degree vertices - share cache lines.  Labels keep
+// their values (original vertex ids), so the method's results do not change;
+// only positions do: position p holds original vertex order[p], and original
+// vertex v sits at position pos[v].
+#include <hipcub/hipcub.hpp>
+
+#include "sweep_kernels.hpp"
+
+namespace gvelpa {
+
+// key = graph << 32 | (0xFFFFFFFF - degree): ascending key = by graph, then by
+// decreasing degree; the radix sort is stable, so ties keep id order.
+__global__ void k_order_keys(const int64_t *off, const int32_t *gid, int64_t n, u64 *key, int32_t *val) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const u64 deg = (u64)(off[v + 1] - off[v]);
+    const u64 g = gid ? (u64)(uint32_t)gid[v] : 0ull;
+    key[v] = (g << 32) | (0xFFFFFFFFull - (deg < 0xFFFFFFFFull ? deg : 0xFFFFFFFFull));
+    val[v] = (int32_t)v;
+  }
+}
+
+__global__ void k_inverse(const int32_t *order, int64_t n, int32_t *pos, int64_t *ndeg, const int64_t *off) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ndeg[n] = 0;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = order[p];
+    pos[v] = (int32_t)p;
+    ndeg[p] = off[v + 1] - off[v];
+  }
+}
+
+// New row p = old row order[p], neighbours renamed to positions; one wave per row.
+template <int WK>
+__global__ __launch_bounds__(256) void k_permute_rows(const int64_t *off, const int32_t *idx, const void *w,
+                                                      const int32_t *order, const int32_t *pos, const int64_t *noff,
+                                                      int32_t *nidx, void *nw, int64_t n) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); p < n; p += (int64_t)gridDim.x * 4) {
+    const int32_t v = order[p];
+    const int64_t b = off[v], e = off[v + 1], nb = noff[p];
+    for (int64_t k = b + lane; k < e; k += 64) {
+      nidx[nb + (k - b)] = pos[idx[k]];
+      if constexpr (WK == W_U8) ((uint8_t *)nw)[nb + (k - b)] = ((const uint8_t *)w)[k];
+      if constexpr (WK == W_U32) ((uint32_t *)nw)[nb + (k - b)] = ((const uint32_t *)w)[k];
+    }
+  }
+}
+
+template <class T>
+__global__ void k_gather(T *dst, const T *src, const int32_t *index, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[index[i]];
+}
+
+static int grid(int64_t n, int per, int cap = 16384) {
+  int64_t b = (n + per - 1) / per;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+// bytes of temporary storage the sort and the scan of build_order need
+int64_t order_temp_bytes(int64_t n) {
+  size_t sort_bytes = 0, scan_bytes = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (u64 *)nullptr, (u64 *)nullptr, (int32_t *)nullptr,
+                                           (int32_t *)nullptr, (int)n, 0, 64);
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int64_t *)nullptr, (int64_t *)nullptr, (int)(n + 1));
+  return (int64_t)std::max(sort_bytes, scan_bytes);
+}
+
+// keys: 2n + 1 u64 of scratch (sort keys in; sort keys out, later the
+// permuted degrees); temp: order_temp_bytes(n) bytes (separately allocated,
+// so it has the alignment of an allocation)
+hipError_t build_order(const int64_t *off, const int32_t *gid, int64_t n, int32_t *order, int32_t *pos,
+                       int64_t *noff, u64 *keys, void *temp, int64_t temp_bytes, hipStream_t st) {
+  u64 *kin = keys, *kout = keys + n;
+  int64_t *deg = (int64_t *)kout;  // reused once the sorted keys are no longer needed
+  int32_t *vin = pos;              // pos is written only after the sort
+  size_t tb = (size_t)temp_bytes;
+  hipLaunchKernelGGL(k_order_keys, dim3(grid(n, 256)), dim3(256), 0, st, off, gid, n, kin, vin);
+  hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, tb, kin, kout, vin, order, (int)n, 0, 64, st);
+  if (e != hipSuccess) return e;
+  // noff[0 .. n] = exclusive prefix sum of the permuted degrees (noff[n] = m)
+  hipLaunchKernelGGL(k_inverse, dim3(grid(n, 256)), dim3(256), 0, st, order, n, pos, deg, off);
+  tb = (size_t)temp_bytes;
+  return hipcub::DeviceScan::ExclusiveSum(temp, tb, deg, noff, (int)(n + 1), st);
+}
+
+void launch_permute_rows(const int64_t *off, const int32_t *idx, const void *w, int wk, const int32_t *order,
+                         const int32_t *pos, const int64_t *noff, int32_t *nidx, void *nw, int64_t n,
+                         hipStream_t st) {
+  const dim3 g(grid(n, 4)), b(256);
+  if (wk == W_U8) hipLaunchKernelGGL(k_permute_rows<W_U8>, g, b, 0, st, off, idx, w, order, pos, noff, nidx, nw, n);
+  else if (wk == W_U32)
+    hipLaunchKernelGGL(k_permute_rows<W_U32>, g, b, 0, st, off, idx, w, order, pos, noff, nidx, nw, n);
+  else hipLaunchKernelGGL(k_permute_rows<W_UNIT>, g, b, 0, st, off, idx, w, order, pos, noff, nidx, nw, n);
+}
+
+void launch_gather_i32(int32_t *dst, const int32_t *src, const int32_t *index, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather<int32_t>, dim3(grid(n, 256)), dim3(256), 0, st, dst, src, index, n);
+}
+
+void launch_gather_u8(uint8_t *dst, const uint8_t *src, const int32_t *index, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather<uint8_t>, dim3(grid(n, 256)), dim3(256), 0, st, dst, src, index, n);
+}
+
+}  // namespace gvelpa

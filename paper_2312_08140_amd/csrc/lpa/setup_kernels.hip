@@ -216,14 +216,20 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int64_t *off, int64_t
 
 // ---------------------------------------------------------------- colouring
 
-// Priority of v: (deg(v), fmix32(v ^ seed), v) in lexicographic order; the
-// first two parts are packed in pk[v] = deg << 32 | fmix32(v ^ seed).
-__device__ __forceinline__ bool higher(u64 pu, int u, u64 pv, int v) { return pu > pv || (pu == pv && u > v); }
+// Priority of vertex id v: (deg(v), fmix32(v ^ seed), v) in lexicographic
+// order; the first two parts are packed in pk = deg << 32 | fmix32(v ^ seed).
+// Kernels index vertices by storage position; orig[p] (NULL: p) is the id.
+__device__ __forceinline__ bool higher(u64 pu, int u, u64 pv, int v, const int32_t *orig) {
+  if (pu != pv) return pu > pv;
+  return orig ? orig[u] > orig[v] : u > v;
+}
 
-__global__ void k_color_prio(const int64_t *off, int32_t *color, u64 *pk, int64_t n, uint32_t seed) {
+__global__ void k_color_prio(const int64_t *off, int32_t *color, u64 *pk, int64_t n, uint32_t seed,
+                             const int32_t *orig) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     color[v] = -1;
-    pk[v] = ((u64)(off[v + 1] - off[v]) << 32) | fmix32((uint32_t)v ^ seed);
+    const uint32_t id = orig ? (uint32_t)orig[v] : (uint32_t)v;
+    pk[v] = ((u64)(off[v + 1] - off[v]) << 32) | fmix32(id ^ seed);
   }
 }
 
@@ -233,14 +239,15 @@ __global__ void k_color_prio(const int64_t *off, int32_t *color, u64 *pk, int64_
 // neighbours - exactly its higher-priority neighbours - which is the greedy
 // colouring in decreasing priority.  One wave per vertex.
 __global__ __launch_bounds__(256) void k_color_pending(const int64_t *off, const int32_t *idx, const u64 *pk,
-                                                       int32_t *pending, int32_t *front, int32_t *count, int64_t n) {
+                                                       int32_t *pending, int32_t *front, int32_t *count, int64_t n,
+                                                       const int32_t *orig) {
   const int lane = threadIdx.x & 63;
   for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < n; v += (int64_t)gridDim.x * 4) {
     const u64 pv = pk[v];
     int c = 0;
     for (int64_t k = off[v] + lane; k < off[v + 1]; k += 64) {
       const int u = idx[k];
-      c += (u != (int)v && higher(pk[u], u, pv, (int)v)) ? 1 : 0;
+      c += (u != (int)v && higher(pk[u], u, pv, (int)v, orig)) ? 1 : 0;
     }
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) c += __shfl_xor(c, m, 64);
@@ -253,7 +260,7 @@ __global__ __launch_bounds__(256) void k_color_pending(const int64_t *off, const
 
 __global__ __launch_bounds__(256) void k_color_round(const int64_t *off, const int32_t *idx, int32_t *color,
                                                      const u64 *pk, int32_t *pending, const int32_t *work_in,
-                                                     int32_t *work_out, int32_t *counts, int r) {
+                                                     int32_t *work_out, int32_t *counts, int r, const int32_t *orig) {
   constexpr int WINDOW = 64 * 32;  // colours tested per pass: one 32-bit word per lane
   __shared__ uint32_t bits_all[4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -290,7 +297,7 @@ __global__ __launch_bounds__(256) void k_color_round(const int64_t *off, const i
     const u64 pv = pk[v];
     for (int64_t k = b + lane; k < e; k += 64) {
       const int u = idx[k];
-      if (u != v && higher(pv, v, pk[u], u) && atomicSub(&pending[u], 1) == 1)
+      if (u != v && higher(pv, v, pk[u], u, orig) && atomicSub(&pending[u], 1) == 1)
         work_out[atomicAdd(&counts[r + 1], 1)] = u;
     }
   }
@@ -346,16 +353,17 @@ void launch_fill_u64(u64 *p, int64_t count, u64 value, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256)), dim3(256), 0, st, p, count, value);
 }
 void launch_color_init(const int64_t *off, const int32_t *idx, int32_t *color, u64 *pk, int32_t *pending,
-                       int32_t *front, int32_t *count, int64_t n, uint32_t seed, hipStream_t st) {
-  hipLaunchKernelGGL(k_color_prio, dim3(grid_for(n, 256)), dim3(256), 0, st, off, color, pk, n, seed);
+                       int32_t *front, int32_t *count, int64_t n, uint32_t seed, const int32_t *orig,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_color_prio, dim3(grid_for(n, 256)), dim3(256), 0, st, off, color, pk, n, seed, orig);
   hipLaunchKernelGGL(k_color_pending, dim3(grid_for(n, 4, 16384)), dim3(256), 0, st, off, idx, pk, pending, front,
-                     count, n);
+                     count, n, orig);
 }
 void launch_color_round(const int64_t *off, const int32_t *idx, int32_t *color, const u64 *pk, int32_t *pending,
                         const int32_t *work_in, int32_t *work_out, int32_t *counts, int r, int blocks,
-                        hipStream_t st) {
+                        const int32_t *orig, hipStream_t st) {
   hipLaunchKernelGGL(k_color_round, dim3(blocks), dim3(256), 0, st, off, idx, color, pk, pending, work_in, work_out,
-                     counts, r);
+                     counts, r, orig);
 }
 
 }  // namespace gvelpa

@@ -23,10 +23,11 @@ namespace gvelpa {
 // is processed in sweep 0 like any other (its flag is cleared, its label
 // kept) and nothing can mark it again, so its flag is cleared here once a run
 // has at least one sweep; such vertices are not in the work lists.
+// Labels start as vertex ids (the id stored at position v: orig[v], or v).
 __global__ void k_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, int set_labels, int set_flags,
-                             int clear_isolated) {
+                             int clear_isolated, const int32_t *orig) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    if (set_labels) C[v] = (int32_t)v;
+    if (set_labels) C[v] = orig ? orig[v] : (int32_t)v;
     if (set_flags) F[v] = 1;
     if (clear_isolated && off[v + 1] == off[v]) F[v] = 0;
   }
@@ -300,9 +301,10 @@ __global__ __launch_bounds__(256) void k_gate_pass(const Ctl *ctl, const float *
   const int sweep = ctl->sweep;
   if (!ctl->gate_on || ctl->verify_phase || sweep < 1) return;
   for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v - threadIdx.x < n; v += (int64_t)gridDim.x * 256) {
-    const int lp = v < n && F[v] ? (int)f.lastp[v] : -1;
+    const float *rec = f.feat + v * FEAT_STRIDE;
+    const int lp = v < n && F[v] ? record_lastp(rec) : -1;
     float x[NFEAT] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (lp >= 0) decision_features(f.feat + v * NSTORED, lp, sweep, f.max_iters, x);
+    if (lp >= 0) decision_features(rec, lp, sweep, f.max_iters, x);
     float logit = 0.0f;
     if (__ballot(lp >= 0)) logit = gate_logit_uniform(gate, x);  // whole waves skip the network
     if (v < n) skip[v] = lp >= 0 && logit < z ? 1 : 0;
@@ -402,11 +404,13 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
 // entries of a row travel in registers (and serve the neighbour marks); the
 // bins' default degree limits keep every row within that first pass.
 
-template <int GROUP, int U, int WK>
+template <int GROUP, int U, int WK, bool FEAT = false>
 struct RowStage {
   int v;
   int64_t b, e;
   int32_t cur;
+  uint32_t K;  // FEAT: weighted degree and sweep of the last processing
+  int lp;
   int j[U];
   uint32_t w[U];
   uint32_t lbl[U];
@@ -417,6 +421,10 @@ struct RowStage {
       b = a.off[v];
       e = a.off[v + 1];
       cur = a.C[v];
+      if constexpr (FEAT) {
+        K = a.f.K[v];
+        lp = record_lastp(a.f.feat + (int64_t)v * FEAT_STRIDE);
+      }
     }
   }
   __device__ __forceinline__ void load_row(const ScanArgs &a, int lane) {
@@ -473,7 +481,7 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
   u64 n_changed = 0, n_scanned = 0, n_vert = 0, n_marks = 0;
   int overflow = 0;
   int i = blockIdx.x * GPB + grp;
-  RowStage<GROUP, U, WK> A, B;
+  RowStage<GROUP, U, WK, FEAT> A, B;
   A.load_head(a, i < count ? a.front[i] : -1);
   B.load_head(a, i + stride < count ? a.front[i + stride] : -1);
   A.load_row(a, lane);
@@ -517,7 +525,8 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
     if constexpr (FEAT) {
       const TabStats t = group_stats<GROUP>(ts);
       if (lane == 0)
-        write_features(a.f, A.v, sweep, A.e - A.b, t, table_lookup<BITS, TS>(T, (uint32_t)A.cur), changed);
+        write_features(a.f, A.v, sweep, A.e - A.b, t, table_lookup<BITS, TS>(T, (uint32_t)A.cur), changed, A.K,
+                       A.lp);
     }
     if (lane == 0) {
       n_scanned += (u64)(A.e - A.b);
@@ -547,7 +556,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
   u64 n_changed = 0, n_scanned = 0, n_vert = 0, n_marks = 0;
   int overflow = 0;
   int i = blockIdx.x;
-  RowStage<BLOCK, U, WK> A, B;
+  RowStage<BLOCK, U, WK, FEAT> A, B;
   A.load_head(a, i < count ? a.front[i] : -1);
   B.load_head(a, i + stride < count ? a.front[i + stride] : -1);
   A.load_row(a, threadIdx.x);
@@ -592,7 +601,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
       if (threadIdx.x == 0) {
         TabStats m = tred[0];
         for (int k = 1; k < BLOCK / 64; ++k) m = merge_stats(m, tred[k]);
-        write_features(a.f, A.v, sweep, A.e - A.b, m, table_lookup<BITS>(T, (uint32_t)A.cur), changed);
+        write_features(a.f, A.v, sweep, A.e - A.b, m, table_lookup<BITS>(T, (uint32_t)A.cur), changed, A.K, A.lp);
       }
     }
     if (threadIdx.x == 0) {
@@ -672,11 +681,11 @@ void launch_compact(const CompactArgs &a, int blocks, hipStream_t st) {
 }
 
 void launch_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, int set_labels, int set_flags,
-                       int clear_isolated, hipStream_t st) {
+                       int clear_isolated, const int32_t *orig, hipStream_t st) {
   int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, st, off, C, F, n, set_labels, set_flags,
-                     clear_isolated);
+                     clear_isolated, orig);
 }
 
 void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount, int nfc,
@@ -700,14 +709,15 @@ void launch_set_phase(Ctl *ctl, int verify, int gate_on, int extra_iters, int32_
   hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(1), 0, st, ctl, verify, gate_on, extra_iters, host_done);
 }
 
-__global__ void k_fill_i16(int16_t *p, int64_t count, int16_t value) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = value;
+// every vertex record: never processed
+__global__ void k_feat_reset(float *feat, int64_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    feat[v * FEAT_STRIDE + FEAT_LASTP] = __int_as_float(-1);
 }
 
-void launch_fill_i16(int16_t *p, int64_t count, int16_t value, hipStream_t st) {
-  int blocks = (int)std::min<int64_t>((count + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_fill_i16, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, st, p, count, value);
+void launch_feat_reset(float *feat, int64_t n, hipStream_t st) {
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_feat_reset, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, st, feat, n);
 }
 
 void launch_dense_fill(const Ctl *ctl, const int64_t *off, uint8_t *F, int64_t n, hipStream_t st) {

@@ -4,6 +4,9 @@
 
 namespace gvelpa {
 
+// records the failing HIP call for lpa_last_error_detail (engine.hip)
+void note_hip_error(int err, const char *what, const char *file, int line);
+
 // Arguments of one frontier compaction (one step: the whole graph in async
 // mode, one colour class in deterministic mode).  Entries [bounds[b],
 // bounds[b+1]) of `list` are the step's vertices of bin b; the flagged ones
@@ -34,12 +37,12 @@ void launch_hub_part(int blocks, bool feat, hipStream_t st, const ScanArgs &a, c
 void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, bool feat, hipStream_t st, const ScanArgs &a,
                        const HubArgs &h);
 void launch_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, int set_labels, int set_flags,
-                       int clear_isolated, hipStream_t st);
+                       int clear_isolated, const int32_t *orig, hipStream_t st);
 void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount, int nfc,
                       int32_t *host_done, int dense_enabled, int dense_first, int gate_on, hipStream_t st);
 void launch_dense_fill(const Ctl *ctl, const int64_t *off, uint8_t *F, int64_t n, hipStream_t st);
 void launch_set_phase(Ctl *ctl, int verify, int gate_on, int extra_iters, int32_t *host_done, hipStream_t st);
-void launch_fill_i16(int16_t *p, int64_t count, int16_t value, hipStream_t st);
+void launch_feat_reset(float *feat, int64_t n, hipStream_t st);
 
 // batched runs (graph g owns vertices [vptr[g], vptr[g+1]))
 struct BatchArgs {
@@ -81,10 +84,11 @@ void launch_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, con
 uint32_t phase_seed();
 void launch_fill_u64(u64 *p, int64_t count, u64 value, hipStream_t st);
 void launch_color_init(const int64_t *off, const int32_t *idx, int32_t *color, u64 *pk, int32_t *pending,
-                       int32_t *front, int32_t *count, int64_t n, uint32_t seed, hipStream_t st);
+                       int32_t *front, int32_t *count, int64_t n, uint32_t seed, const int32_t *orig,
+                       hipStream_t st);
 void launch_color_round(const int64_t *off, const int32_t *idx, int32_t *color, const u64 *pk, int32_t *pending,
                         const int32_t *work_in, int32_t *work_out, int32_t *counts, int r, int blocks,
-                        hipStream_t st);
+                        const int32_t *orig, hipStream_t st);
 
 // metrics_kernels.hip
 struct ModAcc {
@@ -97,6 +101,17 @@ void launch_mod_inside(const int64_t *off, const int32_t *idx, const void *w, in
 int mod_square_blocks();
 void launch_mod_squares(const u64 *tot, int64_t n, u64 *partials /* 2 per block */, hipStream_t st);
 void launch_check_labels(const int32_t *C, int64_t n, int32_t *bad, hipStream_t st);
+
+// reorder.hip: vertices stored in decreasing degree order (labels keep their
+// values, the original ids); order[p] = vertex at position p, pos[v] its position.
+int64_t order_temp_bytes(int64_t n);
+hipError_t build_order(const int64_t *off, const int32_t *gid, int64_t n, int32_t *order, int32_t *pos,
+                       int64_t *noff, u64 *keys, void *temp, int64_t temp_bytes, hipStream_t st);
+void launch_permute_rows(const int64_t *off, const int32_t *idx, const void *w, int wk, const int32_t *order,
+                         const int32_t *pos, const int64_t *noff, int32_t *nidx, void *nw, int64_t n,
+                         hipStream_t st);
+void launch_gather_i32(int32_t *dst, const int32_t *src, const int32_t *index, int64_t n, hipStream_t st);
+void launch_gather_u8(uint8_t *dst, const uint8_t *src, const int32_t *index, int64_t n, hipStream_t st);
 
 // gate_kernels.hip: the gate network's forward pass, gradient of the weighted
 // BCE (per-workgroup partials of GATE_PARAMS + 1 floats, the last the loss,

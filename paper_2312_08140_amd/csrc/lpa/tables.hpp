@@ -214,11 +214,11 @@ __device__ __forceinline__ uint32_t table_lookup(const u64 *T, uint32_t lbl) {
 
 // Stores the features of processed vertex v (sweep s) and, when tracing,
 // records the decision-time features it had before this processing together
-// with whether it changed now.
+// with whether it changed now.  K = weighted degree of v, lp = sweep of its
+// last processing (both loaded ahead by the caller).
 __device__ __forceinline__ void write_features(const FeatArgs &f, int v, int s, int64_t deg, TabStats t,
-                                               uint32_t wown, bool changed) {
-  float *st = f.feat + (int64_t)v * NSTORED;
-  const int lp = f.lastp[v];
+                                               uint32_t wown, bool changed, uint32_t K, int lp) {
+  float *st = f.feat + (int64_t)v * FEAT_STRIDE;
   if (f.trace && lp >= 0 && lp < s) {
     const uint32_t hsh = fmix32((uint32_t)v * 0x9E3779B1u ^ (uint32_t)s * 0x85EBCA77u);
     if (hsh < f.tthresh) {
@@ -232,15 +232,19 @@ __device__ __forceinline__ void write_features(const FeatArgs &f, int v, int s, 
       }
     }
   }
-  const uint32_t K = f.K[v];
-  const float inv = K ? 1.0f / (float)K : 0.0f;
-  st[0] = log2f(1.0f + (float)deg);
-  st[1] = (float)(t.w1 - t.w2) * inv;
-  st[2] = (float)wown * inv;
-  st[3] = changed ? 1.0f : 0.0f;
-  st[4] = (float)t.w1 * inv;
-  st[5] = deg ? (float)t.nd / (float)deg : 0.0f;
-  f.lastp[v] = (int16_t)s;
+  // fast divisions (within 2 ulp): the features only steer a heuristic
+  const float inv = K ? __fdividef(1.0f, (float)K) : 0.0f;
+  float4 r0, r1;
+  r0.x = log2f(1.0f + (float)deg);
+  r0.y = (float)(t.w1 - t.w2) * inv;
+  r0.z = (float)wown * inv;
+  r0.w = changed ? 1.0f : 0.0f;
+  r1.x = (float)t.w1 * inv;
+  r1.y = deg ? __fdividef((float)t.nd, (float)deg) : 0.0f;
+  r1.z = __int_as_float(s);
+  r1.w = 0.0f;
+  reinterpret_cast<float4 *>(st)[0] = r0;
+  reinterpret_cast<float4 *>(st)[1] = r1;
 }
 
 // Block-wide maximum (every thread gets the result); red holds BLOCK/64 entries.

@@ -35,10 +35,10 @@ def star(L):
     return gg.from_edges(L + 1, [(0, i) for i in range(1, L + 1)])
 
 
-def check_det(g, tau=0.05, max_iters=20, prune=True, seed=0, bins=None, flags=0, variants=None):
+def check_det(g, tau=0.05, max_iters=20, prune=True, seed=0, bins=None, flags=0, variants=None, reorder=True):
     say(f"det parity n={g.n} m={g.m} tau={tau} iters={max_iters} prune={prune} bins={bins} flags={flags} "
-        f"variants={variants}")
-    G = abi.LPAGraph(g)
+        f"variants={variants} reorder={reorder}")
+    G = abi.LPAGraph(g, reorder=reorder)
     if bins is not None:
         G.set_bins(bins)
     if variants is not None:
@@ -143,6 +143,41 @@ def test_autotune_installs_a_valid_choice():
             G2.set_variants([3] * 6)
         finally:
             G2.close()
+
+
+@pytest.mark.parametrize("kind", ["rmat", "sbm", "star"])
+def test_storage_order_is_invisible(kind):
+    """Vertices stored in degree order inside the library (the default) or
+    in id order: colouring, labels, per-sweep counts, flags, modularity of
+    given labels and resumed runs are identical, host and device arrays."""
+    import torch
+    g = {"rmat": lambda: gg.rmat(13, 16, seed=21), "sbm": lambda: gg.sbm(3000, 30, 0.05, 0.001, seed=22),
+         "star": lambda: star(20000)}[kind]()
+    check_det(g, reorder=False)
+    A, B = abi.LPAGraph(g), abi.LPAGraph(g, reorder=False)
+    ca, na = A.color(0)
+    cb, nb = B.color(0)
+    assert na == nb and np.array_equal(ca, cb)
+    la, sa = A.run(0.05, 20, DET, True)
+    lb, sb = B.run(0.05, 20, DET, True)
+    assert np.array_equal(la, lb)
+    for key in ("changed", "frontier", "edges_scanned"):
+        assert sa[key] == sb[key]
+    assert np.array_equal(A.flags(), B.flags())
+    rng = np.random.default_rng(23)
+    lab = rng.integers(0, g.n, g.n).astype(np.int32)
+    assert A.modularity(lab) == B.modularity(lab)
+    assert A.modularity(torch.from_numpy(lab).cuda()) == B.modularity(lab)
+    part, _ = A.run(-1.0, 2, DET, True)
+    fl = A.flags()
+    ra, _ = A.run(-1.0, 3, DET, True, init_labels=part.copy(), init_flags=fl)
+    rb, _ = B.run(-1.0, 3, DET, True, init_labels=part.copy(), init_flags=fl)
+    assert np.array_equal(ra, rb)
+    dev_out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    A.run(0.05, 20, DET, True, labels_out=dev_out)
+    assert np.array_equal(dev_out.cpu().numpy(), la)
+    A.close()
+    B.close()
 
 
 def test_graph_and_eager_launches_agree():
@@ -314,13 +349,13 @@ def _small_batch(count, seed, n_range=(60, 1500)):
     return gg.sbm_batch(count=count, master_seed=seed, seed_base=500 + seed, n_range=n_range)
 
 
-@pytest.mark.parametrize("count,seed", [(1, 1), (37, 2), (200, 3)])
-def test_batch_deterministic_equals_independent_runs(count, seed):
+@pytest.mark.parametrize("count,seed,reorder", [(1, 1, True), (37, 2, True), (200, 3, True), (37, 2, False)])
+def test_batch_deterministic_equals_independent_runs(count, seed, reorder):
     """Each graph of the batch follows its own stop test; deterministic mode
     equals the oracle run graph by graph (colour order restricted to the graph)."""
     g, vptr = _small_batch(count, seed)
-    say(f"batch of {count}: n={g.n} m={g.m}")
-    B = abi.LPABatch(g, vptr)
+    say(f"batch of {count}: n={g.n} m={g.m} reorder={reorder}")
+    B = abi.LPABatch(g, vptr, reorder=reorder)
     labels, st = B.run(0.05, 20, DET, True)
     it, cv = B.graph_stats()
     ref = oracle.lpa_batch(g, vptr, deterministic=True, tau=0.05, max_iters=20)
