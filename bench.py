@@ -234,7 +234,7 @@ def main():
     ap.add_argument("--max-iters", type=int, default=20)
     ap.add_argument("--no-det", action="store_true", help="skip the deterministic-mode figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sweeps", type=int, default=1)
+    ap.add_argument("--cpu-sweeps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default schedule and kernel shapes")
