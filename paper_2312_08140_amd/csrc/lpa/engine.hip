@@ -964,6 +964,31 @@ static int create_graph(lpa_graph **out, int64_t n, int64_t m, const int64_t *of
       g->idx = nidx;
       g->w = nw;
       HIP_OK(hipMemcpy(g->h_off.data(), noff, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+      // every row sorted by neighbour position, in chunks of rows of at most CH entries
+      const int64_t CH = std::min<int64_t>(m, (int64_t)1 << 28);
+      const size_t wb = g->wk == W_U8 ? 1 : (g->wk == W_U32 ? 4 : 0);
+      u64 *rkeys = dalloc_n<u64>(g, 2 * CH);
+      int32_t *rperm = wb ? dalloc_n<int32_t>(g, 2 * CH) : nullptr;
+      void *wcopy = wb ? dalloc(g, (size_t)CH * wb) : nullptr;
+      const int64_t rtb = row_sort_temp_bytes(CH);
+      void *rtmp = dalloc(g, (size_t)std::max<int64_t>(rtb, 1));
+      for (int64_t r0 = 0; r0 < n;) {
+        // rows [r0, r1) whose entries fit CH; a single longer row stays unsorted (the
+        // order of a row's entries does not change any result)
+        int64_t r1 = std::upper_bound(g->h_off.begin() + r0 + 1, g->h_off.end(), g->h_off[r0] + CH) -
+                     g->h_off.begin() - 1;
+        if (r1 <= r0) r1 = r0 + 1;
+        const int64_t len = g->h_off[r1] - g->h_off[r0];
+        if (len <= CH)
+          HIP_OK(sort_rows_chunk(g->off, r0, r1, g->h_off[r0], len, g->idx, g->w, g->wk, rkeys, rperm, wcopy, rtmp,
+                                 rtb, g->stream));
+        r0 = r1;
+      }
+      HIP_OK(hipStreamSynchronize(g->stream));
+      dfree(g, rtmp);
+      dfree(g, wcopy);
+      dfree(g, rperm);
+      dfree(g, rkeys);
     }
     g->K = dalloc_n<uint32_t>(g, n);
     launch_weighted_degree(g->off, g->w, g->wk, n, g->K, chk, g->stream);

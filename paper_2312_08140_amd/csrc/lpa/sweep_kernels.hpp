@@ -110,6 +110,10 @@ hipError_t build_order(const int64_t *off, const int32_t *gid, int64_t n, int32_
 void launch_permute_rows(const int64_t *off, const int32_t *idx, const void *w, int wk, const int32_t *order,
                          const int32_t *pos, const int64_t *noff, int32_t *nidx, void *nw, int64_t n,
                          hipStream_t st);
+int64_t row_sort_temp_bytes(int64_t chunk);
+hipError_t sort_rows_chunk(const int64_t *off, int64_t r0, int64_t r1, int64_t e0, int64_t len, int32_t *idx,
+                           void *w, int wk, u64 *keys, int32_t *perm, void *wcopy, void *temp, int64_t temp_bytes,
+                           hipStream_t st);
 void launch_gather_i32(int32_t *dst, const int32_t *src, const int32_t *index, int64_t n, hipStream_t st);
 void launch_gather_u8(uint8_t *dst, const uint8_t *src, const int32_t *index, int64_t n, hipStream_t st);
 
