@@ -444,8 +444,9 @@ void ensure_colored(lpa_graph *g, uint32_t seed);
 // of consecutive colour classes holding about n_active / nphase vertices each.
 void build_async(lpa_graph *g, lpa_graph::AsyncSched &sc) {
   if (!sc.list) sc.list = dalloc_n<int32_t>(g, g->n_active);
+  const bool by_colour = g->async_by_colour && sc.nphase > 1;  // a one-step sweep needs no grouping
   std::vector<int32_t> cmap;
-  if (g->async_by_colour) {
+  if (by_colour) {
     std::vector<int64_t> csize(std::max(1, g->ncol), 0);
     for (int64_t v = 0; v < g->n; ++v)
       if (g->h_off[v + 1] > g->h_off[v]) csize[g->h_color[v]] += 1;
@@ -462,7 +463,7 @@ void build_async(lpa_graph *g, lpa_graph::AsyncSched &sc) {
     d_cmap = dalloc_n<int32_t>(g, (int64_t)cmap.size());
     HIP_OK(hipMemcpyAsync(d_cmap, cmap.data(), sizeof(int32_t) * cmap.size(), hipMemcpyHostToDevice, g->stream));
   }
-  build_lists(g, g->async_by_colour ? g->color : nullptr, d_cmap, sc.nphase, sc.nphase * NBINS, sc.list, sc.start);
+  build_lists(g, by_colour ? g->color : nullptr, d_cmap, sc.nphase, sc.nphase * NBINS, sc.list, sc.start);
   dfree(g, d_cmap);
   ensure_fcount(g, sc.nphase * NBINS);
   sc.hub_chunks.assign(sc.nphase, 0);
@@ -470,7 +471,7 @@ void build_async(lpa_graph *g, lpa_graph::AsyncSched &sc) {
   for (size_t k = 0; k < g->h_hub_ids.size(); ++k) {
     const uint32_t v = (uint32_t)g->h_hub_ids[k];
     int ph = 0;
-    if (g->async_by_colour) ph = cmap[g->h_color[v]];
+    if (by_colour) ph = cmap[g->h_color[v]];
     else if (sc.nphase > 1) ph = (int)(fmix32(v ^ phase_seed()) % (uint32_t)sc.nphase);
     sc.hub_chunks[ph] += g->h_hub_chunks[k];
     sc.hub_parts[ph] += g->h_hub_parts[k];
@@ -482,7 +483,8 @@ void ensure_lists(lpa_graph *g) {
   drop_graphs(g);
   if (!g->front) g->front = dalloc_n<int32_t>(g, g->n_active);
   build_hubs(g);
-  if (g->async_by_colour) ensure_colored(g, g->colored ? g->color_seed : 0u);
+  if (g->async_by_colour && (g->sched[0].nphase > 1 || g->sched[1].nphase > 1))
+    ensure_colored(g, g->colored ? g->color_seed : 0u);
   build_async(g, g->sched[0]);
   if (g->sched[1].nphase != g->sched[0].nphase) build_async(g, g->sched[1]);
   g->sched[2].nphase = 1;
@@ -543,7 +545,7 @@ void ensure_colored(lpa_graph *g, uint32_t seed) {
   g->color_seed = seed;
   g->colored = true;
   g->dlists_ready = false;
-  if (g->async_by_colour) g->lists_ready = false;
+  if (g->async_by_colour && (g->sched[0].nphase > 1 || g->sched[1].nphase > 1)) g->lists_ready = false;
 }
 
 void ensure_dlists(lpa_graph *g) {
@@ -1195,7 +1197,8 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
   // 1. Asynchronous schedule: the fastest candidate whose modularity stays
   //    within 0.002 of the all-16-step schedule's.
   if (mode == LPA_MODE_ASYNC) {
-    static const int32_t cand[][3] = {{16, 0, 16}, {16, 2, 4}, {16, 2, 8}, {16, 3, 4}, {16, 3, 8}};
+    static const int32_t cand[][3] = {{16, 0, 16}, {16, 1, 4}, {16, 2, 4}, {16, 2, 8},
+                                      {16, 3, 4},  {16, 3, 8}, {1, 0, 1}};
     double q_ref = 0.0, best_ms = 1e300;
     int best = 0;
     for (int c = 0; c < (int)(sizeof(cand) / sizeof(cand[0])); ++c) {

@@ -130,7 +130,7 @@ def test_autotune_installs_a_valid_choice():
     G = abi.LPAGraph(g)
     v, ms, sch = G.autotune(0.05, 20, ASYNC)
     assert v.shape == (6,) and np.all((v >= 0) & (v < 3)) and np.all(ms >= 0)
-    assert sch in [(16, 0, 16), (16, 2, 4), (16, 2, 8), (16, 3, 4), (16, 3, 8)]
+    assert sch in [(16, 0, 16), (16, 1, 4), (16, 2, 4), (16, 2, 8), (16, 3, 4), (16, 3, 8), (1, 0, 1)]
     colors, nc = G.color(0)
     labels, st = G.run(0.05, 20, DET, True)
     ref = oracle.lpa(g, order=oracle.color_order(colors, nc), tau=0.05, max_iters=20)
