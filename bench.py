@@ -136,7 +136,7 @@ def _compare(G, gate_info, tau, max_iters, out, truth=None, plain=None):
     return r
 
 
-def gate_comparison(args, G, g, runs, q_async, out):
+def gate_comparison(args, G, g, runs, q_async, out, tuned=None):
     """Learned active-set gate vs plain pruning: SBM-1M (gate trained on traces
     of other SBM-1M graphs) and the R-MAT graph of the headline (gate trained
     on traces of smaller R-MAT graphs).  Training is outside every timed run."""
@@ -144,11 +144,14 @@ def gate_comparison(args, G, g, runs, q_async, out):
     from paper_2312_08140_amd import abi, gate, graphgen
     res = {}
     t = time.time()
+    # traces from handles tuned like the ones the gate serves: the schedule
+    # shapes the label dynamics the features have to predict
+    sched = None if args.no_tune else "tuned"
     train = [_sbm1m(mu, 100 + i) for i, mu in enumerate((0.1, 0.2, 0.3, 0.4) * 2)]
-    X, y = gate.collect(train, probability=0.25)
+    X, y = gate.collect(train, probability=0.25, schedule=sched)
     del train
     info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
-    res["sbm_gate"] = {"train_graphs": 8, "samples": int(len(y)), "positive_share": round(float(y.mean()), 4),
+    res["sbm_gate"] = {"train_graphs": 8, "trace_schedule": sched or "default", "samples": int(len(y)), "positive_share": round(float(y.mean()), 4),
                        "threshold": round(info["threshold"], 6), "holdout_recall": round(info["holdout_recall"], 4),
                        "holdout_skip": round(info["holdout_skip"], 4),
                        "loss": [round(float(v), 5) for v in info["losses"]], "seconds": round(time.time() - t, 2)}
@@ -168,10 +171,12 @@ def gate_comparison(args, G, g, runs, q_async, out):
     res["sbm1m"] = rows
     t = time.time()
     train = [graphgen.rmat(20, args.edge_factor, seed=100 + i, weighted=True) for i in range(4)]
-    X, y = gate.collect(train, probability=0.25)
+    rsched = sched if tuned is None else tuned["schedule"]
+    X, y = gate.collect(train, probability=0.25, schedule=rsched)
     del train
     info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
-    res["rmat_gate"] = {"train_graphs": "R-MAT scale 20, seeds 100-103", "samples": int(len(y)),
+    res["rmat_gate"] = {"train_graphs": "R-MAT scale 20, seeds 100-103", "trace_schedule": rsched or "default",
+                        "samples": int(len(y)),
                         "threshold": round(info["threshold"], 6), "holdout_recall": round(info["holdout_recall"], 4),
                         "holdout_skip": round(info["holdout_skip"], 4), "seconds": round(time.time() - t, 2)}
     p_ms = float(np.median([r["total_ms"] for r in runs]))
@@ -357,7 +362,7 @@ def main():
 
     gated = None
     if not args.no_gate:
-        gated = gate_comparison(args, G, g, runs, q_async, out)
+        gated = gate_comparison(args, G, g, runs, q_async, out, tuned)
 
     cpu = None
     if not args.no_cpu:
