@@ -186,8 +186,9 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
  * tolerance, max_iters >= 1 and mode (pruning on).  Asynchronous mode first:
  * among the schedules (early steps, early sweeps, late steps) = (16, 0, 16),
  * (16, 1, 4), (16, 2, 4), (16, 2, 8), (16, 3, 4), (16, 3, 8), (1, 0, 1) (one
- * step: every flagged vertex at once) it installs the fastest
- * whose modularity stays within 0.002 of the first's (schedule_out: int32[3],
+ * step: every flagged vertex at once) it installs the fastest whose runs
+ * converge (a batch: every graph) and whose modularity stays within 0.002 of
+ * the first's; the first stays when no other qualifies (schedule_out: int32[3],
  * may be NULL).  Then it times every kernel
  * shape variant (per-kernel timing), keeps for each bin the fastest and
  * returns it in variant_out (int32[6], may be NULL) with the chosen kernels'

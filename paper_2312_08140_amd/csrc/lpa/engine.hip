@@ -1194,8 +1194,9 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
   if (!g || max_iters < 1 || max_iters > 1000 || (mode != LPA_MODE_ASYNC && mode != LPA_MODE_DETERMINISTIC))
     return LPA_ERR_INVALID_ARG;
   int rc = LPA_OK;
-  // 1. Asynchronous schedule: the fastest candidate whose modularity stays
-  //    within 0.002 of the all-16-step schedule's.
+  // 1. Asynchronous schedule: the fastest candidate whose runs converge (for
+  //    a batch: every graph) and whose modularity stays within 0.002 of the
+  //    all-16-step schedule's.
   if (mode == LPA_MODE_ASYNC) {
     static const int32_t cand[][3] = {{16, 0, 16}, {16, 1, 4}, {16, 2, 4}, {16, 2, 8},
                                       {16, 3, 4},  {16, 3, 8}, {1, 0, 1}};
@@ -1205,17 +1206,19 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
       rc = lpa_set_async_schedule(g, cand[c][0], cand[c][1], cand[c][2], g->async_by_colour ? 1 : 0);
       if (rc != LPA_OK) return rc;
       double ms = 1e300, q = 0.0;
+      bool converged = true;
       for (int rep = 0; rep < 2; ++rep) {
         lpa_stats st;
         rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
         if (rc != LPA_OK) return rc;
         ms = std::min(ms, st.total_ms);
+        converged = converged && st.converged;
       }
       rc = lpa_modularity(g, nullptr, 0, &q);
       if (rc != LPA_OK) return rc;
       if (c == 0) q_ref = q;
       // a candidate must be clearly faster (3 %) to displace an earlier one
-      if (q >= q_ref - 0.002 && ms < 0.97 * best_ms) {
+      if (converged && q >= q_ref - 0.002 && ms < 0.97 * best_ms) {
         best_ms = ms;
         best = c;
       }
