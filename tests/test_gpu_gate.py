@@ -170,6 +170,30 @@ def test_trace_matches_oracle(seed):
                 assert np.allclose(np.sort(a[:, q]), np.sort(b[:, q]), rtol=1e-6, atol=1e-6), (s, t, q)
 
 
+def test_trace_hub_path_matches_oracle():
+    """Every vertex a hub (all bin limits 0): the features the hub path writes
+    (from its label partitions' statistics) equal the trace oracle's."""
+    g = gg.sbm(800, 4, 0.08, 0.01, seed=2, weighted=True)
+    G = abi.LPAGraph(g)
+    G.set_bins([0, 0, 0, 0, 0, 0])
+    colors, nc = G.color(0)
+    G.set_trace(1 << 20, 1.0)
+    labels, st = G.run(0.0, 12, DET, True, flags=abi.LPA_FLAG_TRACE)
+    X, y = G.gate_trace()
+    G.close()
+    ref = lpa_trace(g, order=oracle.color_order(colors, nc), tau=0.0, max_iters=12)
+    assert np.array_equal(labels, ref["labels"])
+    assert len(y) == len(ref["y"])
+    sw = np.rint(X[:, 4] * 12).astype(np.int64)
+    for s in np.unique(ref["sweep"]):
+        for t in (0, 1):
+            a = X[(sw == s) & (y == t)]
+            b = ref["X"][(ref["sweep"] == s) & (ref["y"] == t)]
+            assert a.shape == b.shape, (s, t)
+            for q in range(8):
+                assert np.allclose(np.sort(a[:, q]), np.sort(b[:, q]), rtol=1e-6, atol=1e-6), (s, t, q)
+
+
 def test_trace_sampling_and_capacity():
     g = gg.sbm(20_000, 20, 0.01, 0.0005, seed=4)
     G = abi.LPAGraph(g)
