@@ -37,15 +37,18 @@ def library_digest():
     return h.hexdigest()[:16]
 
 
+DEFAULT_BINS = [4, 16, 64, 256, 1024, 4096]  # the library's default degree limits of bins 0-5
+
+
 def profiled_config(workload):
-    """(variants, schedule) the committed byte counters were taken with, when the
-    library sources still match them; else None."""
+    """(variants, schedule, bins) the committed byte counters were taken with, when
+    the library sources still match them; else None."""
     try:
         for line in (ROOT / "profiles" / f"{workload}_async_hbm_traffic.md").read_text().splitlines():
             if line.startswith("machine-readable: "):
                 d = json.loads(line[len("machine-readable: "):])
                 if d.get("sources") == library_digest():
-                    return d["variants"], d["schedule"]
+                    return d["variants"], d["schedule"], d.get("bins", DEFAULT_BINS)
     except OSError:
         pass
     return None
@@ -60,7 +63,8 @@ def measured_traffic(kernel, tuned, workload):
                 d = json.loads(line[len("machine-readable: "):])
                 if d.get("sources") != library_digest():
                     return None
-                if tuned is None or d.get("variants") != tuned["variants"] or d.get("schedule") != tuned["schedule"]:
+                if tuned is None or d.get("variants") != tuned["variants"] or d.get("schedule") != tuned["schedule"] \
+                        or d.get("bins", DEFAULT_BINS) != tuned["bins"]:
                     return None
                 return d["bytes_per_launch"].get(kernel)
     except OSError:
@@ -219,9 +223,13 @@ def batch_workload(args):
     res["det_default"] = timed(abi.LPA_MODE_DETERMINISTIC, "det default")
     if not args.no_tune:
         t = time.time()
-        v, _, sch = B.autotune(args.tau, args.max_iters, abi.LPA_MODE_ASYNC)
-        res["tuning"] = {"variants": [int(x) for x in v], "schedule": list(sch), "seconds": round(time.time() - t, 2)}
+        v, _, sch, lim = B.autotune(args.tau, args.max_iters, abi.LPA_MODE_ASYNC)
+        res["tuning"] = {"variants": [int(x) for x in v], "schedule": list(sch), "bins": list(lim),
+                         "seconds": round(time.time() - t, 2)}
         res["async_tuned"] = timed(abi.LPA_MODE_ASYNC, "async tuned")
+        t = time.time()
+        dv, _, _, dlim = B.autotune(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC)
+        res["det_tuning"] = {"variants": [int(x) for x in dv], "bins": list(dlim), "seconds": round(time.time() - t, 2)}
         res["det_tuned"] = timed(abi.LPA_MODE_DETERMINISTIC, "det tuned")
     B.close()
     return res
@@ -245,6 +253,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default schedule and kernel shapes")
     ap.add_argument("--variants", default=None,
                     help="kernel shape per degree bin, e.g. 2,1,1,2,2,1 (instead of autotuning; with --schedule)")
+    ap.add_argument("--bins", default=None,
+                    help="degree limits of bins 0-5, e.g. 4,16,64,256,1024,4096 (instead of autotuning)")
     ap.add_argument("--schedule", default=None,
                     help="asynchronous schedule early_steps,early_sweeps,late_steps (instead of autotuning)")
     ap.add_argument("--no-gate", action="store_true", help="skip the plain-vs-gated comparison")
@@ -276,25 +286,31 @@ def main():
     A = abi.LPA_MODE_ASYNC
     out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
     tuned = None
-    if args.variants or args.schedule:
+    if args.variants or args.schedule or args.bins:
         v = [int(x) for x in args.variants.split(",")] if args.variants else [0] * 6
         s = [int(x) for x in args.schedule.split(",")] if args.schedule else [16, 2, 4]
+        lim = [int(x) for x in args.bins.split(",")] if args.bins else list(DEFAULT_BINS)
         G.set_variants(v)
         G.set_async_schedule(*s)
-        tuned = {"variants": v, "schedule": s, "seconds": 0.0, "given": True}
+        G.set_bins(lim)
+        tuned = {"variants": v, "schedule": s, "bins": lim, "seconds": 0.0, "given": True}
     elif not args.no_tune:
         t = time.time()
-        variants, bin_ms, sched = G.autotune(args.tau, args.max_iters, A)
-        tuned = {"variants": [int(v) for v in variants], "schedule": list(sched), "seconds": round(time.time() - t, 2),
-                 "source": "autotune"}
+        variants, bin_ms, sched, lim = G.autotune(args.tau, args.max_iters, A)
+        tuned = {"variants": [int(v) for v in variants], "schedule": list(sched), "bins": list(lim),
+                 "seconds": round(time.time() - t, 2), "source": "autotune"}
         prof = profiled_config(f"rmat{args.scale}")
-        if prof is not None and (prof[0] != tuned["variants"] or prof[1] != tuned["schedule"]):
+        if prof is not None and (prof[0] != tuned["variants"] or prof[1] != tuned["schedule"]
+                                 or prof[2] != tuned["bins"]):
             # the autotuner's near-ties flip between runs; time the configuration it
             # chose when the byte counters were taken, so the counters apply
-            tuned["autotune_pick"] = {"variants": tuned["variants"], "schedule": tuned["schedule"]}
-            tuned.update(variants=prof[0], schedule=prof[1], source="autotune pick recorded with the profile")
+            tuned["autotune_pick"] = {"variants": tuned["variants"], "schedule": tuned["schedule"],
+                                      "bins": tuned["bins"]}
+            tuned.update(variants=prof[0], schedule=prof[1], bins=prof[2],
+                         source="autotune pick recorded with the profile")
             G.set_variants(prof[0])
             G.set_async_schedule(*prof[1])
+            G.set_bins(prof[2])
         log(f"autotune: {tuned}")
 
     for _ in range(args.warmup):
@@ -349,14 +365,25 @@ def main():
     det = None
     if not args.no_det:
         t = time.time()
+        det_tuning = None
+        if tuned is not None and not tuned.get("given"):
+            # the deterministic mode runs colour class by colour class: its own
+            # bin limits and kernel shapes (the results do not depend on them)
+            dv, _, _, dlim = G.autotune(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC)
+            det_tuning = {"variants": [int(x) for x in dv], "bins": list(dlim), "seconds": round(time.time() - t, 2)}
         _, sd = G.run(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC, True, labels_out=out)
         q_det = G.modularity(out)
         _, sd2 = G.run(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC, True, labels_out=out)
         det = dict(time_to_converge_ms=round(sd2["total_ms"], 3), colouring_and_capture_ms=round(sd["setup_ms"], 1),
                    sweeps=sd2["iterations"], colours=sd2["num_colors"], modularity=round(q_det, 6),
                    edges_per_s=round(sum(sd2["edges_scanned"]) / (sd2["total_ms"] * 1e-3), 1),
-                   sweep0_edges_per_s=round(g.m / (sd2["ms"][0] * 1e-3), 1) if sd2["iterations"] else None)
+                   sweep0_edges_per_s=round(g.m / (sd2["ms"][0] * 1e-3), 1) if sd2["iterations"] else None,
+                   tuning=det_tuning)
         log(f"det: {det} ({time.time() - t:.1f}s)")
+        if det_tuning is not None:  # back to the asynchronous tuning for what follows
+            G.set_variants(tuned["variants"])
+            G.set_async_schedule(*tuned["schedule"])
+            G.set_bins(tuned["bins"])
 
     batch = batch_workload(args) if args.batch else None
 

@@ -189,16 +189,21 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
  * step: every flagged vertex at once) it installs the fastest whose runs
  * converge (a batch: every graph) and whose modularity stays within 0.002 of
  * the first's; the first stays when no other qualifies (schedule_out: int32[3],
- * may be NULL).  Then it times every kernel
+ * may be NULL).  Then the degree limits of the bins (lpa_set_bins): each
+ * bin's LDS table has a fixed size (8, 32, 128, 512, 2048, 8192 slots), and
+ * the candidates let it fill to at most 1/2 (the default), 1/4, 3/4 or all of
+ * them; the fastest is installed and returned in bins_out (int32[6], may be
+ * NULL).  Then it times every kernel
  * shape variant (per-kernel timing), keeps for each bin the fastest and
  * returns it in variant_out (int32[6], may be NULL) with the chosen kernels'
  * times in bin_ms_out (double[6], ms per run, 0 for an empty bin; may be
  * NULL).  A later candidate replaces an earlier one only when it is at least
- * 3 % faster, so near-ties keep the earlier (default) choice.  Leaves the
- * labels of its last trial run.
+ * 3 % faster, so near-ties keep the earlier (default) choice.  None of these
+ * settings changes a deterministic result.  Leaves the labels of its last
+ * trial run.
  */
 int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_t *variant_out, double *bin_ms_out,
-                 int32_t *schedule_out);
+                 int32_t *schedule_out, int32_t *bins_out);
 
 /*
  * lpa_set_async_schedule - schedule of the asynchronous mode.  The flagged

@@ -115,7 +115,7 @@ SIGNATURES = {
     "lpa_set_async_phases": (ctypes.c_int, [_vp, _i32, _i32]),
     "lpa_set_async_schedule": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32]),
     "lpa_set_variants": (ctypes.c_int, [_vp, _vp, _i32]),
-    "lpa_autotune": (ctypes.c_int, [_vp, _f64, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
+    "lpa_autotune": (ctypes.c_int, [_vp, _f64, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "lpa_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_uint]),
     "lpa_batch_stats": (ctypes.c_int, [_vp, _vp, _vp]),
     "lpa_gate_load": (ctypes.c_int, [_vp, _vp, _f32]),
@@ -233,9 +233,10 @@ def lpa_set_variants(handle, variant=None):
     return load().lpa_set_variants(handle, _ptr(arr), 0 if arr is None else len(arr))
 
 
-def lpa_autotune(handle, tolerance, max_iters, mode, variant_out=None, bin_ms_out=None, schedule_out=None):
+def lpa_autotune(handle, tolerance, max_iters, mode, variant_out=None, bin_ms_out=None, schedule_out=None,
+                 bins_out=None):
     return load().lpa_autotune(handle, tolerance, max_iters, mode, _ptr(variant_out), _ptr(bin_ms_out),
-                               _ptr(schedule_out))
+                               _ptr(schedule_out), _ptr(bins_out))
 
 
 def lpa_batch_create(n_graphs, graph_vptr, n, m, offsets, indices, weights=None, device=0, hip_stream=None, flags=0):
@@ -410,12 +411,13 @@ class LPAGraph:
         _check(lpa_set_variants(self.handle, variant), "lpa_set_variants")
 
     def autotune(self, tolerance=0.05, max_iters=20, mode=LPA_MODE_ASYNC):
-        """Returns (variant per bin, ms per run of each chosen bin kernel, schedule)."""
+        """Returns (variant per bin, ms per run of each chosen bin kernel, schedule, bin degree limits)."""
         v = np.zeros(6, np.int32)
         ms = np.zeros(6, np.float64)
         sch = np.zeros(3, np.int32)
-        _check(lpa_autotune(self.handle, tolerance, max_iters, mode, v, ms, sch), "lpa_autotune")
-        return v, ms, tuple(int(x) for x in sch)
+        lim = np.zeros(6, np.int32)
+        _check(lpa_autotune(self.handle, tolerance, max_iters, mode, v, ms, sch, lim), "lpa_autotune")
+        return v, ms, tuple(int(x) for x in sch), tuple(int(x) for x in lim)
 
     def gate_load(self, params, threshold):
         p = np.ascontiguousarray(params, dtype=np.float32)

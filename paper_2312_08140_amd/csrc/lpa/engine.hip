@@ -1190,7 +1190,7 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count) {
 }
 
 int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_t *variant_out, double *bin_ms_out,
-                 int32_t *schedule_out) {
+                 int32_t *schedule_out, int32_t *bins_out) {
   if (!g || max_iters < 1 || max_iters > 1000 || (mode != LPA_MODE_ASYNC && mode != LPA_MODE_DETERMINISTIC))
     return LPA_ERR_INVALID_ARG;
   int rc = LPA_OK;
@@ -1231,7 +1231,40 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
     schedule_out[1] = g->early_sweeps;
     schedule_out[2] = g->sched[1].nphase;
   }
-  // 2. Kernel shapes: every bin is its own kernel, so one run per variant
+  // 2. Degree limits of the bins.  A bin's LDS table has a fixed size, so its
+  //    limit sets how full the table can get: the candidates fill the tables
+  //    to at most 1/2 (the default), 1/4, 3/4 or all of their slots.  A lower
+  //    limit gives the bin's rows sparser tables (shorter probe chains) and
+  //    sends more rows to the next, wider bin.
+  {
+    static const int32_t lim_cand[][NBINS - 1] = {{4, 16, 64, 256, 1024, 4096},
+                                                  {2, 8, 32, 128, 512, 2048},
+                                                  {6, 24, 96, 384, 1536, 6144},
+                                                  {7, 31, 127, 511, 2047, 8191}};
+    double best_ms = 1e300;
+    int best = 0;
+    for (int c = 0; c < (int)(sizeof(lim_cand) / sizeof(lim_cand[0])); ++c) {
+      rc = lpa_set_bins(g, lim_cand[c], NBINS - 1);
+      if (rc != LPA_OK) return rc;
+      double ms = 1e300;
+      bool converged = true;
+      for (int rep = 0; rep < 2; ++rep) {
+        lpa_stats st;
+        rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
+        if (rc != LPA_OK) return rc;
+        ms = std::min(ms, st.total_ms);
+        converged = converged && st.converged;
+      }
+      if ((converged || c == 0) && ms < 0.97 * best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    rc = lpa_set_bins(g, lim_cand[best], NBINS - 1);
+    if (rc != LPA_OK) return rc;
+    if (bins_out) std::memcpy(bins_out, lim_cand[best], sizeof(lim_cand[best]));
+  }
+  // 3. Kernel shapes: every bin is its own kernel, so one run per variant
   //    times all bins at once; each run is repeated and the faster kept.
   double best_ms[NBINS - 1];
   int32_t best_v[NBINS - 1];

@@ -128,8 +128,10 @@ def test_kernel_shapes_do_not_change_results(variant):
 def test_autotune_installs_a_valid_choice():
     g = gg.rmat(14, 16, seed=13)
     G = abi.LPAGraph(g)
-    v, ms, sch = G.autotune(0.05, 20, ASYNC)
+    v, ms, sch, lim = G.autotune(0.05, 20, ASYNC)
     assert v.shape == (6,) and np.all((v >= 0) & (v < 3)) and np.all(ms >= 0)
+    assert lim in [(4, 16, 64, 256, 1024, 4096), (2, 8, 32, 128, 512, 2048), (6, 24, 96, 384, 1536, 6144),
+                   (7, 31, 127, 511, 2047, 8191)]
     assert sch in [(16, 0, 16), (16, 1, 4), (16, 2, 4), (16, 2, 8), (16, 3, 4), (16, 3, 8), (1, 0, 1)]
     colors, nc = G.color(0)
     labels, st = G.run(0.05, 20, DET, True)
