@@ -121,11 +121,6 @@ __global__ void k_check_symmetric(const int64_t *off, const int32_t *idx, const 
   atomicAdd(&sums[1], bwd);
 }
 
-__global__ void k_fill_u64(u64 *p, int64_t count, u64 value) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = value;
-}
-
 // Batched handles: no stored entry may join two graphs.
 __global__ void k_check_block_diagonal(const int64_t *off, const int32_t *idx, const int32_t *gid, int64_t n,
                                        int32_t *bad) {
@@ -349,9 +344,6 @@ void launch_check_block_diagonal(const int64_t *off, const int32_t *idx, const i
   hipLaunchKernelGGL(k_check_block_diagonal, dim3(grid_for(n, 4, 16384)), dim3(256), 0, st, off, idx, gid, n, bad);
 }
 
-void launch_fill_u64(u64 *p, int64_t count, u64 value, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256)), dim3(256), 0, st, p, count, value);
-}
 void launch_color_init(const int64_t *off, const int32_t *idx, int32_t *color, u64 *pk, int32_t *pending,
                        int32_t *front, int32_t *count, int64_t n, uint32_t seed, const int32_t *orig,
                        hipStream_t st) {

@@ -82,7 +82,6 @@ void launch_bin_hist(const int64_t *off, int64_t n, const int32_t *color, const 
 void launch_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, const int32_t *cmap, int nphase,
                         const BinLimits &lim, int32_t *cursor, int32_t *list, int nkeys, hipStream_t st);
 uint32_t phase_seed();
-void launch_fill_u64(u64 *p, int64_t count, u64 value, hipStream_t st);
 void launch_color_init(const int64_t *off, const int32_t *idx, int32_t *color, u64 *pk, int32_t *pending,
                        int32_t *front, int32_t *count, int64_t n, uint32_t seed, const int32_t *orig,
                        hipStream_t st);
