@@ -176,10 +176,12 @@ def gate_comparison(args, G, g, runs, q_async, out, tuned=None):
     t = time.time()
     train = [graphgen.rmat(20, args.edge_factor, seed=100 + i, weighted=True) for i in range(4)]
     rsched = sched if tuned is None else tuned["schedule"]
-    X, y = gate.collect(train, probability=0.25, schedule=rsched)
+    rbins = None if tuned is None else tuned["bins"]
+    X, y = gate.collect(train, probability=0.25, schedule=rsched, bins=rbins)
     del train
     info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
     res["rmat_gate"] = {"train_graphs": "R-MAT scale 20, seeds 100-103", "trace_schedule": rsched or "default",
+                        "trace_bins": rbins or "default",
                         "samples": int(len(y)),
                         "threshold": round(info["threshold"], 6), "holdout_recall": round(info["holdout_recall"], 4),
                         "holdout_skip": round(info["holdout_skip"], 4), "seconds": round(time.time() - t, 2)}

@@ -30,14 +30,15 @@ def init_params(seed: int = 0) -> np.ndarray:
 
 
 def collect(graphs, probability: float = 0.25, capacity: int = 1 << 22, tau: float = 0.05, max_iters: int = 20,
-            mode: int = abi.LPA_MODE_ASYNC, schedule=None):
+            mode: int = abi.LPA_MODE_ASYNC, schedule=None, bins=None):
     """Traces plain pruned runs of every CSR in ``graphs``; returns (X float32[S][8], y uint8[S]).
 
     ``schedule``: asynchronous schedule (early steps, early sweeps, late steps)
     of the traced runs, best that of the runs the gate will serve (the label
     dynamics, hence what the features predict, depend on it); "tuned" lets
-    ``lpa_autotune`` pick it per graph, as for tuned handles; None keeps the
-    library's default."""
+    ``lpa_autotune`` pick it (and the bin limits) per graph, as for tuned
+    handles; None keeps the library's default.  ``bins``: degree limits of
+    the bins for the traced runs (they change the processing order too)."""
     xs, ys = [], []
     for csr in graphs:
         G = abi.LPAGraph(csr)
@@ -45,6 +46,8 @@ def collect(graphs, probability: float = 0.25, capacity: int = 1 << 22, tau: flo
             G.autotune(tau, max_iters, mode)
         elif schedule is not None:
             G.set_async_schedule(*schedule)
+        if bins is not None and schedule != "tuned":
+            G.set_bins(list(bins))
         G.set_trace(capacity, probability)
         G.run(tau, max_iters, mode, True, flags=abi.LPA_FLAG_TRACE)
         x, y = G.gate_trace()
