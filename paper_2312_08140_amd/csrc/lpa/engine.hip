@@ -229,40 +229,54 @@ int validate_host(int64_t n, int64_t m, const int64_t *off, const int32_t *idx, 
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
   };
+  // each thread keeps its results in locals and stores them once: per-entry
+  // stores into the shared per-thread vectors would bounce their cache lines
+  // between the threads on every entry
   auto work = [&](unsigned t) {
     const int64_t v0 = n * t / nt, v1 = n * (t + 1) / nt;
+    uint32_t l_wmax = 0;
+    int l_ones = 0, l_big = 0;
+    u64 l_fwd = 0, l_bwd = 0;
+    auto done = [&]() {
+      wmax[t] = l_wmax;
+      ones[t] = l_ones;
+      big[t] = l_big;
+      fwd[t] = l_fwd;
+      bwd[t] = l_bwd;
+    };
     for (int64_t v = v0; v < v1; ++v) {
       if (off[v + 1] < off[v] || off[v] < 0 || off[v + 1] > m) {
         bad_off[t] = 1;
-        return;
+        return done();
       }
       u64 deg = 0;
       for (int64_t e = off[v]; e < off[v + 1]; ++e) {
         const int32_t j = idx[e];
         if (j < 0 || (int64_t)j >= n) {
           bad_idx[t] = 1;
-          return;
+          return done();
         }
         uint32_t x = 1;
         if (w) {
           const float f = w[e];
           if (!(f >= 0.0f) || f > 16777216.0f || std::floor(f) != f) {
             bad_w[t] = 1;
-            return;
+            return done();
           }
           x = (uint32_t)f;
-          wmax[t] = std::max(wmax[t], x);
-          ones[t] |= x != 1u;
+          l_wmax = std::max(l_wmax, x);
+          l_ones |= x != 1u;
         }
         deg += x;
         if (check_sym) {
           const u64 hx = mix(x + 0x9E3779B97F4A7C15ull);
-          fwd[t] += mix(((u64)v << 32 | (uint32_t)j) ^ hx);
-          bwd[t] += mix(((u64)(uint32_t)j << 32 | (u64)v) ^ hx);
+          l_fwd += mix(((u64)v << 32 | (uint32_t)j) ^ hx);
+          l_bwd += mix(((u64)(uint32_t)j << 32 | (u64)v) ^ hx);
         }
       }
-      if (deg >= (1ull << 32)) big[t] = 1;
+      if (deg >= (1ull << 32)) l_big = 1;
     }
+    done();
   };
   std::vector<std::thread> th;
   for (unsigned t = 1; t < nt; ++t) th.emplace_back(work, t);
