@@ -198,9 +198,13 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
  * returns it in variant_out (int32[6], may be NULL) with the chosen kernels'
  * times in bin_ms_out (double[6], ms per run, 0 for an empty bin; may be
  * NULL).  A later candidate replaces an earlier one only when it is at least
- * 3 % faster, so near-ties keep the earlier (default) choice.  None of these
- * settings changes a deterministic result.  Leaves the labels of its last
- * trial run.
+ * 3 % faster, so near-ties keep the earlier (default) choice.  In the
+ * asynchronous mode every candidate of the three steps must also converge
+ * and keep the modularity of its runs within 0.002 of the all-16-step
+ * schedule's (the processing order they set changes which labels a sweep
+ * sees); the mix of per-bin kernel shapes is checked once more as a whole
+ * and replaced by the default shapes if it fails.  None of these settings
+ * changes a deterministic result.  Leaves the labels of its last trial run.
  */
 int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_t *variant_out, double *bin_ms_out,
                  int32_t *schedule_out, int32_t *bins_out);

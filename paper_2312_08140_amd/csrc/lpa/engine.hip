@@ -1208,13 +1208,20 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
   if (!g || max_iters < 1 || max_iters > 1000 || (mode != LPA_MODE_ASYNC && mode != LPA_MODE_DETERMINISTIC))
     return LPA_ERR_INVALID_ARG;
   int rc = LPA_OK;
+  // Every candidate of every step must keep the modularity of its runs
+  // within 0.002 of q_ref: the asynchronous processing order (schedule, bin
+  // limits, kernel shapes) changes which labels a sweep sees.  In the
+  // deterministic mode results do not depend on these settings.
+  double q_ref = 0.0;
+  bool have_ref = false;
+  auto quality_ok = [&](double q) { return !have_ref || q >= q_ref - 0.002; };
   // 1. Asynchronous schedule: the fastest candidate whose runs converge (for
   //    a batch: every graph) and whose modularity stays within 0.002 of the
   //    all-16-step schedule's.
   if (mode == LPA_MODE_ASYNC) {
     static const int32_t cand[][3] = {{16, 0, 16}, {16, 1, 4}, {16, 2, 4}, {16, 2, 8},
                                       {16, 3, 4},  {16, 3, 8}, {1, 0, 1}};
-    double q_ref = 0.0, best_ms = 1e300;
+    double best_ms = 1e300;
     int best = 0;
     for (int c = 0; c < (int)(sizeof(cand) / sizeof(cand[0])); ++c) {
       rc = lpa_set_async_schedule(g, cand[c][0], cand[c][1], cand[c][2], g->async_by_colour ? 1 : 0);
@@ -1230,9 +1237,12 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
       }
       rc = lpa_modularity(g, nullptr, 0, &q);
       if (rc != LPA_OK) return rc;
-      if (c == 0) q_ref = q;
+      if (c == 0) {
+        q_ref = q;
+        have_ref = true;
+      }
       // a candidate must be clearly faster (3 %) to displace an earlier one
-      if (converged && q >= q_ref - 0.002 && ms < 0.97 * best_ms) {
+      if (converged && quality_ok(q) && ms < 0.97 * best_ms) {
         best_ms = ms;
         best = c;
       }
@@ -1260,7 +1270,7 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
     for (int c = 0; c < (int)(sizeof(lim_cand) / sizeof(lim_cand[0])); ++c) {
       rc = lpa_set_bins(g, lim_cand[c], NBINS - 1);
       if (rc != LPA_OK) return rc;
-      double ms = 1e300;
+      double ms = 1e300, q = 0.0;
       bool converged = true;
       for (int rep = 0; rep < 2; ++rep) {
         lpa_stats st;
@@ -1269,7 +1279,12 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
         ms = std::min(ms, st.total_ms);
         converged = converged && st.converged;
       }
-      if ((converged || c == 0) && ms < 0.97 * best_ms) {
+      if (mode == LPA_MODE_ASYNC) {
+        rc = lpa_modularity(g, nullptr, 0, &q);
+        if (rc != LPA_OK) return rc;
+      }
+      const bool ok = c == 0 || (converged && (mode != LPA_MODE_ASYNC || quality_ok(q)));
+      if (ok && ms < 0.97 * best_ms) {
         best_ms = ms;
         best = c;
       }
@@ -1309,6 +1324,25 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
   }
   rc = lpa_set_variants(g, best_v, NBINS - 1);
   if (rc != LPA_OK) return rc;
+  if (mode == LPA_MODE_ASYNC) {
+    // the mix of per-bin picks must converge and keep the quality; else every
+    // bin goes back to its default shape
+    bool converged = true;
+    for (int rep = 0; rep < 2; ++rep) {
+      lpa_stats st;
+      rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
+      if (rc != LPA_OK) return rc;
+      converged = converged && st.converged;
+    }
+    double q = 0.0;
+    rc = lpa_modularity(g, nullptr, 0, &q);
+    if (rc != LPA_OK) return rc;
+    if (!converged || !quality_ok(q)) {
+      for (int b = 0; b < NBINS - 1; ++b) best_v[b] = 0;
+      rc = lpa_set_variants(g, best_v, NBINS - 1);
+      if (rc != LPA_OK) return rc;
+    }
+  }
   if (variant_out) std::memcpy(variant_out, best_v, sizeof(best_v));
   if (bin_ms_out)
     for (int b = 0; b < NBINS - 1; ++b) bin_ms_out[b] = best_ms[b] < 1e299 ? best_ms[b] : 0.0;

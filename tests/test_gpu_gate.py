@@ -29,6 +29,29 @@ def say(*a):
     sys.stdout.flush()
 
 
+def _oracle_order(G, g, seed=0):
+    """The deterministic mode's vertex order from the oracle's greedy colouring
+    (checked equal to the library's colouring first)."""
+    colors, nc = G.color(seed)
+    ocol, onc = oracle.color(g, seed)
+    assert nc == onc and np.array_equal(colors, ocol), "colouring differs from the greedy oracle"
+    return oracle.color_order(ocol, onc)
+
+
+def _same_samples(X, y, ref, decimals=4):
+    """Trace samples equal the oracle's as a multiset of whole rows (features
+    and target together): both sides sorted lexicographically by (target,
+    features rounded to a few decimals), then compared row by row."""
+    assert len(y) == len(ref["y"])
+    a = np.column_stack([y.astype(np.float64), X.astype(np.float64)])
+    b = np.column_stack([ref["y"].astype(np.float64), ref["X"]])
+    ka, kb = np.round(a, decimals), np.round(b, decimals)
+    a = a[np.lexsort(ka.T[::-1])]
+    b = b[np.lexsort(kb.T[::-1])]
+    assert np.array_equal(a[:, 0], b[:, 0])
+    assert np.allclose(a[:, 1:], b[:, 1:], rtol=1e-6, atol=1e-5)
+
+
 def random_samples(count, seed):
     """Features in the ranges the sweep produces: f0 = log2(1 + deg), f3 0/1, the rest in [0, 1]."""
     rng = np.random.default_rng(seed)
@@ -145,14 +168,13 @@ def test_threshold_keeps_recall():
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_trace_matches_oracle(seed):
-    """Deterministic run, every re-processing traced: the sample multiset
-    equals the trace oracle's in (colour, id) order, compared per (sweep,
-    target) group column by column."""
+    """Deterministic run, every re-processing traced: the samples equal the
+    trace oracle's in (colour, id) order as a multiset of whole rows (the
+    sweep is feature 4), so no feature can move between samples unnoticed."""
     g = gg.sbm(400 * seed, 4, 0.08, 0.01, seed=seed, weighted=seed == 2)
     say(f"trace parity n={g.n} m={g.m} seed={seed}")
     G = abi.LPAGraph(g)
-    colors, nc = G.color(0)
-    order = oracle.color_order(colors, nc)
+    order = _oracle_order(G, g)
     G.set_trace(1 << 20, 1.0)
     labels, st = G.run(0.0, 12, DET, True, flags=abi.LPA_FLAG_TRACE)
     X, y = G.gate_trace()
@@ -160,14 +182,7 @@ def test_trace_matches_oracle(seed):
     ref = lpa_trace(g, order=order, tau=0.0, max_iters=12)
     assert np.array_equal(labels, ref["labels"])
     assert len(y) == len(ref["y"])
-    sw = np.rint(X[:, 4] * 12).astype(np.int64)
-    for s in np.unique(ref["sweep"]):
-        for t in (0, 1):
-            a = X[(sw == s) & (y == t)]
-            b = ref["X"][(ref["sweep"] == s) & (ref["y"] == t)]
-            assert a.shape == b.shape, (s, t)
-            for q in range(8):
-                assert np.allclose(np.sort(a[:, q]), np.sort(b[:, q]), rtol=1e-6, atol=1e-6), (s, t, q)
+    _same_samples(X, y, ref)
 
 
 def test_trace_hub_path_matches_oracle():
@@ -176,22 +191,15 @@ def test_trace_hub_path_matches_oracle():
     g = gg.sbm(800, 4, 0.08, 0.01, seed=2, weighted=True)
     G = abi.LPAGraph(g)
     G.set_bins([0, 0, 0, 0, 0, 0])
-    colors, nc = G.color(0)
+    order = _oracle_order(G, g)
     G.set_trace(1 << 20, 1.0)
     labels, st = G.run(0.0, 12, DET, True, flags=abi.LPA_FLAG_TRACE)
     X, y = G.gate_trace()
     G.close()
-    ref = lpa_trace(g, order=oracle.color_order(colors, nc), tau=0.0, max_iters=12)
+    ref = lpa_trace(g, order=order, tau=0.0, max_iters=12)
     assert np.array_equal(labels, ref["labels"])
     assert len(y) == len(ref["y"])
-    sw = np.rint(X[:, 4] * 12).astype(np.int64)
-    for s in np.unique(ref["sweep"]):
-        for t in (0, 1):
-            a = X[(sw == s) & (y == t)]
-            b = ref["X"][(ref["sweep"] == s) & (ref["y"] == t)]
-            assert a.shape == b.shape, (s, t)
-            for q in range(8):
-                assert np.allclose(np.sort(a[:, q]), np.sort(b[:, q]), rtol=1e-6, atol=1e-6), (s, t, q)
+    _same_samples(X, y, ref)
 
 
 def test_trace_sampling_and_capacity():
@@ -230,8 +238,7 @@ def test_threshold_zero_is_plain_with_verification(kind):
     assert np.array_equal(a, b)
     assert sa["changed"] == sb["changed"] and sa["verify_changed"] == sb["verify_changed"]
     assert sa["verified"] == sb["verified"] and sum(sa["gated_out"]) == 0
-    colors, nc = G.color(0)
-    order = oracle.color_order(colors, nc)
+    order = _oracle_order(G, g)
     r1 = oracle.lpa(g, order=order, tau=0.05, max_iters=20)
     r2 = oracle.lpa(g, order=order, tau=0.05, max_iters=1, prune=False, init_labels=r1["labels"])
     assert sa["verify_changed"] == int(r2["changed"][0])
@@ -330,3 +337,65 @@ def test_trained_gate_saves_work_on_rmat():
     assert abi.nmi(plain, lab) >= 0.99
     assert np.median(eg) < 0.95 * np.median(ep)
     G.close()
+
+
+# ---------------------------------------------------------------- the gate inside the sweep
+
+def _pick_gate(g, order, seeds=(21, 22, 23, 24), tau=0.05, max_iters=20, min_margin=1e-3):
+    """Parameters and a threshold in (0, 1) for which the gated oracle takes
+    no decision within ``min_margin`` of the threshold's logit and skips at
+    least one flagged vertex.  Candidate logit thresholds are midpoints of the
+    widest gaps between the decision logits of the plain trace (middle half of
+    their range); all of it runs on the oracle side."""
+    from oracle.gate_trace import _logit_fp64, lpa_gated, lpa_trace
+    trace = lpa_trace(g, order=order, tau=tau, max_iters=max_iters)
+    for seed in seeds:
+        theta = random_params(seed)
+        z = np.sort(np.unique(_logit_fp64(mlp.bf16_round(theta), trace["X"])))
+        if len(z) < 8:
+            continue
+        lo, hi = len(z) // 4, 3 * len(z) // 4
+        gaps = np.diff(z[lo:hi + 1])
+        for k in np.argsort(gaps)[::-1][:6]:
+            zc = 0.5 * (z[lo + k] + z[lo + k + 1])
+            thr = float(np.float32(1.0 / (1.0 + np.exp(-zc))))
+            if not 0.0 < thr < 1.0:
+                continue
+            ref = lpa_gated(g, theta, thr, order=order, tau=tau, max_iters=max_iters)
+            if ref["margin"] >= min_margin and ref["gated"].sum() > 0:
+                return theta, thr, ref
+    raise AssertionError("no gate with a safe margin found")
+
+
+@pytest.mark.parametrize("kind", ["sbm", "rmat", "all_hubs"])
+def test_gated_deterministic_equals_gated_oracle(kind):
+    """The network evaluated inside the sweep (decision pass + compaction)
+    against the gated method's oracle at a threshold strictly inside (0, 1):
+    deterministic mode, so labels, per-sweep dN, processed vertices, scanned
+    entries, gated-out vertices and the verification outcome must all be equal.
+    The threshold is chosen (on the oracle side) so that no decision lies
+    within 1e-3 of it in logit, beyond any fp32-vs-fp64 difference."""
+    if kind == "rmat":
+        g = gg.rmat(11, 8, seed=5, weighted=True)
+    else:
+        g = gg.sbm(1200 if kind == "sbm" else 800, 6 if kind == "sbm" else 4, 0.05, 0.006, seed=11,
+                   weighted=True)
+    G = abi.LPAGraph(g)
+    if kind == "all_hubs":
+        G.set_bins([0, 0, 0, 0, 0, 0])  # every vertex through the hub kernels (their feature writes)
+    order = _oracle_order(G, g)
+    theta, thr, ref = _pick_gate(g, order)
+    say(f"gated {kind}: n={g.n} m={g.m} threshold={thr:.6f} margin={ref['margin']:.2e} "
+        f"gated={ref['gated'].tolist()} changed={ref['changed'].tolist()} verified={ref['verified']}")
+    G.gate_load(theta, thr)
+    lab, st = G.run(0.05, 20, DET, True, flags=abi.LPA_FLAG_GATE)
+    G.close()
+    assert np.array_equal(lab, ref["labels"])
+    assert st["iterations"] == ref["iterations"] and st["converged"] == ref["converged"]
+    assert st["changed"] == ref["changed"].tolist()
+    assert st["frontier"] == ref["processed"].tolist()
+    assert st["edges_scanned"] == ref["scanned"].tolist()
+    assert st["gated_out"] == ref["gated"].tolist()
+    assert st["verify_changed"] == ref["verify_changed"]
+    assert st["verify_edges_scanned"] == ref["verify_scanned"]
+    assert st["verified"] == ref["verified"]

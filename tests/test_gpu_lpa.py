@@ -134,8 +134,10 @@ def test_autotune_installs_a_valid_choice():
                    (7, 31, 127, 511, 2047, 8191)]
     assert sch in [(16, 0, 16), (16, 1, 4), (16, 2, 4), (16, 2, 8), (16, 3, 4), (16, 3, 8), (1, 0, 1)]
     colors, nc = G.color(0)
+    ocol, onc = oracle.color(g, 0)
+    assert nc == onc and np.array_equal(colors, ocol)
     labels, st = G.run(0.05, 20, DET, True)
-    ref = oracle.lpa(g, order=oracle.color_order(colors, nc), tau=0.05, max_iters=20)
+    ref = oracle.lpa(g, order=oracle.color_order(ocol, onc), tau=0.05, max_iters=20)
     assert np.array_equal(labels, ref["labels"])
     G.set_variants(None)
     G.close()
@@ -255,15 +257,18 @@ def _components(g):
 def test_async_quality_and_invariants(seed):
     g = gg.sbm(20000, 20, 0.02, 0.0002, seed=seed, method="skip")
     G = abi.LPAGraph(g)
-    lab_a, st_a = G.run(0.05, 20, ASYNC, True)
+    lab_a, st_a = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_VERIFY)
     q_a = G.modularity(lab_a)
     lab_d, st_d = G.run(0.05, 20, DET, True)
     q_d = G.modularity(lab_d)
-    say(f"async Q={q_a:.5f} ({st_a['iterations']} sweeps)  det Q={q_d:.5f} ({st_d['iterations']} sweeps)")
+    say(f"async Q={q_a:.5f} ({st_a['iterations']} sweeps, verify dN {st_a['verify_changed']})  "
+        f"det Q={q_d:.5f} ({st_d['iterations']} sweeps)")
     assert st_a["converged"]
-    # several results are correct; the asynchronous one must not lose more
-    # than 0.01 modularity against the deterministic (sequential-order) one
-    assert q_a >= q_d - 0.01
+    # several results are correct; the asynchronous one stays within 0.01
+    # modularity of the deterministic (sequential-order) one, and reaches a
+    # verified fixed point: one more sweep changes at most tau * n labels
+    assert abs(q_a - q_d) <= 0.01
+    assert st_a["verified"] and st_a["verify_changed"] <= 0.05 * g.n
     comp = _components(g)
     assert np.array_equal(comp[lab_a], comp)  # every label is a vertex of the same component
     G.close()
@@ -275,12 +280,13 @@ def test_async_quality_sbm_1m(mu):
     n, k, d = 1000000, 1000, 32.0
     g = gg.sbm(n, k, d * (1 - mu) / 999, d * mu / (n - 1000), seed=3)
     G = abi.LPAGraph(g)
-    lab_a, st_a = G.run(0.05, 20, ASYNC, True)
+    lab_a, st_a = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_VERIFY)
     q_a = G.modularity(lab_a)
     lab_d, _ = G.run(0.05, 20, DET, True)
     q_d = G.modularity(lab_d)
-    say(f"mu={mu}: async Q={q_a:.5f} det Q={q_d:.5f}")
-    assert q_a >= q_d - 0.01
+    say(f"mu={mu}: async Q={q_a:.5f} (verify dN {st_a['verify_changed']}) det Q={q_d:.5f}")
+    assert abs(q_a - q_d) <= 0.01
+    assert st_a["converged"] and st_a["verified"]
     G.close()
 
 

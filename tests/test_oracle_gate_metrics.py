@@ -164,3 +164,108 @@ def test_trace_lpa_equals_c_oracle(seed):
     X = r["X"]
     assert np.all((X[:, 1:] >= 0) & (X[:, 1:] <= 1)) and not iso.all()
     assert np.all(X[:, 5] >= X[:, 1]) and np.all(X[:, 5] >= X[:, 2])  # W1 bounds W1 - W2 and W(own)
+
+
+def test_trace_weighted_by_hand():
+    """Weighted triangle 0-1-2 (w01 = w02 = 1, w12 = 2) with a pendant 3 on 2
+    (w23 = 1), id order, tau < 0, three sweeps.  K = (2, 3, 4, 1).
+    Sweep 0: 0 ties {1:1, 2:1} and takes 1; 1 sees {1:1, 2:2} and takes 2;
+    2 (marked by 0) sees {1:1, 2:2, 3:1} and keeps 2; 3 takes 2.  Flags left:
+    0 (marked by 1) and 2 (marked by 3).  Sweep 1: 0 sees {2:2} and changes;
+    its mark re-flags 1 before its turn, so 1 is re-processed in the same
+    sweep and keeps 2; 2 keeps 2.  The features divide by the weighted degree
+    K (not by deg): vertex 1's margin (2 - 1)/3 and vertex 2's W(own)/K = 2/4."""
+    from oracle.gate_trace import lpa_trace
+    from paper_2312_08140_amd import graphgen as gg
+    g = gg.from_edges(4, [(0, 1), (0, 2), (1, 2), (2, 3)], [1, 1, 2, 1])
+    r = lpa_trace(g, tau=-1.0, max_iters=3)
+    assert list(r["labels"]) == [2, 2, 2, 2]
+    assert list(r["changed"]) == [3, 1, 0]
+    l3 = np.log2(3.0)
+    expect = np.array([[l3, 0.0, 0.0, 1.0, 1 / 3, 0.5, 1.0, 0.125],          # vertex 0: changed 0 -> 1 at sweep 0
+                       [l3, 1 / 3, 1 / 3, 1.0, 1 / 3, 2 / 3, 1.0, 0.125],    # vertex 1: {1:1, 2:2}, took 2
+                       [2.0, 0.25, 0.5, 0.0, 1 / 3, 0.5, 1.0, 0.125]])       # vertex 2: {1:1, 2:2, 3:1}, kept 2
+    assert np.allclose(r["X"], expect, atol=1e-15)
+    assert list(r["y"]) == [1, 0, 0] and list(r["sweep"]) == [1, 1, 1]
+
+
+# ---------------------------------------------------------------- gated-method oracle
+
+def _x3_gate():
+    """Parameters whose logit is x3 - 0.5 (x3 = changed at the last processing):
+    with threshold 0.5 a flagged vertex is skipped iff it kept its label last time."""
+    from oracle import mlp
+    P = {name: np.zeros(shape) for name, shape in mlp.SHAPES}
+    P["W1"][0, 3] = 1.0
+    P["W2"][0, 0] = 1.0
+    P["W3"][0, 0] = 1.0
+    P["b3"][0] = -0.5
+    return mlp.pack(P).astype(np.float32)
+
+
+def test_gated_path_by_hand():
+    """Path 0-1-2-3, unit weights, id order, gate 'skip if unchanged last time'.
+    Sweep 0 (ungated): 0 takes 1; 1 ties {1, 2} and keeps 1; 2 ties {1, 3} and
+    takes 1 (re-flagging 1 and 3); 3 (already flagged) takes 1 and re-flags 2.
+    Flagged at sweep 1: 1 (kept its label: skipped, stays flagged) and 2
+    (changed: processed, keeps 1).  dN = 0 stops the run; the verification
+    sweep processes the still-flagged 1, which keeps 1."""
+    from oracle.gate_trace import lpa_gated
+    from paper_2312_08140_amd import graphgen as gg
+    g = gg.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    r = lpa_gated(g, _x3_gate(), 0.5, tau=0.05, max_iters=20)
+    assert list(r["labels"]) == [1, 1, 1, 1]
+    assert list(r["changed"]) == [3, 0] and list(r["processed"]) == [4, 1] and list(r["gated"]) == [0, 1]
+    assert list(r["scanned"]) == [6, 2]
+    assert r["converged"] and r["verified"] and r["verify_changed"] == 0 and r["verify_scanned"] == 2
+    assert r["margin"] == pytest.approx(0.5)
+
+
+def _sbm_colour_order(seed, n=400):
+    from paper_2312_08140_amd import graphgen as gg
+    g = gg.sbm(n, 4, 0.08, 0.01, seed=seed, weighted=seed % 2 == 0)
+    return g, oracle.color_order(*oracle.color(g, 0))
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_gated_threshold_zero_is_plain_plus_verification(seed):
+    """Threshold 0 gates nothing: the main loop is the C oracle's run, and the
+    verification sweep is one more pruned sweep resumed from its state."""
+    from oracle.gate_trace import lpa_gated
+    g, order = _sbm_colour_order(seed)
+    theta = np.random.default_rng(seed).normal(0, 0.3, 1377).astype(np.float32)
+    r = lpa_gated(g, theta, 0.0, order=order, tau=0.05, max_iters=20)
+    ref = oracle.lpa(g, order=order, tau=0.05, max_iters=20)
+    k = ref["iterations"]
+    assert r["iterations"] >= k
+    assert list(r["changed"][:k]) == list(ref["changed"]) and list(r["processed"][:k]) == list(ref["processed"])
+    assert list(r["scanned"][:k]) == list(ref["scanned"]) and not r["gated"].any()
+    v = oracle.lpa(g, order=order, tau=-1.0, max_iters=1, init_labels=ref["labels"], init_flags=ref["flags"])
+    assert r["verify_changed"] >= v["changed"][0]
+    if v["changed"][0] <= 0.05 * g.n:
+        assert r["verified"] and r["iterations"] == k and np.array_equal(r["labels"], v["labels"])
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_gated_threshold_one_stalls_then_falls_back(seed):
+    """Threshold 1 skips every re-processing: sweep 1 processes nothing and
+    stops the run; the verification sweep and the plain fallback are the C
+    oracle resumed from the state after sweep 0 (cap: max_iters more sweeps,
+    counted with the verification sweep), then verification again."""
+    from oracle.gate_trace import lpa_gated
+    g, order = _sbm_colour_order(seed)
+    theta = np.random.default_rng(seed).normal(0, 0.3, 1377).astype(np.float32)
+    tau, it = 0.05, 20
+    r = lpa_gated(g, theta, 1.0, order=order, tau=tau, max_iters=it)
+    s0 = oracle.lpa(g, order=order, tau=-1.0, max_iters=1)
+    assert r["changed"][0] == s0["changed"][0] and r["changed"][1] == 0 and r["processed"][1] == 0
+    assert r["gated"][1] == int(s0["flags"].sum())
+    v1 = oracle.lpa(g, order=order, tau=-1.0, max_iters=1, init_labels=s0["labels"], init_flags=s0["flags"])
+    assert v1["changed"][0] > tau * g.n      # sweep 0 leaves much to do: the fallback runs
+    fb = oracle.lpa(g, order=order, tau=tau, max_iters=min(it, 2 * it - 3), init_labels=v1["labels"],
+                    init_flags=v1["flags"])
+    v2 = oracle.lpa(g, order=order, tau=-1.0, max_iters=1, init_labels=fb["labels"], init_flags=fb["flags"])
+    assert list(r["changed"][2:]) == list(fb["changed"])
+    assert r["verify_changed"] == v1["changed"][0] + v2["changed"][0]
+    assert np.array_equal(r["labels"], v2["labels"])
+    assert r["verified"] == (v2["changed"][0] <= tau * g.n)
