@@ -5,7 +5,8 @@ leg of the benchmark may import this package.  The product library never
 calls it and shares no code with it.
 
 * ``lpa``          Algorithm 1 (Section 4.2) executed sequentially in an
-                   explicit vertex order (C, ``lpa_oracle.c``).
+                   explicit vertex order (C, ``lpa_oracle.c``), strict or
+                   non-strict (Section 4.1.5; ``TIE_A``, ``TIE_P``).
 * ``color``        greedy colouring in decreasing (degree, hash, id) priority; with
                    ``color_order`` it fixes the order of the deterministic mode.
 * ``modularity``   Eq. (1), community form, exact integers + one FP64 division.
@@ -24,6 +25,10 @@ from . import build as _build
 from .metrics import nmi  # noqa: F401
 
 MAX_STATS = 64
+# Non-strict tie rule: among the labels of maximum weight, vertex v takes the
+# label c of smallest rank ((c + 1) * TIE_A^(1 + v mod 64)) mod TIE_P (lpa_oracle.c)
+TIE_P = 2147483647
+TIE_A = 1580030173
 _lib = None
 
 
@@ -35,7 +40,7 @@ def _load():
         lib = ctypes.CDLL(str(_build.LIB))
         vp = ctypes.c_void_p
         lib.oracle_lpa.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                   vp, vp, vp, vp, vp, vp, vp, vp, vp]
+                                   vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
         lib.oracle_lpa.restype = ctypes.c_int
         lib.oracle_color.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_uint32, vp]
         lib.oracle_color.restype = ctypes.c_int64
@@ -57,8 +62,9 @@ def _csr_arrays(g):
 
 
 def lpa(g, order=None, tau: float = 0.05, max_iters: int = 20, prune: bool = True, init_labels=None,
-        init_flags=None) -> dict:
-    """Strict LPA on CSR ``g`` (attributes n, offsets, indices, weights).
+        init_flags=None, strict: bool = True) -> dict:
+    """Strict (or, with ``strict=False``, non-strict) LPA on CSR ``g``
+    (attributes n, offsets, indices, weights).
 
     Returns a dict with ``labels``, ``flags``, per-sweep ``changed``,
     ``processed``, ``scanned`` (length = iterations, capped at 64),
@@ -79,7 +85,7 @@ def lpa(g, order=None, tau: float = 0.05, max_iters: int = 20, prune: bool = Tru
     conv = ctypes.c_int32()
     rc = lib.oracle_lpa(n, _p(off), _p(idx), _p(w), _p(order), float(tau), int(max_iters), int(bool(prune)),
                         _p(il), _p(ifl), _p(labels), _p(flags), _p(changed), _p(processed), _p(scanned),
-                        ctypes.addressof(it), ctypes.addressof(conv))
+                        ctypes.addressof(it), ctypes.addressof(conv), 0 if strict else 1)
     if rc != 0:
         raise ValueError(f"oracle_lpa failed ({rc})")
     k = min(it.value, MAX_STATS)

@@ -13,7 +13,8 @@
  *                      explicit order pi; the update rule is Eq. (2) (the
  *                      label-propagation argmax, Section 3.3) in its strict
  *                      form (Section 4.1.5, and the smallest-id tie rule
- *                      stated in Section 2).
+ *                      stated in Section 2) or, on request, the non-strict
+ *                      form of Section 4.1.5 (tie_rank below).
  *   oracle_color       greedy colouring in decreasing (degree, hash, id)
  *                      priority; defines the vertex order of the
  *                      deterministic GPU mode.
@@ -35,6 +36,25 @@
 #include <string.h>
 
 #define ORACLE_MAX_STATS 64
+
+/* Non-strict tie rule (Section 4.1.5 names it: among the labels of maximum
+ * weight one is picked by a modulo operation on the label id instead of the
+ * smallest id).  Reading taken here: vertex v ranks the dominant labels by
+ *   r_v(c) = ((c + 1) * A^(1 + (v mod 64))) mod P,  P = 2^31 - 1 (prime),
+ * A = TIE_A, and takes the label of smallest rank.  For a fixed v, distinct
+ * labels get distinct ranks (P is prime and neither factor is 0 mod P), so
+ * the pick is unique; it changes with v mod 64 like a random pick would. */
+#define TIE_P 2147483647ull
+#define TIE_A 1580030173ull
+
+/* A^(1 + (v mod 64)) mod P, by repeated multiplication */
+static uint64_t tie_mult(int64_t v) {
+  uint64_t m = 1;
+  for (int64_t k = 0; k <= v % 64; ++k) m = m * TIE_A % TIE_P;
+  return m;
+}
+
+static uint64_t tie_rank(int32_t c, uint64_t mult) { return ((uint64_t)c + 1) % TIE_P * mult % TIE_P; }
 
 /* MurmurHash3 32-bit finaliser (Appleby, public domain). */
 static uint32_t fmix32(uint32_t h) {
@@ -64,12 +84,14 @@ static int weights_ok(int64_t m, const float *w) {
  * (flagged vertices visited that have at least one stored entry) and
  * scanned[s] (stored entries of those vertices).  *iterations = number of
  * lpaMove calls executed; *converged = 1 when the stop test held.
+ * nonstrict = 0: ties go to the smallest label id (strict LPA); 1: to the
+ * smallest rank r_v (non-strict LPA, above).
  * Returns 0, or -1 for invalid arguments, -3 for non-integral weights.
  */
 int oracle_lpa(int64_t n, const int64_t *off, const int32_t *idx, const float *w, const int32_t *order,
                double tau, int max_iters, int prune, const int32_t *init_labels, const uint8_t *init_flags,
                int32_t *labels, uint8_t *flags_out, int64_t *changed, int64_t *processed, int64_t *scanned,
-               int32_t *iterations, int32_t *converged) {
+               int32_t *iterations, int32_t *converged, int nonstrict) {
   if (n < 0 || !off || (off[n] > 0 && !idx) || !labels || max_iters < 0) return -1;
   const int64_t m = off[n];
   if (!weights_ok(m, w)) return -3;
@@ -115,11 +137,13 @@ int oracle_lpa(int64_t n, const int64_t *off, const int32_t *idx, const float *w
         acc[c] += w ? (uint64_t)w[k] : 1u;
       }
       if (nt == 0) continue; /* no neighbour other than itself: keep the label */
-      /* most weighted label; the smallest id among equals */
+      /* most weighted label; among equals the smallest id (strict) or rank */
+      const uint64_t mult = nonstrict ? tie_mult(v) : 0;
       int32_t best = touched[0];
       for (int64_t t = 1; t < nt; ++t) {
         const int32_t c = touched[t];
-        if (acc[c] > acc[best] || (acc[c] == acc[best] && c < best)) best = c;
+        const int smaller = nonstrict ? tie_rank(c, mult) < tie_rank(best, mult) : c < best;
+        if (acc[c] > acc[best] || (acc[c] == acc[best] && smaller)) best = c;
       }
       for (int64_t t = 0; t < nt; ++t) seen[touched[t]] = 0;
       if (best == C[v]) continue;

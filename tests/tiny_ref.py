@@ -20,7 +20,9 @@ def dense(n, offsets, indices, weights=None):
     return W, adj
 
 
-def lpa_dense(W, adj, order=None, tau=0.05, max_iters=20, prune=True):
+def lpa_dense(W, adj, order=None, tau=0.05, max_iters=20, prune=True, tie=None):
+    """tie(c, v): key of label c among equally heavy labels at vertex v (the
+    smallest key wins); None = the label id itself (strict LPA)."""
     n = len(W)
     order = list(range(n)) if order is None else [int(v) for v in order]
     label = list(range(n))
@@ -39,7 +41,8 @@ def lpa_dense(W, adj, order=None, tau=0.05, max_iters=20, prune=True):
             tally = {}
             for j in nbrs:
                 tally[label[j]] = tally.get(label[j], 0) + W[v][j]
-            best = max(tally.items(), key=lambda kv: (kv[1], -kv[0]))[0]
+            top = max(tally.values())
+            best = min((c for c, x in tally.items() if x == top), key=lambda c: c if tie is None else tie(c, v))
             if best != label[v]:
                 label[v] = best
                 moved += 1
