@@ -1,20 +1,24 @@
-"""Benchmark: strict label propagation on an R-MAT graph, one MI355X.
+"""Benchmark: strict label propagation on R-MAT graphs, one MI355X.
 
-Workload (default): R-MAT scale 24, edge factor 16, (a, b, c, d) = (0.57,
-0.19, 0.19, 0.05), symmetrised, self-loops and duplicates removed, integer
-weights 1..8 stored as fp32, seed 1; tau = 0.05, at most 20 sweeps, vertex
-pruning on.  A step is one whole run of the method (every sweep to
+Headline workload (default): R-MAT scale 26, edge factor 32, (a, b, c, d) =
+(0.57, 0.19, 0.19, 0.05), symmetrised, self-loops and duplicates removed,
+integer weights 1..8 stored as fp32, seed 1 (67.1 M vertices, 4.16 G stored
+entries), generated and assembled on the GPU; tau = 0.05, at most 20 sweeps,
+vertex pruning on.  A step is one whole run of the method (every sweep to
 convergence) in the asynchronous mode, with the graph already resident in HBM.
 
 Printed: one JSON line.  ``value`` is edges scanned per second over the timed
 runs (the per-sweep rate, weighted by the work of each sweep); the line also
 carries the sweep-0 rate, time to converge, modularity, the deterministic
 mode's figures, the roofline of the dominant kernel (HIP events on the
-library's stream) and the sequential CPU oracle timed on a bounded sample.
+library's stream), the same figures on R-MAT scale 24 (edge factor 16), the
+batch of 4,096 uneven SBMs, plain-vs-gated comparisons, and the sequential CPU
+oracle timed on bounded samples of these workloads.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 from pathlib import Path
@@ -234,6 +238,211 @@ def batch_workload(args):
         res["det_tuning"] = {"variants": [int(x) for x in dv], "bins": list(dlim), "seconds": round(time.time() - t, 2)}
         res["det_tuned"] = timed(abi.LPA_MODE_DETERMINISTIC, "det tuned")
     B.close()
+    return res, (csr, vptr)
+
+
+def _stats_summary(runs, m):
+    ttc = [r["total_ms"] for r in runs]
+    sweep0 = [r["ms"][0] for r in runs if r["iterations"] > 0]
+    return {"time_to_converge_ms": {"median": round(float(np.median(ttc)), 3), "min": round(float(np.min(ttc)), 3)},
+            "sweeps": runs[0]["iterations"],
+            "sweep0_edges_per_s": round(m / (np.median(sweep0) * 1e-3), 1) if sweep0 else None,
+            "m_over_time_to_converge": round(m / (np.median(ttc) * 1e-3), 1)}
+
+
+def _apply(G, cfg):
+    G.set_variants(cfg["variants"])
+    G.set_async_schedule(*cfg["schedule"])
+    G.set_bins(cfg["bins"])
+
+
+def tune_async(args, G, workload):
+    """Autotuned asynchronous configuration of handle G (or the one given on
+    the command line); when the autotuner's near-tie pick differs from the
+    configuration the committed byte counters of this workload were taken
+    with, that one is timed instead so the counters apply."""
+    from paper_2312_08140_amd import abi
+    if args.variants or args.schedule or args.bins:
+        v = [int(x) for x in args.variants.split(",")] if args.variants else [0] * 6
+        s = [int(x) for x in args.schedule.split(",")] if args.schedule else [16, 2, 4]
+        lim = [int(x) for x in args.bins.split(",")] if args.bins else list(DEFAULT_BINS)
+        tuned = {"variants": v, "schedule": s, "bins": lim, "seconds": 0.0, "given": True}
+        _apply(G, tuned)
+        return tuned
+    if args.no_tune:
+        return None
+    t = time.time()
+    variants, bin_ms, sched, lim = G.autotune(args.tau, args.max_iters, abi.LPA_MODE_ASYNC)
+    tuned = {"variants": [int(v) for v in variants], "schedule": list(sched), "bins": list(lim),
+             "seconds": round(time.time() - t, 2), "source": "autotune"}
+    prof = profiled_config(workload)
+    if prof is not None and (prof[0] != tuned["variants"] or prof[1] != tuned["schedule"] or prof[2] != tuned["bins"]):
+        tuned["autotune_pick"] = {"variants": tuned["variants"], "schedule": tuned["schedule"], "bins": tuned["bins"]}
+        tuned.update(variants=prof[0], schedule=prof[1], bins=prof[2], source="autotune pick recorded with the profile")
+        _apply(G, tuned)
+    return tuned
+
+
+def roofline_of(G, args, out, tuned, workload):
+    """Per-kernel HIP-event timing run (eager launches on the library's stream)
+    and the roofline of the dominant kernel on algorithmic bytes."""
+    from paper_2312_08140_amd import abi
+    _, kt = G.run(args.tau, args.max_iters, abi.LPA_MODE_ASYNC, True, flags=abi.LPA_FLAG_KERNEL_TIMING,
+                  labels_out=out)
+    kb = kernel_bytes(kt)
+    kms = dict(kt["kernel_ms"])
+    hub_ms = sum(kms.get(k, 0) for k in ("hub_plan", "hub_chunk", "hub_part", "hub_finish"))
+    dominant = max(kms, key=lambda k: kms[k])
+    per_kernel = {}
+    for k, ms in kms.items():
+        byt = kb.get(k, 0)
+        ms_eff = hub_ms if k == "hub_chunk" else ms
+        per_kernel[k] = dict(ms=round(ms, 4), launches=kt["kernel_launches"][k], bytes=int(byt),
+                             gbs=round(byt / (ms_eff * 1e-3) / 1e9, 1) if byt and ms_eff > 0 else None)
+    dom_bytes = kb.get(dominant, 0)
+    dom_launches = kt["kernel_launches"][dominant]
+    dom_ms = kms[dominant] / dom_launches
+    achieved = (dom_bytes / dom_launches) / (dom_ms * 1e-3) / 1e9
+    total_bytes = sum(kb.values())
+    sweep_ms = sum(kt["ms"])
+    return {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": int(dom_bytes / dom_launches), "avg_launch_ms": round(dom_ms, 5),
+            "traffic": measured_traffic(dominant, tuned, workload),
+            "whole_sweep": {"bytes": int(total_bytes), "ms": round(sweep_ms, 3),
+                            "achieved": round(total_bytes / (sweep_ms * 1e-3) / 1e9, 1),
+                            "frac": round(total_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "per_kernel": per_kernel}
+
+
+def deterministic_of(G, args, out, m, tuned):
+    """The deterministic mode on its own tuning (colour class by colour class
+    it prefers other bin limits and shapes; results do not depend on them)."""
+    from paper_2312_08140_amd import abi
+    t = time.time()
+    det_tuning = None
+    if tuned is not None and not tuned.get("given"):
+        dv, _, _, dlim = G.autotune(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC)
+        det_tuning = {"variants": [int(x) for x in dv], "bins": list(dlim), "seconds": round(time.time() - t, 2)}
+    _, sd = G.run(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC, True, labels_out=out)
+    q_det = G.modularity(out)
+    runs = []
+    for _ in range(3):
+        _, sd2 = G.run(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC, True, labels_out=out)
+        runs.append(sd2)
+    det = dict(colouring_and_capture_ms=round(sd["setup_ms"], 1), colours=sd["num_colors"],
+               modularity=round(q_det, 6), tuning=det_tuning, **_stats_summary(runs, m))
+    det["edges_per_s"] = round(sum(runs[-1]["edges_scanned"]) / (runs[-1]["total_ms"] * 1e-3), 1)
+    if tuned is not None:  # back to the asynchronous tuning
+        _apply(G, tuned)
+    return det, q_det
+
+
+def timed_async(G, args, out, steps, warmup):
+    from paper_2312_08140_amd import abi
+    import torch
+    for _ in range(warmup):
+        G.run(args.tau, args.max_iters, abi.LPA_MODE_ASYNC, True, labels_out=out)
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = G.run(args.tau, args.max_iters, abi.LPA_MODE_ASYNC, True, labels_out=out)
+        runs.append(st)
+    torch.cuda.synchronize()
+    return runs, time.perf_counter() - t0
+
+
+def secondary_rmat(args):
+    """R-MAT scale 24, edge factor 16 (the mid-size configuration): asynchronous
+    and deterministic figures, tuned like the headline."""
+    import torch
+    from paper_2312_08140_amd import abi, graphgen
+    t = time.time()
+    d = graphgen.rmat_device(args.secondary_scale, args.secondary_edge_factor, seed=args.seed, weighted=True)
+    G = abi.LPAGraph(n=d.n, offsets=d.offsets, indices=d.indices, weights=d.weights)
+    torch.cuda.synchronize()
+    wl = f"rmat{args.secondary_scale}"
+    res = {"workload": f"rmat{args.secondary_scale}_ef{args.secondary_edge_factor}_w1-8_seed{args.seed}", "n": d.n,
+           "m": d.m, "generate_and_create_s": round(time.time() - t, 2)}
+    sub = argparse.Namespace(**{**vars(args), "variants": None, "schedule": None, "bins": None})
+    tuned = tune_async(sub, G, wl)
+    out = torch.empty(d.n, dtype=torch.int32, device="cuda:0")
+    runs, wall = timed_async(G, args, out, 10, 2)
+    res.update(value=round(sum(sum(r["edges_scanned"]) for r in runs) / wall, 1),
+               ms_per_run=round(wall * 1e3 / len(runs), 3), modularity=round(G.modularity(out), 6), tuning=tuned,
+               **_stats_summary(runs, d.m))
+    lab_a = out.clone()
+    _, sv = G.run(args.tau, args.max_iters, abi.LPA_MODE_ASYNC, True, flags=abi.LPA_FLAG_VERIFY, labels_out=out)
+    res["verified"] = bool(sv["verified"])
+    res["verify_changed"] = int(sv["verify_changed"])
+    res["roofline"] = roofline_of(G, args, out, tuned, wl)
+    if not args.no_det:
+        res["deterministic"], q_det = deterministic_of(G, args, out, d.m, tuned)
+        res["q_async_minus_det"] = round(res["modularity"] - q_det, 6)
+    log(f"{res['workload']}: {res['value'] / 1e9:.1f} G edges/s, {res['ms_per_run']} ms/run")
+    G.close()
+    return res, d, lab_a
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
+
+
+def cpu_baselines(args, head_host, sec_host, batch_in):
+    """The sequential C oracle (one core; it is sequential by definition) on
+    bounded samples: sweep 0 of the headline graph, the mid-size R-MAT to
+    convergence in id order and in (colour, id) order, and the 4,096-graph
+    batch to convergence spread over every host core (one graph per thread)."""
+    import oracle
+    res = {"cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    if head_host is not None:
+        t = time.perf_counter()
+        r = oracle.lpa(head_host, tau=args.tau, max_iters=1, prune=True)
+        dt = time.perf_counter() - t
+        res["headline_sweep0"] = {"value": round(float(r["scanned"].sum()) / dt, 1), "unit": "edges/s", "cores": 1,
+                                  "seconds": round(dt, 2), "entries": int(r["scanned"].sum()),
+                                  "sample": "sweep 0 (every vertex) of the headline graph, id order"}
+        log(f"cpu oracle headline sweep 0: {res['headline_sweep0']}")
+    if sec_host is not None:
+        rows = {}
+        t = time.perf_counter()
+        r = oracle.lpa(sec_host, tau=args.tau, max_iters=args.max_iters, prune=True)
+        dt = time.perf_counter() - t
+        rows["id_order"] = {"seconds": round(dt, 2), "sweeps": r["iterations"], "entries": int(r["scanned"].sum()),
+                            "edges_per_s": round(float(r["scanned"].sum()) / dt, 1),
+                            "m_over_time_to_converge": round(sec_host.m / dt, 1)}
+        t = time.perf_counter()
+        col, nc = oracle.color(sec_host, 0)
+        order = oracle.color_order(col, nc)
+        tc = time.perf_counter() - t
+        t = time.perf_counter()
+        r = oracle.lpa(sec_host, order=order, tau=args.tau, max_iters=args.max_iters, prune=True)
+        dt = time.perf_counter() - t
+        rows["colour_order"] = {"seconds": round(dt, 2), "colouring_s": round(tc, 2), "sweeps": r["iterations"],
+                                "entries": int(r["scanned"].sum()),
+                                "edges_per_s": round(float(r["scanned"].sum()) / dt, 1),
+                                "m_over_time_to_converge": round(sec_host.m / dt, 1)}
+        res["secondary_to_convergence"] = rows
+        log(f"cpu oracle secondary: {rows}")
+    if batch_in is not None:
+        g, vptr = batch_in
+        threads = os.cpu_count() or 1
+        t = time.perf_counter()
+        ref = oracle.lpa_batch(g, vptr, deterministic=False, tau=args.tau, max_iters=args.max_iters, threads=threads)
+        dt = time.perf_counter() - t
+        ent = int(sum(int(r["scanned"].sum()) for r in ref))
+        res["batch_to_convergence"] = {"seconds": round(dt, 2), "cores": threads, "entries": ent,
+                                       "edges_per_s": round(ent / dt, 1), "m_over_time": round(g.m / dt, 1),
+                                       "sample": f"{len(vptr) - 1} graphs, id order, one graph per thread"}
+        log(f"cpu oracle batch: {res['batch_to_convergence']}")
     return res
 
 
@@ -242,26 +451,27 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=24)
-    ap.add_argument("--edge-factor", type=int, default=16)
+    ap.add_argument("--scale", type=int, default=26)
+    ap.add_argument("--edge-factor", type=int, default=32)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tau", type=float, default=0.05)
     ap.add_argument("--max-iters", type=int, default=20)
+    ap.add_argument("--secondary-scale", type=int, default=24, help="mid-size R-MAT scale (0: skip)")
+    ap.add_argument("--secondary-edge-factor", type=int, default=16)
     ap.add_argument("--no-det", action="store_true", help="skip the deterministic-mode figures")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default schedule and kernel shapes")
     ap.add_argument("--variants", default=None,
-                    help="kernel shape per degree bin, e.g. 2,1,1,2,2,1 (instead of autotuning; with --schedule)")
+                    help="kernel shape per degree bin of the headline graph, e.g. 2,1,1,2,2,1 (instead of autotuning)")
     ap.add_argument("--bins", default=None,
                     help="degree limits of bins 0-5, e.g. 4,16,64,256,1024,4096 (instead of autotuning)")
     ap.add_argument("--schedule", default=None,
                     help="asynchronous schedule early_steps,early_sweeps,late_steps (instead of autotuning)")
     ap.add_argument("--no-gate", action="store_true", help="skip the plain-vs-gated comparison")
-    ap.add_argument("--batch", type=int, default=0,
-                    help="also run the batched workload of this many SBMs (4096 = the uneven SBM batch)")
+    ap.add_argument("--batch", type=int, default=4096,
+                    help="batched workload of this many uneven SBMs (4096 = the benchmark batch; 0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -272,6 +482,7 @@ def main():
     from paper_2312_08140_amd import abi, graphgen
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t_start = time.time()
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
         dst = torch.empty_like(src)
@@ -279,146 +490,85 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     t = time.time()
-    g = graphgen.rmat(args.scale, args.edge_factor, seed=args.seed, weighted=True)
-    log(f"generated R-MAT scale {args.scale}: n={g.n} m={g.m} in {time.time() - t:.1f}s")
+    d = graphgen.rmat_device(args.scale, args.edge_factor, seed=args.seed, weighted=True)
+    gen_s = time.time() - t
+    n_head, m_head = d.n, d.m
+    log(f"generated R-MAT scale {args.scale} on the GPU: n={d.n} m={d.m} in {gen_s:.1f}s")
     t = time.time()
-    G = abi.LPAGraph(g)
+    G = abi.LPAGraph(n=d.n, offsets=d.offsets, indices=d.indices, weights=d.weights)
     torch.cuda.synchronize()
-    log(f"uploaded in {time.time() - t:.1f}s")
+    create_s = time.time() - t
+    log(f"lpa_create in {create_s:.1f}s")
+    workload = f"rmat{args.scale}"
     A = abi.LPA_MODE_ASYNC
-    out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
-    tuned = None
-    if args.variants or args.schedule or args.bins:
-        v = [int(x) for x in args.variants.split(",")] if args.variants else [0] * 6
-        s = [int(x) for x in args.schedule.split(",")] if args.schedule else [16, 2, 4]
-        lim = [int(x) for x in args.bins.split(",")] if args.bins else list(DEFAULT_BINS)
-        G.set_variants(v)
-        G.set_async_schedule(*s)
-        G.set_bins(lim)
-        tuned = {"variants": v, "schedule": s, "bins": lim, "seconds": 0.0, "given": True}
-    elif not args.no_tune:
-        t = time.time()
-        variants, bin_ms, sched, lim = G.autotune(args.tau, args.max_iters, A)
-        tuned = {"variants": [int(v) for v in variants], "schedule": list(sched), "bins": list(lim),
-                 "seconds": round(time.time() - t, 2), "source": "autotune"}
-        prof = profiled_config(f"rmat{args.scale}")
-        if prof is not None and (prof[0] != tuned["variants"] or prof[1] != tuned["schedule"]
-                                 or prof[2] != tuned["bins"]):
-            # the autotuner's near-ties flip between runs; time the configuration it
-            # chose when the byte counters were taken, so the counters apply
-            tuned["autotune_pick"] = {"variants": tuned["variants"], "schedule": tuned["schedule"],
-                                      "bins": tuned["bins"]}
-            tuned.update(variants=prof[0], schedule=prof[1], bins=prof[2],
-                         source="autotune pick recorded with the profile")
-            G.set_variants(prof[0])
-            G.set_async_schedule(*prof[1])
-            G.set_bins(prof[2])
-        log(f"autotune: {tuned}")
+    out = torch.empty(d.n, dtype=torch.int32, device="cuda:0")
+    tuned = tune_async(args, G, workload)
+    log(f"autotune: {tuned}")
 
-    for _ in range(args.warmup):
-        G.run(args.tau, args.max_iters, A, True, labels_out=out)
-    torch.cuda.synchronize()
-    runs = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, st = G.run(args.tau, args.max_iters, A, True, labels_out=out)
-        runs.append(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    runs, wall = timed_async(G, args, out, args.steps, args.warmup)
     scanned = sum(sum(r["edges_scanned"]) for r in runs)
     value = scanned / wall
     ms_per_step = wall * 1000.0 / args.steps
-    sweep0 = [r["ms"][0] for r in runs if r["iterations"] > 0]
     q_async = G.modularity(out)
-    ttc = [r["total_ms"] for r in runs]
-    log(f"async: {value / 1e9:.2f} G edges/s, {ms_per_step:.2f} ms/run, sweeps {runs[0]['iterations']}, Q {q_async:.5f}")
+    log(f"async: {value / 1e9:.2f} G edges/s, {ms_per_step:.2f} ms/run, sweeps {runs[0]['iterations']}, Q {q_async:.6f}")
+    lab_async = out.clone()
+    _, sv = G.run(args.tau, args.max_iters, A, True, flags=abi.LPA_FLAG_VERIFY, labels_out=out)
+    verify = {"verified": bool(sv["verified"]), "verify_changed": int(sv["verify_changed"]),
+              "modularity": round(G.modularity(out), 6)}
+    roofline = roofline_of(G, args, out, tuned, workload)
+    log(f"dominant kernel {roofline['kernel']}: {roofline['achieved']:.0f} GB/s ({roofline['frac'] * 100:.1f}% of peak)")
 
-    # per-kernel HIP-event timing (eager launches on the library's stream)
-    _, kt = G.run(args.tau, args.max_iters, A, True, flags=abi.LPA_FLAG_KERNEL_TIMING, labels_out=out)
-    kb = kernel_bytes(kt)
-    kms = dict(kt["kernel_ms"])
-    hub_ms = sum(kms.get(k, 0) for k in ("hub_plan", "hub_chunk", "hub_part", "hub_finish"))
-    dominant = max(kms, key=lambda k: kms[k])
-    per_kernel = {}
-    for k, ms in kms.items():
-        byt = kb.get(k, 0)
-        if k == "hub_chunk":
-            ms_eff = hub_ms
-        else:
-            ms_eff = ms
-        per_kernel[k] = dict(ms=round(ms, 4), launches=kt["kernel_launches"][k],
-                             gbs=round(byt / (ms_eff * 1e-3) / 1e9, 1) if byt and ms_eff > 0 else None)
-    dom_bytes = kb.get(dominant, 0)
-    dom_launches = kt["kernel_launches"][dominant]
-    dom_ms = kms[dominant] / dom_launches
-    achieved = (dom_bytes / dom_launches) / (dom_ms * 1e-3) / 1e9
-    total_bytes = sum(kb.values())
-    sweep_ms = sum(kt["ms"])
-    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "bytes_per_launch": int(dom_bytes / dom_launches), "avg_launch_ms": round(dom_ms, 5),
-                "traffic": measured_traffic(dominant, tuned, f"rmat{args.scale}"),
-                "whole_sweep": {"bytes": int(total_bytes), "ms": round(sweep_ms, 3),
-                                "achieved": round(total_bytes / (sweep_ms * 1e-3) / 1e9, 1),
-                                "frac": round(total_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-                "per_kernel": per_kernel}
-    log(f"dominant kernel {dominant}: {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS * 100:.1f}% of peak)")
-
-    det = None
+    det, q_det = (None, None)
     if not args.no_det:
-        t = time.time()
-        det_tuning = None
-        if tuned is not None and not tuned.get("given"):
-            # the deterministic mode runs colour class by colour class: its own
-            # bin limits and kernel shapes (the results do not depend on them)
-            dv, _, _, dlim = G.autotune(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC)
-            det_tuning = {"variants": [int(x) for x in dv], "bins": list(dlim), "seconds": round(time.time() - t, 2)}
-        _, sd = G.run(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC, True, labels_out=out)
-        q_det = G.modularity(out)
-        _, sd2 = G.run(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC, True, labels_out=out)
-        det = dict(time_to_converge_ms=round(sd2["total_ms"], 3), colouring_and_capture_ms=round(sd["setup_ms"], 1),
-                   sweeps=sd2["iterations"], colours=sd2["num_colors"], modularity=round(q_det, 6),
-                   edges_per_s=round(sum(sd2["edges_scanned"]) / (sd2["total_ms"] * 1e-3), 1),
-                   sweep0_edges_per_s=round(g.m / (sd2["ms"][0] * 1e-3), 1) if sd2["iterations"] else None,
-                   tuning=det_tuning)
-        log(f"det: {det} ({time.time() - t:.1f}s)")
-        if det_tuning is not None:  # back to the asynchronous tuning for what follows
-            G.set_variants(tuned["variants"])
-            G.set_async_schedule(*tuned["schedule"])
-            G.set_bins(tuned["bins"])
-
-    batch = batch_workload(args) if args.batch else None
+        det, q_det = deterministic_of(G, args, out, d.m, tuned)
+        log(f"det: {det}")
 
     gated = None
     if not args.no_gate:
-        gated = gate_comparison(args, G, g, runs, q_async, out, tuned)
+        gated = gate_comparison(args, G, d, runs, q_async, out, tuned)
 
+    secondary, sec_dev = None, None
+    if args.secondary_scale:
+        secondary, sec_dev, _ = secondary_rmat(args)
+
+    batch, batch_in = None, None
+    if args.batch:
+        batch, batch_in = batch_workload(args)
+
+    head_host = None
+    if not args.no_cpu:
+        G.close()
+        G = None
+        head_host = d.to_host()
+    del d
+    torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu:
-        import oracle
-        t = time.perf_counter()
-        r = oracle.lpa(g, tau=args.tau, max_iters=args.cpu_sweeps, prune=True)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(float(r["scanned"].sum()) / dt, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
-               "sample": f"sequential oracle, id order, first {args.cpu_sweeps} sweeps of the same graph "
-                         f"({int(r['scanned'].sum())} entries scanned in {dt:.1f}s)"}
-        log(f"cpu oracle: {cpu['value'] / 1e6:.1f} M edges/s")
+        sec_host = sec_dev.to_host() if sec_dev is not None else None
+        del sec_dev
+        extra = cpu_baselines(args, head_host, sec_host, batch_in)
+        hs = extra.get("headline_sweep0")
+        cpu = {"value": hs["value"] if hs else None, "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": "sequential C oracle (one thread), sweep 0 of the headline graph in id order "
+                         "(every vertex flagged; all stored entries scanned once)", **extra}
 
     res = {
         "metric": "LPA edges/s per sweep + time-to-converge at equal modularity, plain vs gated",
         "value": round(value, 1), "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"rmat{args.scale}_ef{args.edge_factor}_w1-8_seed{args.seed}", "n": g.n, "m": g.m,
-                   "mode": "async", "prune": True, "tau": args.tau, "max_iters": args.max_iters},
-        "sweep0_edges_per_s": round(g.m / (np.median(sweep0) * 1e-3), 1) if sweep0 else None,
-        "time_to_converge_ms": {"median": round(float(np.median(ttc)), 3), "min": round(float(np.min(ttc)), 3)},
-        "sweeps": runs[0]["iterations"], "modularity": round(q_async, 6),
-        "m_over_time_to_converge": round(g.m / (np.median(ttc) * 1e-3), 1),
-        "deterministic": det, "tuning": tuned, "gated": gated, "batch": batch, "roofline": roofline, "cpu_baseline": cpu,
+        "config": {"workload": f"rmat{args.scale}_ef{args.edge_factor}_w1-8_seed{args.seed}", "n": n_head,
+                   "m": m_head, "mode": "async", "prune": True, "tau": args.tau, "max_iters": args.max_iters},
+        "modularity": round(q_async, 6), "verification": verify,
+        "q_async_minus_det": round(q_async - q_det, 6) if q_det is not None else None,
+        **_stats_summary(runs, m_head),
+        "generate_s": round(gen_s, 2), "create_s": round(create_s, 2),
+        "deterministic": det, "tuning": tuned, "gated": gated, "secondary": secondary, "batch": batch,
+        "roofline": roofline, "cpu_baseline": cpu, "bench_seconds": round(time.time() - t_start, 1),
     }
     print(json.dumps(res), flush=True)
-    G.close()
+    if G is not None:
+        G.close()
 
 
 if __name__ == "__main__":

@@ -3,6 +3,10 @@
 * ``lib/libgvelpa.so``: the HIP library behind the C ABI in ``include/gvelpa.h``
   (gfx950 device code + host runtime), built with ``hipcc``.
 * ``lib/libgvelpa_gen.so``: the host-only seeded graph generators (g++/OpenMP).
+* ``lib/libgvelpa_gen_gpu.so``: the same R-MAT generator assembled into CSR on
+  the GPU (``include/gvelpa_gen.h``), built with ``hipcc``.
+* ``lib/libgvelpa_cpu.so``: the multicore CPU comparator in the paper's design
+  (``include/gvelpa_cpu.h``, g++/OpenMP; never called by the GPU path).
 
 ``build_all()`` always recompiles; ``ensure_built()`` compiles only what is
 missing.  Nothing here runs any GPU code.
@@ -21,6 +25,8 @@ INCLUDE = ROOT / "include"
 
 LPA_LIB = LIBDIR / "libgvelpa.so"
 GEN_LIB = LIBDIR / "libgvelpa_gen.so"
+GEN_GPU_LIB = LIBDIR / "libgvelpa_gen_gpu.so"
+CPU_LIB = LIBDIR / "libgvelpa_cpu.so"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -56,6 +62,23 @@ def build_gen() -> Path:
     return GEN_LIB
 
 
+def build_cpu() -> Path:
+    LIBDIR.mkdir(exist_ok=True)
+    tmp = CPU_LIB.with_suffix(".so.tmp")
+    _run(["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-I", str(INCLUDE),
+          str(CSRC / "cpu" / "lpa_omp.cpp"), "-o", str(tmp)])
+    os.replace(tmp, CPU_LIB)
+    return CPU_LIB
+
+
+def build_gen_gpu() -> Path:
+    LIBDIR.mkdir(exist_ok=True)
+    tmp = GEN_GPU_LIB.with_suffix(".so.tmp")
+    _run([HIPCC, *HIP_FLAGS, "-shared", "-I", str(INCLUDE), str(CSRC / "gen" / "rmat_gpu.hip"), "-o", str(tmp)])
+    os.replace(tmp, GEN_GPU_LIB)
+    return GEN_GPU_LIB
+
+
 def build_lpa() -> Path:
     LIBDIR.mkdir(exist_ok=True)
     objdir = PKG / "_build"
@@ -83,11 +106,17 @@ def build_lpa() -> Path:
 
 def build_all() -> None:
     build_gen()
+    build_cpu()
+    build_gen_gpu()
     build_lpa()
 
 
 def ensure_built() -> None:
     if not GEN_LIB.exists():
         build_gen()
+    if not GEN_GPU_LIB.exists():
+        build_gen_gpu()
+    if not CPU_LIB.exists():
+        build_cpu()
     if not LPA_LIB.exists():
         build_lpa()

@@ -1,5 +1,6 @@
-// Seeded synthetic graph generators: R-MAT, stochastic block model (SBM) and a
-// batch of uneven SBMs laid out block-diagonally.
+// Seeded synthetic graph generators: R-MAT, stochastic block model (SBM), a
+// batch of uneven SBMs laid out block-diagonally, and a sparse road-like
+// lattice (low average degree).
 //
 // This module only builds inputs.  It holds none of the label-propagation
 // arithmetic, and both the sequential oracle and the GPU library consume the
@@ -288,6 +289,35 @@ int gg_sbm_batch(int32_t count, const int64_t *n_g, const int64_t *k_g, const do
   };
   *n_out = n;
   return build_csr(n, (int64_t)edges.size(), src, weighted, stream_key(seed_base, 0x57454947ull), alloc, m_out);
+}
+
+// Low-degree, road-like graph: the 4-neighbour lattice of rows x cols
+// vertices (row-major ids), each lattice edge kept with probability p_keep
+// (one counter-based draw per candidate edge: horizontal ones first, then
+// vertical).  With p_keep = 0.55 the average degree is about 2.2, the order
+// of the road and k-mer graphs of the paper's dataset.
+int gg_grid(int64_t rows, int64_t cols, double p_keep, uint64_t seed, int weighted, alloc_fn alloc, int64_t *n_out,
+            int64_t *m_out) {
+  if (rows < 1 || cols < 1 || rows * cols >= ((int64_t)1 << 31) || !(p_keep >= 0.0) || p_keep > 1.0) return -2;
+  const int64_t n = rows * cols;
+  const int64_t nh = rows * (cols - 1), nv = (rows - 1) * cols;
+  const uint64_t thr = p_keep >= 1.0 ? (1ull << 32) : (uint64_t)std::llround(p_keep * 4294967296.0);
+  const uint64_t key = stream_key(seed, 0x47524944ull);
+  auto src = [&](int64_t e, uint32_t &u, uint32_t &v) -> bool {
+    if ((draw(key, (uint64_t)e) >> 32) >= thr) return false;
+    if (e < nh) {
+      const int64_t r = e / (cols - 1), c = e % (cols - 1);
+      u = (uint32_t)(r * cols + c);
+      v = u + 1;
+    } else {
+      const int64_t f = e - nh;
+      u = (uint32_t)f;
+      v = (uint32_t)(f + cols);
+    }
+    return true;
+  };
+  *n_out = n;
+  return build_csr(n, nh + nv, src, weighted, stream_key(seed, 0x57454947ull), alloc, m_out);
 }
 
 int gg_num_threads(void) { return omp_get_max_threads(); }

@@ -9,6 +9,10 @@ parameters and seed.
 CSR layout: undirected with both directions stored, self-loops and duplicate
 entries removed, rows sorted; ``offsets`` int64[n+1], ``indices`` int32[m],
 ``weights`` float32[m] holding small integers, or ``None`` for unit weights.
+
+``rmat_device`` builds the same R-MAT graph in GPU memory
+(``lib/libgvelpa_gen_gpu.so``, ``include/gvelpa_gen.h``): the CSR is
+bit-identical to ``rmat``'s and lands in torch tensors on the device.
 """
 from __future__ import annotations
 
@@ -23,6 +27,7 @@ from . import _build
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_int, ctypes.c_int64)
 _lib = None
+_gpu_lib = None
 
 
 def _load():
@@ -38,6 +43,7 @@ def _load():
         lib.gg_sbm.argtypes = [i64, i64, f64, f64, u64, ctypes.c_int, ctypes.c_int, _ALLOC, p64]
         lib.gg_sbm_batch_params.argtypes = [i32, u64, f64, f64, f64, f64, f64, f64, p64, p64, pf64, pf64]
         lib.gg_sbm_batch.argtypes = [i32, p64, p64, pf64, pf64, u64, ctypes.c_int, _ALLOC, p64, p64, p64]
+        lib.gg_grid.argtypes = [i64, i64, f64, u64, ctypes.c_int, _ALLOC, p64, p64]
         _lib = lib
     return _lib
 
@@ -115,6 +121,21 @@ def sbm(n: int, blocks: int, p_in: float, p_out: float, seed: int = 1, weighted=
     g = CSR(n, arr.get(0), arr.get(1), arr.get(2), name=f"sbm{n}_k{blocks}_s{seed}",
             meta=dict(kind="sbm", blocks=blocks, p_in=p_in, p_out=p_out, seed=seed))
     return g
+
+
+def grid(rows: int, cols: int, p_keep: float = 0.55, seed: int = 1, weighted=False) -> CSR:
+    """Low-degree road-like graph: the 4-neighbour lattice of rows x cols
+    vertices with every lattice edge kept with probability p_keep (average
+    degree about 4 p_keep)."""
+    lib = _load()
+    arr = _Arrays()
+    n = ctypes.c_int64()
+    m = ctypes.c_int64()
+    rc = lib.gg_grid(rows, cols, p_keep, seed, _weighted_code(weighted), arr.cb, ctypes.byref(n), ctypes.byref(m))
+    if rc != 0:
+        raise ValueError(f"gg_grid failed ({rc})")
+    return CSR(n.value, arr.get(0), arr.get(1), arr.get(2), name=f"grid{rows}x{cols}_p{p_keep}_s{seed}",
+               meta=dict(kind="grid", rows=rows, cols=cols, p_keep=p_keep, seed=seed))
 
 
 def sbm_truth(n: int, blocks: int) -> np.ndarray:
@@ -199,8 +220,85 @@ def from_edges(n: int, edges, weights=None, keep_self_loops: bool = False, symme
     return CSR(n, off, e[:, 1].astype(np.int32), None if w is None else w.astype(np.float32))
 
 
+@dataclass
+class DeviceCSR:
+    """CSR graph in device memory (torch tensors); ``weights is None`` means unit weights."""
+    n: int
+    offsets: object
+    indices: object
+    weights: object = None
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return int(self.indices.shape[0])
+
+    def to_host(self) -> CSR:
+        w = None if self.weights is None else self.weights.cpu().numpy()
+        return CSR(self.n, self.offsets.cpu().numpy(), self.indices.cpu().numpy(), w, name=self.name,
+                   meta=dict(self.meta))
+
+
+def _load_gpu():
+    global _gpu_lib
+    if _gpu_lib is None:
+        import torch  # noqa: F401  (binds the library to torch's HIP runtime)
+        if not _build.GEN_GPU_LIB.exists():
+            raise RuntimeError(f"GPU generator not built: {_build.GEN_GPU_LIB} (run __graft_entry__.build())")
+        lib = ctypes.CDLL(str(_build.GEN_GPU_LIB))
+        lib.gvgen_rmat.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, _ALLOC,
+                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        lib.gvgen_rmat.restype = ctypes.c_int
+        lib.gvgen_status_string.argtypes = [ctypes.c_int]
+        lib.gvgen_status_string.restype = ctypes.c_char_p
+        _gpu_lib = lib
+    return _gpu_lib
+
+
+class _DeviceArrays:
+    def __init__(self, device):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.arrays = {}
+        self.cb = _ALLOC(self._alloc)
+
+    def _alloc(self, kind, count):
+        t = self.torch
+        dtype = {0: t.int64, 1: t.int32, 2: t.float32}[kind]
+        a = t.empty(max(int(count), 1), dtype=dtype, device=self.device)
+        self.arrays[kind] = (a, int(count))
+        return a.data_ptr()
+
+    def get(self, kind):
+        if kind not in self.arrays:
+            return None
+        a, c = self.arrays[kind]
+        return a[:c]
+
+
+def rmat_device(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+                seed: int = 1, weighted=True, device: int = 0) -> DeviceCSR:
+    """``rmat`` generated and assembled on GPU ``device`` (same CSR, bit for bit)."""
+    import torch
+    lib = _load_gpu()
+    arr = _DeviceArrays(device)
+    n = ctypes.c_int64()
+    m = ctypes.c_int64()
+    stream = torch.cuda.current_stream(device).cuda_stream
+    rc = lib.gvgen_rmat(scale, edge_factor, a, b, c, seed, _weighted_code(weighted), device, stream, arr.cb,
+                        ctypes.byref(n), ctypes.byref(m))
+    if rc != 0:
+        raise RuntimeError(f"gvgen_rmat failed: {lib.gvgen_status_string(rc).decode()} ({rc})")
+    return DeviceCSR(n.value, arr.get(0), arr.get(1), arr.get(2), name=f"rmat{scale}_ef{edge_factor}_s{seed}",
+                     meta=dict(kind="rmat", scale=scale, edge_factor=edge_factor, a=a, b=b, c=c, seed=seed))
+
+
 def rmat_expected_edges(scale: int, edge_factor: int) -> int:
     return edge_factor << scale
 
 
-__all__ = ["CSR", "rmat", "sbm", "sbm_truth", "sbm_batch", "sbm_batch_params", "from_edges"]
+__all__ = ["CSR", "DeviceCSR", "rmat", "rmat_device", "sbm", "sbm_truth", "sbm_batch", "sbm_batch_params",
+           "grid", "from_edges"]

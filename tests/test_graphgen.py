@@ -71,3 +71,27 @@ def test_thread_count_independent():
         env = dict(os.environ, OMP_NUM_THREADS=t)
         outs.append(subprocess.check_output([sys.executable, "-c", code], env=env, text=True).strip())
     assert outs[0] == outs[1]
+
+
+def test_grid_lattice_structure():
+    """The low-degree lattice: every entry joins lattice neighbours, rows are
+    sorted and symmetric, p_keep = 1 gives the full 4-neighbour lattice, and
+    the average degree is about 4 p_keep; the graph is a function of the seed."""
+    from paper_2312_08140_amd import graphgen as gg
+    full = gg.grid(7, 9, 1.0)
+    assert full.n == 63 and full.m == 2 * (7 * 8 + 6 * 9)
+    for v in range(full.n):
+        r, c = divmod(v, 9)
+        want = sorted(u for u in (v - 9, v - 1, v + 1, v + 9)
+                      if 0 <= u < 63 and (abs(u - v) == 9 or u // 9 == r))
+        assert full.indices[full.offsets[v]:full.offsets[v + 1]].tolist() == want
+    g = gg.grid(300, 400, 0.55, seed=5)
+    assert abs(g.m / g.n - 4 * 0.55 * (1 - 0.5 / 300 - 0.5 / 400)) < 0.02
+    h = gg.grid(300, 400, 0.55, seed=5)
+    assert np.array_equal(g.indices, h.indices) and np.array_equal(g.offsets, h.offsets)
+    lat = set()
+    for v in range(g.n):
+        for u in g.indices[g.offsets[v]:g.offsets[v + 1]]:
+            assert abs(int(u) - v) in (1, 400) and (v, int(u)) not in lat
+            lat.add((v, int(u)))
+    assert all((u, v) in lat for v, u in lat)
