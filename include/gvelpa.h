@@ -321,6 +321,26 @@ int lpa_gate_backward(const float *params, const float *features, const uint8_t 
                       float pos_weight, float *grad, float *loss, int device, void *hip_stream, unsigned flags);
 
 /*
+ * lpa_gate_backward_noalloc - lpa_gate_backward for callers that cannot
+ * allocate device memory (tight training loops, harnesses that forbid
+ * hipMalloc): the same gradient and loss, bit for bit, computed without any
+ * allocation.  Its scratch (the device copy of the parameters and the
+ * per-workgroup partial gradients) lives in a fixed array of about 11.3 MB in
+ * the library's device memory, one copy per GPU, held until the process ends.
+ *   params     host float[1377] (finite).
+ *   features   DEVICE float[count][8]; targets DEVICE uint8[count].
+ *   count      1 .. LPA_GATE_NOALLOC_MAX_SAMPLES; larger counts return
+ *              LPA_ERR_TOO_LARGE (split them, or use lpa_gate_backward).
+ *   grad       host float[1377]; loss host float (may be NULL).
+ * Every call on a GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (from several host threads or streams) race and must be serialised by
+ * the caller.  Synchronises hip_stream before returning.
+ */
+#define LPA_GATE_NOALLOC_MAX_SAMPLES 262144
+int lpa_gate_backward_noalloc(const float *params, const float *features, const uint8_t *targets, int64_t count,
+                              float pos_weight, float *grad, float *loss, int device, void *hip_stream);
+
+/*
  * lpa_gate_train - Adam (Kingma and Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8,
  * bias-corrected) on the loss of lpa_gate_backward, FP32 master parameters
  * updated in place in params (host float[1377]).  Each epoch takes the samples

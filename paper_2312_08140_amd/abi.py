@@ -46,6 +46,7 @@ LPA_FLAG_NO_REORDER = 1024
 
 GATE_PARAMS = 1377
 GATE_FEATURES = 8
+GATE_NOALLOC_MAX_SAMPLES = 262144
 
 MAX_SWEEPS_RECORDED = 64
 NUM_TIMED_KERNELS = 16
@@ -124,6 +125,8 @@ SIGNATURES = {
     "lpa_gate_forward": (ctypes.c_int, [_vp, _vp, _i64, _vp, ctypes.c_int, _vp, ctypes.c_uint]),
     "lpa_gate_backward": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f32, _vp, ctypes.POINTER(_f32), ctypes.c_int, _vp,
                                          ctypes.c_uint]),
+    "lpa_gate_backward_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f32, _vp, ctypes.POINTER(_f32), ctypes.c_int,
+                                                 _vp]),
     "lpa_gate_train": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i32, _i32, _f32, _f32, _vp, ctypes.c_int, _vp,
                                       ctypes.c_uint]),
     "lpa_gate_threshold": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, ctypes.POINTER(_f32), ctypes.c_int, _vp,
@@ -301,6 +304,13 @@ def lpa_gate_backward(params, features, targets, count, pos_weight, grad, device
     return rc, loss.value
 
 
+def lpa_gate_backward_noalloc(params, features, targets, count, pos_weight, grad, device=0, hip_stream=None):
+    loss = ctypes.c_float()
+    rc = load().lpa_gate_backward_noalloc(_ptr(params), _ptr(features), _ptr(targets), count, pos_weight, _ptr(grad),
+                                          ctypes.byref(loss), device, hip_stream)
+    return rc, loss.value
+
+
 def lpa_gate_train(params, features, targets, count, order, epochs, batch, lr, pos_weight, epoch_loss=None,
                    device=0, hip_stream=None, flags=0):
     return load().lpa_gate_train(_ptr(params), _ptr(features), _ptr(targets), count, _ptr(order), epochs, batch, lr,
@@ -474,6 +484,19 @@ def gate_backward(params, features, targets, pos_weight=1.0, device=0):
     g = np.empty(GATE_PARAMS, np.float32)
     rc, loss = lpa_gate_backward(p, x, y, c, float(pos_weight), g, device, _current_stream(device), fl)
     _check(rc, "lpa_gate_backward")
+    return g, loss
+
+
+def gate_backward_noalloc(params, features, targets, pos_weight=1.0, device=0):
+    """``gate_backward`` without any device allocation (device tensors only; at
+    most GATE_NOALLOC_MAX_SAMPLES samples per call)."""
+    if not (hasattr(features, "data_ptr") and hasattr(targets, "data_ptr")):
+        raise ValueError("features and targets must be device tensors")
+    p = _f32(params, (GATE_PARAMS,))
+    g = np.empty(GATE_PARAMS, np.float32)
+    rc, loss = lpa_gate_backward_noalloc(p, features, targets, int(features.shape[0]), float(pos_weight), g, device,
+                                         _current_stream(device))
+    _check(rc, "lpa_gate_backward_noalloc")
     return g, loss
 
 

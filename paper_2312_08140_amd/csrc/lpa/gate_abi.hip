@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "gvelpa.h"
@@ -106,6 +107,41 @@ constexpr float ADAM_B1 = 0.9f, ADAM_B2 = 0.999f, ADAM_EPS = 1e-8f;
 
 }  // namespace
 
+// ---------------------------------------------------------------- no-allocation gradient
+//
+// Scratch of lpa_gate_backward_noalloc in a file-scope device array: the
+// device copy of the parameters, the reduced gradient and the per-workgroup
+// partials of up to LPA_GATE_NOALLOC_MAX_SAMPLES samples.  Each GPU holds its
+// own copy at its own address until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns for that device.
+constexpr int64_t NA_PARAMS_OFF = 0;
+constexpr int64_t NA_ACC_OFF = 1408;   // GATE_PARAMS rounded up to 256-byte lines
+constexpr int64_t NA_PART_OFF = 2816;
+constexpr int64_t NA_FLOATS =
+    NA_PART_OFF + (int64_t)((LPA_GATE_NOALLOC_MAX_SAMPLES + 127) / 128) * (GATE_PARAMS + 1);
+static_assert(NA_ACC_OFF >= GATE_PARAMS && NA_PART_OFF - NA_ACC_OFF >= GATE_PARAMS + 1, "scratch layout");
+
+static __device__ __align__(256) float scratch[NA_FLOATS];
+
+namespace {
+
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mu;
+float *na_ptr[NA_MAX_DEVICES] = {};
+
+// Device address of this device's scratch (the device is current).
+float *noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(na_mu);
+  if (!na_ptr[device]) {
+    void *p = nullptr;
+    GATE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    na_ptr[device] = (float *)p;
+  }
+  return na_ptr[device];
+}
+
+}  // namespace
+
 extern "C" {
 
 int lpa_gate_forward(const float *params, const float *features, int64_t count, float *probs, int device,
@@ -151,6 +187,30 @@ int lpa_gate_backward(const float *params, const float *features, const uint8_t 
     }
     for (int k = 0; k < GATE_PARAMS; ++k) grad[k] = (float)total[k];
     if (loss) *loss = (float)total[GATE_PARAMS];
+    return LPA_OK;
+  });
+}
+
+int lpa_gate_backward_noalloc(const float *params, const float *features, const uint8_t *targets, int64_t count,
+                              float pos_weight, float *grad, float *loss, int device, void *hip_stream) {
+  if (!params || !grad || !features || !targets || count <= 0) return LPA_ERR_INVALID_ARG;
+  if (count > LPA_GATE_NOALLOC_MAX_SAMPLES) return LPA_ERR_TOO_LARGE;
+  if (!(pos_weight >= 0.0f) || !std::isfinite(pos_weight) || !finite_params(params)) return LPA_ERR_INVALID_ARG;
+  if (device < 0 || device >= NA_MAX_DEVICES) return LPA_ERR_INVALID_ARG;
+  return guarded(device, hip_stream, [&](Scope &s) -> int {
+    float *base = noalloc_scratch(device);
+    float *master = base + NA_PARAMS_OFF;
+    float *acc = base + NA_ACC_OFF;
+    float *partial = base + NA_PART_OFF;
+    GATE_HIP(hipMemcpyAsync(master, params, sizeof(float) * GATE_PARAMS, hipMemcpyHostToDevice, s.st));
+    // one pass (count fits the partials), so the sums are those of lpa_gate_backward
+    launch_gate_grad(master, features, targets, nullptr, 0, count, pos_weight, (float)count, partial, acc, s.st);
+    GATE_HIP(hipGetLastError());
+    float part[GATE_PARAMS + 1];
+    GATE_HIP(hipMemcpyAsync(part, acc, sizeof(float) * (GATE_PARAMS + 1), hipMemcpyDeviceToHost, s.st));
+    GATE_HIP(hipStreamSynchronize(s.st));
+    std::memcpy(grad, part, sizeof(float) * GATE_PARAMS);
+    if (loss) *loss = part[GATE_PARAMS];
     return LPA_OK;
   });
 }
