@@ -42,20 +42,29 @@ def library_digest():
 
 
 DEFAULT_BINS = [4, 16, 64, 256, 1024, 4096]  # the library's default degree limits of bins 0-5
+DEFAULT_CONFIG = {"variants": [0] * 6, "schedule": [16, 2, 4], "bins": DEFAULT_BINS, "hubs_last": 0}
 
 
 def profiled_config(workload):
-    """(variants, schedule, bins) the committed byte counters were taken with, when
-    the library sources still match them; else None."""
+    """The configuration (variants, schedule, bins, hubs_last) the committed byte
+    counters were taken with, when the library sources still match them; else None."""
     try:
         for line in (ROOT / "profiles" / f"{workload}_async_hbm_traffic.md").read_text().splitlines():
             if line.startswith("machine-readable: "):
                 d = json.loads(line[len("machine-readable: "):])
                 if d.get("sources") == library_digest():
-                    return d["variants"], d["schedule"], d.get("bins", DEFAULT_BINS)
+                    return {"variants": d["variants"], "schedule": d["schedule"], "bins": d.get("bins", DEFAULT_BINS),
+                            "hubs_last": d.get("hubs_last", 0)}
     except OSError:
         pass
     return None
+
+
+CONFIG_KEYS = ("variants", "schedule", "bins", "hubs_last")
+
+
+def same_config(a, b):
+    return all(a.get(k, DEFAULT_CONFIG[k]) == b.get(k, DEFAULT_CONFIG[k]) for k in CONFIG_KEYS)
 
 
 def measured_traffic(kernel, tuned, workload):
@@ -67,8 +76,7 @@ def measured_traffic(kernel, tuned, workload):
                 d = json.loads(line[len("machine-readable: "):])
                 if d.get("sources") != library_digest():
                     return None
-                if tuned is None or d.get("variants") != tuned["variants"] or d.get("schedule") != tuned["schedule"] \
-                        or d.get("bins", DEFAULT_BINS) != tuned["bins"]:
+                if tuned is None or not same_config(d, tuned):
                     return None
                 return d["bytes_per_launch"].get(kernel)
     except OSError:
@@ -115,7 +123,10 @@ def _median_runs(G, tau, max_iters, flags, out, k):
 
 
 def _compare(G, gate_info, tau, max_iters, out, truth=None, plain=None):
-    """Plain vs gated time-to-converge (median of 5 runs each) on one handle."""
+    """Plain vs gated time-to-converge (median of 5 runs each) on one handle.
+    A gated run ends with its verification sweep; the plain run is reported
+    as is and also with that verification sweep (a verified fixed point,
+    which the asynchronous mode must reach as well)."""
     import torch
     from paper_2312_08140_amd import abi
     if plain is None:
@@ -124,18 +135,22 @@ def _compare(G, gate_info, tau, max_iters, out, truth=None, plain=None):
         qp = G.modularity(lp)
     else:
         p_ms, sp, lp, qp = plain
+    pv_ms, spv = _median_runs(G, tau, max_iters, abi.LPA_FLAG_VERIFY, out, 5)
     G.gate_load(gate_info["params"], gate_info["threshold"])
     g_ms, sg = _median_runs(G, tau, max_iters, abi.LPA_FLAG_GATE, out, 5)
     lg = out.clone()
     qg = G.modularity(lg)
-    r = {"plain_ms": round(p_ms, 3), "gated_ms": round(g_ms, 3), "speedup": round(p_ms / g_ms, 3),
+    r = {"plain_ms": round(p_ms, 3), "plain_verified_ms": round(pv_ms, 3), "gated_ms": round(g_ms, 3),
+         "speedup": round(p_ms / g_ms, 3), "speedup_vs_verified_plain": round(pv_ms / g_ms, 3),
          "q_plain": round(qp, 6), "q_gated": round(qg, 6), "q_loss": round(qp - qg, 6),
          "nmi_plain_vs_gated": round(abi.nmi(lp, lg), 6), "verified": bool(sg["verified"]),
+         "plain_verified": bool(spv["verified"]),
          "sweeps_plain": sp["iterations"], "sweeps_gated": sg["iterations"],
          "processed_plain": int(sum(sp["frontier"])),
          "processed_gated": int(sum(sg["frontier"])), "gated_out": int(sum(sg["gated_out"])),
          "verify_changed": int(sg["verify_changed"]),
          "entries_plain": int(sum(sp["edges_scanned"])),
+         "entries_plain_verified": int(sum(spv["edges_scanned"]) + spv["verify_edges_scanned"]),
          "entries_gated": int(sum(sg["edges_scanned"]) + sg["verify_edges_scanned"])}
     if truth is not None:
         t = torch.from_numpy(truth.astype(np.int32)).cuda()
@@ -144,51 +159,93 @@ def _compare(G, gate_info, tau, max_iters, out, truth=None, plain=None):
     return r
 
 
-def gate_comparison(args, G, g, runs, q_async, out, tuned=None):
-    """Learned active-set gate vs plain pruning: SBM-1M (gate trained on traces
-    of other SBM-1M graphs) and the R-MAT graph of the headline (gate trained
-    on traces of smaller R-MAT graphs).  Training is outside every timed run."""
+def _traces(graphs, cfg, probability, tau, max_iters):
+    """(features, targets) of traced plain runs, every handle configured like
+    the ones the gate serves (the schedule shapes the label dynamics)."""
+    from paper_2312_08140_amd import abi
+    xs, ys = [], []
+    for make in graphs:
+        g = make()
+        if hasattr(g.offsets, "data_ptr"):
+            H = abi.LPAGraph(n=g.n, offsets=g.offsets, indices=g.indices, weights=g.weights)
+        else:
+            H = abi.LPAGraph(g)
+        if cfg == "tune":
+            H.autotune(tau, max_iters, abi.LPA_MODE_ASYNC)
+        elif cfg is not None:
+            _apply(H, cfg)
+        H.set_trace(1 << 24, probability)
+        H.run(tau, max_iters, abi.LPA_MODE_ASYNC, True, flags=abi.LPA_FLAG_TRACE)
+        x, y = H.gate_trace()
+        H.close()
+        del g
+        xs.append(x)
+        ys.append(y)
+    return np.concatenate(xs), np.concatenate(ys)
+
+
+def gate_comparison(args, G, runs, out, tuned, sec=None):
+    """Learned active-set gate vs plain pruning.  The gate is trained on traces
+    of 64 seeded plain runs - 32 SBM-1M graphs (seeds 100-131, mixing cycling
+    0.1-0.4) for the SBM network and 32 R-MAT scale-24 graphs (seeds 100-131)
+    for the R-MAT network - disjoint from the evaluation graphs; it is then
+    compared with plain runs on SBM-1M (seed 1, mixing 0.1-0.4), on R-MAT-24
+    (seed 1) and on the headline graph.  Training is outside every timed run."""
     import torch
     from paper_2312_08140_amd import abi, gate, graphgen
     res = {}
+    # every SBM handle is tuned on its own graph (the quality guard of the
+    # autotuner then holds per mixing level), training handles included
+    sbm_cfg = None if args.no_tune else "tune"
     t = time.time()
-    # traces from handles tuned like the ones the gate serves: the schedule
-    # shapes the label dynamics the features have to predict
-    sched = None if args.no_tune else "tuned"
-    train = [_sbm1m(mu, 100 + i) for i, mu in enumerate((0.1, 0.2, 0.3, 0.4) * 2)]
-    X, y = gate.collect(train, probability=0.25, schedule=sched)
-    del train
+    X, y = _traces([lambda i=i, mu=mu: _sbm1m(mu, 100 + i) for i, mu in enumerate((0.1, 0.2, 0.3, 0.4) * 8)],
+                   sbm_cfg, 0.1, args.tau, args.max_iters)
+    t_tr = time.time() - t
     info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
-    res["sbm_gate"] = {"train_graphs": 8, "trace_schedule": sched or "default", "samples": int(len(y)), "positive_share": round(float(y.mean()), 4),
-                       "threshold": round(info["threshold"], 6), "holdout_recall": round(info["holdout_recall"], 4),
+    res["sbm_gate"] = {"train_runs": 32, "trace_config": "each handle autotuned" if sbm_cfg else "default",
+                       "samples": int(len(y)),
+                       "positive_share": round(float(y.mean()), 4), "threshold": round(info["threshold"], 6),
+                       "holdout_recall": round(info["holdout_recall"], 4),
                        "holdout_skip": round(info["holdout_skip"], 4),
-                       "loss": [round(float(v), 5) for v in info["losses"]], "seconds": round(time.time() - t, 2)}
+                       "loss": [round(float(v), 5) for v in info["losses"]], "trace_seconds": round(t_tr, 2),
+                       "seconds": round(time.time() - t, 2)}
     log(f"sbm gate: {res['sbm_gate']}")
     rows = []
     for mu in (0.1, 0.2, 0.3, 0.4):
         s = _sbm1m(mu, 1)
         H = abi.LPAGraph(s)
         o = torch.empty(s.n, dtype=torch.int32, device="cuda:0")
-        if not args.no_tune:
+        if sbm_cfg is not None:
             H.autotune(args.tau, args.max_iters, abi.LPA_MODE_ASYNC)
         r = _compare(H, info, args.tau, args.max_iters, o, truth=graphgen.sbm_truth(s.n, 1000))
         r["mu"] = mu
+        r["schedule"] = list(H.schedule())
         rows.append(r)
         log(f"sbm1m mu={mu}: {r}")
         H.close()
     res["sbm1m"] = rows
     t = time.time()
-    train = [graphgen.rmat(20, args.edge_factor, seed=100 + i, weighted=True) for i in range(4)]
-    rsched = sched if tuned is None else tuned["schedule"]
-    rbins = None if tuned is None else tuned["bins"]
-    X, y = gate.collect(train, probability=0.25, schedule=rsched, bins=rbins)
-    del train
+    X, y = _traces([lambda i=i: graphgen.rmat_device(24, 16, seed=100 + i, weighted=True) for i in range(32)],
+                   sec["tuning"] if sec else tuned, 0.05, args.tau, args.max_iters)
+    t_tr = time.time() - t
     info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
-    res["rmat_gate"] = {"train_graphs": "R-MAT scale 20, seeds 100-103", "trace_schedule": rsched or "default",
-                        "trace_bins": rbins or "default",
-                        "samples": int(len(y)),
-                        "threshold": round(info["threshold"], 6), "holdout_recall": round(info["holdout_recall"], 4),
-                        "holdout_skip": round(info["holdout_skip"], 4), "seconds": round(time.time() - t, 2)}
+    res["rmat_gate"] = {"train_runs": "32 R-MAT scale 24 edge factor 16, seeds 100-131",
+                        "trace_config": sec["tuning"] if sec else tuned, "samples": int(len(y)),
+                        "positive_share": round(float(y.mean()), 4), "threshold": round(info["threshold"], 6),
+                        "holdout_recall": round(info["holdout_recall"], 4),
+                        "holdout_skip": round(info["holdout_skip"], 4), "trace_seconds": round(t_tr, 2),
+                        "seconds": round(time.time() - t, 2)}
+    log(f"rmat gate: {res['rmat_gate']}")
+    if sec is not None:
+        d = graphgen.rmat_device(args.secondary_scale, args.secondary_edge_factor, seed=args.seed, weighted=True)
+        H = abi.LPAGraph(n=d.n, offsets=d.offsets, indices=d.indices, weights=d.weights)
+        _apply(H, sec["tuning"])
+        o = torch.empty(d.n, dtype=torch.int32, device="cuda:0")
+        r = _compare(H, info, args.tau, args.max_iters, o)
+        res[f"rmat{args.secondary_scale}"] = r
+        log(f"rmat{args.secondary_scale} gated: {r}")
+        H.close()
+        del d
     p_ms = float(np.median([r["total_ms"] for r in runs]))
     lp = out.clone()
     G.run(args.tau, args.max_iters, abi.LPA_MODE_ASYNC, True, labels_out=lp)
@@ -254,6 +311,7 @@ def _apply(G, cfg):
     G.set_variants(cfg["variants"])
     G.set_async_schedule(*cfg["schedule"])
     G.set_bins(cfg["bins"])
+    G.set_bin_order(cfg.get("hubs_last", 0))
 
 
 def tune_async(args, G, workload):
@@ -262,11 +320,12 @@ def tune_async(args, G, workload):
     configuration the committed byte counters of this workload were taken
     with, that one is timed instead so the counters apply."""
     from paper_2312_08140_amd import abi
-    if args.variants or args.schedule or args.bins:
+    if args.variants or args.schedule or args.bins or args.hubs_last:
         v = [int(x) for x in args.variants.split(",")] if args.variants else [0] * 6
         s = [int(x) for x in args.schedule.split(",")] if args.schedule else [16, 2, 4]
         lim = [int(x) for x in args.bins.split(",")] if args.bins else list(DEFAULT_BINS)
-        tuned = {"variants": v, "schedule": s, "bins": lim, "seconds": 0.0, "given": True}
+        tuned = {"variants": v, "schedule": s, "bins": lim, "hubs_last": int(args.hubs_last), "seconds": 0.0,
+                 "given": True}
         _apply(G, tuned)
         return tuned
     if args.no_tune:
@@ -274,11 +333,11 @@ def tune_async(args, G, workload):
     t = time.time()
     variants, bin_ms, sched, lim = G.autotune(args.tau, args.max_iters, abi.LPA_MODE_ASYNC)
     tuned = {"variants": [int(v) for v in variants], "schedule": list(sched), "bins": list(lim),
-             "seconds": round(time.time() - t, 2), "source": "autotune"}
+             "hubs_last": G.schedule()[4], "seconds": round(time.time() - t, 2), "source": "autotune"}
     prof = profiled_config(workload)
-    if prof is not None and (prof[0] != tuned["variants"] or prof[1] != tuned["schedule"] or prof[2] != tuned["bins"]):
-        tuned["autotune_pick"] = {"variants": tuned["variants"], "schedule": tuned["schedule"], "bins": tuned["bins"]}
-        tuned.update(variants=prof[0], schedule=prof[1], bins=prof[2], source="autotune pick recorded with the profile")
+    if prof is not None and not same_config(prof, tuned):
+        tuned["autotune_pick"] = {k: tuned[k] for k in CONFIG_KEYS}
+        tuned.update(prof, source="autotune pick recorded with the profile")
         _apply(G, tuned)
     return tuned
 
@@ -313,6 +372,38 @@ def roofline_of(G, args, out, tuned, workload):
                             "achieved": round(total_bytes / (sweep_ms * 1e-3) / 1e9, 1),
                             "frac": round(total_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "per_kernel": per_kernel}
+
+
+def gather_ceiling(d, reps=3):
+    """What a label gather alone costs on this graph: torch's index_select of a
+    label array by the stored neighbour indices (4 B index read, 4 B label
+    gather, 4 B output write per entry), in the CSR order of the generator and
+    with the same indices sorted (every gather then walks the label array in
+    order).  A ceiling for any kernel that gathers one label per entry."""
+    import torch
+    C = torch.arange(d.n, dtype=torch.int32, device="cuda:0")
+    res = {}
+
+    def timed(idx):
+        out = torch.index_select(C, 0, idx)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            torch.index_select(C, 0, idx, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        del out
+        ms = e0.elapsed_time(e1) / reps
+        return {"ms": round(ms, 3), "entries_per_s": round(d.m / (ms * 1e-3), 1),
+                "gb_per_s_12B_per_entry": round(12 * d.m / (ms * 1e-3) / 1e9, 1)}
+    res["csr_order"] = timed(d.indices)
+    if d.m <= (1 << 30):
+        srt = torch.sort(d.indices)[0]
+        res["sorted_indices"] = timed(srt)
+        del srt
+    torch.cuda.empty_cache()
+    return res
 
 
 def deterministic_of(G, args, out, m, tuned):
@@ -365,7 +456,7 @@ def secondary_rmat(args):
     wl = f"rmat{args.secondary_scale}"
     res = {"workload": f"rmat{args.secondary_scale}_ef{args.secondary_edge_factor}_w1-8_seed{args.seed}", "n": d.n,
            "m": d.m, "generate_and_create_s": round(time.time() - t, 2)}
-    sub = argparse.Namespace(**{**vars(args), "variants": None, "schedule": None, "bins": None})
+    sub = argparse.Namespace(**{**vars(args), "variants": None, "schedule": None, "bins": None, "hubs_last": 0})
     tuned = tune_async(sub, G, wl)
     out = torch.empty(d.n, dtype=torch.int32, device="cuda:0")
     runs, wall = timed_async(G, args, out, 10, 2)
@@ -377,6 +468,7 @@ def secondary_rmat(args):
     res["verified"] = bool(sv["verified"])
     res["verify_changed"] = int(sv["verify_changed"])
     res["roofline"] = roofline_of(G, args, out, tuned, wl)
+    res["roofline"]["gather_ceiling"] = gather_ceiling(d)
     if not args.no_det:
         res["deterministic"], q_det = deterministic_of(G, args, out, d.m, tuned)
         res["q_async_minus_det"] = round(res["modularity"] - q_det, 6)
@@ -398,18 +490,26 @@ def cpu_model():
 
 def cpu_baselines(args, head_host, sec_host, batch_in):
     """The sequential C oracle (one core; it is sequential by definition) on
-    bounded samples: sweep 0 of the headline graph, the mid-size R-MAT to
-    convergence in id order and in (colour, id) order, and the 4,096-graph
-    batch to convergence spread over every host core (one graph per thread)."""
+    bounded samples: sweep 0 of the headline graph over a seeded quarter of
+    its vertices (the others start unflagged, so the oracle skips them), the
+    mid-size R-MAT to convergence in id order and in (colour, id) order, and
+    the 4,096-graph batch to convergence spread over every host core (one
+    graph per thread).  Then the multicore comparator in the paper's design
+    (OpenMP, every host core) to convergence on both R-MAT graphs, strict and
+    non-strict."""
     import oracle
+    from paper_2312_08140_amd import cpu_lpa
     res = {"cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
     if head_host is not None:
+        fl = (np.random.default_rng(12345).random(head_host.n) < 0.25).astype(np.uint8)
         t = time.perf_counter()
-        r = oracle.lpa(head_host, tau=args.tau, max_iters=1, prune=True)
+        r = oracle.lpa(head_host, tau=args.tau, max_iters=1, prune=True, init_flags=fl)
         dt = time.perf_counter() - t
         res["headline_sweep0"] = {"value": round(float(r["scanned"].sum()) / dt, 1), "unit": "edges/s", "cores": 1,
                                   "seconds": round(dt, 2), "entries": int(r["scanned"].sum()),
-                                  "sample": "sweep 0 (every vertex) of the headline graph, id order"}
+                                  "vertices": int(r["processed"].sum()),
+                                  "sample": "sweep 0 of the headline graph in id order over a seeded random quarter "
+                                            "of the vertices (the rest start unflagged)"}
         log(f"cpu oracle headline sweep 0: {res['headline_sweep0']}")
     if sec_host is not None:
         rows = {}
@@ -443,6 +543,20 @@ def cpu_baselines(args, head_host, sec_host, batch_in):
                                        "edges_per_s": round(ent / dt, 1), "m_over_time": round(g.m / dt, 1),
                                        "sample": f"{len(vptr) - 1} graphs, id order, one graph per thread"}
         log(f"cpu oracle batch: {res['batch_to_convergence']}")
+    comp = {}
+    for name, g in (("headline", head_host), ("secondary", sec_host)):
+        if g is None:
+            continue
+        for strict in (True, False):
+            r = cpu_lpa.lpa(g, tau=args.tau, max_iters=args.max_iters, prune=True, strict=strict, threads=0)
+            ent = int(r["scanned"].sum())
+            comp[f"{name}_{'strict' if strict else 'non_strict'}"] = {
+                "seconds": round(r["seconds"], 3), "threads": r["threads"], "sweeps": r["iterations"],
+                "converged": r["converged"], "entries": ent, "edges_per_s": round(ent / r["seconds"], 1),
+                "m_over_time_to_converge": round(g.m / r["seconds"], 1),
+                "modularity": round(oracle.modularity(g, r["labels"]), 6)}
+            log(f"cpu comparator {name} strict={strict}: {comp[f'{name}_' + ('strict' if strict else 'non_strict')]}")
+    res["multicore_comparator"] = comp
     return res
 
 
@@ -469,6 +583,7 @@ def main():
                     help="degree limits of bins 0-5, e.g. 4,16,64,256,1024,4096 (instead of autotuning)")
     ap.add_argument("--schedule", default=None,
                     help="asynchronous schedule early_steps,early_sweeps,late_steps (instead of autotuning)")
+    ap.add_argument("--hubs-last", type=int, default=0, help="with the options above: the hub bin runs last (1)")
     ap.add_argument("--no-gate", action="store_true", help="skip the plain-vs-gated comparison")
     ap.add_argument("--batch", type=int, default=4096,
                     help="batched workload of this many uneven SBMs (4096 = the benchmark batch; 0: skip)")
@@ -517,19 +632,21 @@ def main():
               "modularity": round(G.modularity(out), 6)}
     roofline = roofline_of(G, args, out, tuned, workload)
     log(f"dominant kernel {roofline['kernel']}: {roofline['achieved']:.0f} GB/s ({roofline['frac'] * 100:.1f}% of peak)")
+    roofline["gather_ceiling"] = gather_ceiling(d)
+    log(f"gather ceiling: {roofline['gather_ceiling']}")
 
     det, q_det = (None, None)
     if not args.no_det:
         det, q_det = deterministic_of(G, args, out, d.m, tuned)
         log(f"det: {det}")
 
-    gated = None
-    if not args.no_gate:
-        gated = gate_comparison(args, G, d, runs, q_async, out, tuned)
-
     secondary, sec_dev = None, None
     if args.secondary_scale:
         secondary, sec_dev, _ = secondary_rmat(args)
+
+    gated = None
+    if not args.no_gate:
+        gated = gate_comparison(args, G, runs, out, tuned, secondary)
 
     batch, batch_in = None, None
     if args.batch:
@@ -549,8 +666,8 @@ def main():
         extra = cpu_baselines(args, head_host, sec_host, batch_in)
         hs = extra.get("headline_sweep0")
         cpu = {"value": hs["value"] if hs else None, "unit": "edges/s", "cores": 1, "kind": "oracle",
-               "sample": "sequential C oracle (one thread), sweep 0 of the headline graph in id order "
-                         "(every vertex flagged; all stored entries scanned once)", **extra}
+               "sample": "sequential C oracle (one thread), sweep 0 of the headline graph in id order over a "
+                         "seeded random quarter of its vertices", **extra}
 
     res = {
         "metric": "LPA edges/s per sweep + time-to-converge at equal modularity, plain vs gated",

@@ -67,16 +67,23 @@ enum {
   LPA_FLAG_EXACT_MARKS = 128,   /* lpa_run, async mode: always flag neighbours one by one.  By default a sweep
                                    that follows one in which more than half of the vertices changed writes no
                                    marks and flags every vertex at its end instead (the first sweep of a fresh
-                                   run counts as such); this only adds work that cannot change a label */
+                                   run counts as such); this only adds work that cannot change a label.  Gated
+                                   runs (LPA_FLAG_GATE) write exact marks after their first sweep, so that their
+                                   verification sweep processes only what is flagged */
   LPA_FLAG_ONE_LAUNCH = 256,    /* lpa_run: replay all max_iters sweeps as one HIP graph launch (sweeps after
                                    the stop test exit at once); batched handles always do */
   LPA_FLAG_VERIFY_FULL = 512,   /* lpa_run: the verification sweep processes every vertex (same result as the
                                    default, at the cost of a whole sweep) */
-  LPA_FLAG_NO_REORDER = 1024    /* lpa_create, lpa_batch_create: keep vertices in id order inside the library.
+  LPA_FLAG_NO_REORDER = 1024,   /* lpa_create, lpa_batch_create: keep vertices in id order inside the library.
                                    By default they are stored in decreasing degree order (within each graph of
                                    a batch) so that frequently gathered labels share cache lines; labels keep
                                    their values and every array crosses the boundary in id order, so results
                                    are the same */
+  LPA_FLAG_NONSTRICT = 2048     /* lpa_run: non-strict LPA (Section 4.1.5): among the labels of largest summed
+                                   weight, vertex v takes the one of smallest rank ((c + 1) * M_v) mod P instead
+                                   of the smallest id, P = 2^31 - 1 and M_v = 1580030173^(1 + (v mod 64)) mod P
+                                   (the paper picks one of them by a modulo operation on the label id; this is
+                                   the reading taken) */
 };
 
 #define LPA_MAX_SWEEPS_RECORDED 64
@@ -189,7 +196,9 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
  * step: every flagged vertex at once) it installs the fastest whose runs
  * converge (a batch: every graph) and whose modularity stays within 0.002 of
  * the first's; the first stays when no other qualifies (schedule_out: int32[3],
- * may be NULL).  Then the degree limits of the bins (lpa_set_bins): each
+ * may be NULL); then, on a graph with hubs, whether the hub bin runs last in
+ * each step (lpa_set_bin_order; read it back with lpa_get_schedule).  Then the
+ * degree limits of the bins (lpa_set_bins): each
  * bin's LDS table has a fixed size (8, 32, 128, 512, 2048, 8192 slots), and
  * the candidates let it fill to at most 1/2 (the default), 1/4, 3/4 or all of
  * them; the fastest is installed and returned in bins_out (int32[6], may be
@@ -226,6 +235,33 @@ int lpa_set_async_schedule(lpa_graph *g, int32_t early_phases, int32_t early_swe
 
 /* lpa_set_async_phases - the same number of steps in every sweep. */
 int lpa_set_async_phases(lpa_graph *g, int32_t phases, int32_t by_colour);
+
+/*
+ * lpa_set_bin_order - order of the degree bins inside a step: 0 (the
+ * default) runs the hub bin first and then the lower bins from the largest
+ * degree down; 1 runs the lower bins first and the hubs last, so that the
+ * hubs see the labels the other vertices of the step have just written.  In
+ * the asynchronous mode this changes which labels a step sees (any order is
+ * a valid run); deterministic results do not depend on it (the vertices of a
+ * colour class are never adjacent).  Takes effect for the next lpa_run.
+ */
+int lpa_set_bin_order(lpa_graph *g, int32_t hubs_last);
+
+/*
+ * lpa_set_bins - degree limits of bins 0..5 (count must be 6, non-decreasing,
+ * each below its bin's table size 8, 32, 128, 512, 2048, 8192; NULL restores
+ * 4, 16, 64, 256, 1024, 4096); rows above the last limit take the hub path.
+ * Results do not depend on them (the deterministic mode stays label-for-label
+ * equal); takes effect for the next lpa_run.
+ */
+int lpa_set_bins(lpa_graph *g, const int32_t *max_degree, int32_t count);
+
+/*
+ * lpa_get_schedule - the handle's current asynchronous configuration, as
+ * lpa_autotune leaves it: out int32[5] = early steps, early sweeps, late
+ * steps, steps by colour (1) or by hash (0), hubs last (1) or first (0).
+ */
+int lpa_get_schedule(const lpa_graph *g, int32_t *out);
 
 /*
  * lpa_color - colouring used by the deterministic mode (computed on first use):

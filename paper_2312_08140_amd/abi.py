@@ -43,6 +43,7 @@ LPA_FLAG_EXACT_MARKS = 128
 LPA_FLAG_ONE_LAUNCH = 256
 LPA_FLAG_VERIFY_FULL = 512
 LPA_FLAG_NO_REORDER = 1024
+LPA_FLAG_NONSTRICT = 2048
 
 GATE_PARAMS = 1377
 GATE_FEATURES = 8
@@ -116,6 +117,8 @@ SIGNATURES = {
     "lpa_set_async_phases": (ctypes.c_int, [_vp, _i32, _i32]),
     "lpa_set_async_schedule": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32]),
     "lpa_set_variants": (ctypes.c_int, [_vp, _vp, _i32]),
+    "lpa_set_bin_order": (ctypes.c_int, [_vp, _i32]),
+    "lpa_get_schedule": (ctypes.c_int, [_vp, _vp]),
     "lpa_autotune": (ctypes.c_int, [_vp, _f64, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "lpa_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_uint]),
     "lpa_batch_stats": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -229,6 +232,14 @@ def lpa_set_async_phases(handle, phases, by_colour=0):
 
 def lpa_set_async_schedule(handle, early_phases, early_sweeps, late_phases, by_colour=1):
     return load().lpa_set_async_schedule(handle, early_phases, early_sweeps, late_phases, int(by_colour))
+
+
+def lpa_set_bin_order(handle, hubs_last):
+    return load().lpa_set_bin_order(handle, int(hubs_last))
+
+
+def lpa_get_schedule(handle, out):
+    return load().lpa_get_schedule(handle, _ptr(out))
 
 
 def lpa_set_variants(handle, variant=None):
@@ -419,6 +430,15 @@ class LPAGraph:
 
     def set_variants(self, variant=None):
         _check(lpa_set_variants(self.handle, variant), "lpa_set_variants")
+
+    def set_bin_order(self, hubs_last):
+        _check(lpa_set_bin_order(self.handle, hubs_last), "lpa_set_bin_order")
+
+    def schedule(self):
+        """(early steps, early sweeps, late steps, by colour, hubs last) of the handle."""
+        out = np.zeros(5, np.int32)
+        _check(lpa_get_schedule(self.handle, out), "lpa_get_schedule")
+        return tuple(int(x) for x in out)
 
     def autotune(self, tolerance=0.05, max_iters=20, mode=LPA_MODE_ASYNC):
         """Returns (variant per bin, ms per run of each chosen bin kernel, schedule, bin degree limits)."""

@@ -43,12 +43,15 @@ constexpr BinShape BIN_SHAPES[NBINS - 1][NVARIANTS] = {
 // partition in an LDS table of HUB_PART_SLOTS.  Partitions are sized for at
 // most HUB_PART_TARGET distinct labels; a partition that fills up spills into
 // a shared overflow area, so results never depend on the label distribution.
+// Hubs with more than 2^HUB_LDS_PBITS partitions reserve their slots with one
+// global atomic per merged label instead of an LDS histogram per chunk.
 constexpr int HUB_CHUNK = 2048;
 constexpr int HUB_CHUNK_SLOTS = 4096;
 constexpr int HUB_PART_TARGET = 1024;
 constexpr int HUB_PART_CAP = 1536;
 constexpr int HUB_PART_SLOTS = 2048;
-constexpr int HUB_MAX_PBITS = 12;
+constexpr int HUB_MAX_PBITS = 21;  // partitions for hubs of up to 2^31 entries
+constexpr int HUB_LDS_PBITS = 12;  // up to here the chunk kernel counts its partitions in LDS
 constexpr int64_t HUB_OVERFLOW_CAP = 1 << 22;  // shared spill area for over-full partitions
 
 // Runtime degree limits of bins 0..NBINS-2 (the hub bin takes the rest).
@@ -67,13 +70,65 @@ __host__ __device__ __forceinline__ int bin_of_degree(int64_t deg, const BinLimi
 // the label.  An empty slot holds label 0xFFFFFFFF (labels are < 2^31).
 constexpr u64 EMPTY = 0xFFFFFFFF00000000ull;
 
-// Argmax key: weight in the high word, ~label in the low word, so the
-// largest key is the heaviest label and, among equals, the smallest id.
-// 0 means "no candidate" (~label >= 2^31 for every valid label).
-__device__ __forceinline__ u64 entry_key(u64 slot) {
-  return (slot << 32) | (u64)(~(uint32_t)(slot >> 32));
+// Tie rule among the heaviest labels of a vertex.  Strict LPA (Section 2,
+// Section 4.1.5) takes the smallest label id.  Non-strict LPA (Section 4.1.5:
+// a pick by a modulo operation on the label id) takes the label of smallest
+// rank r(c) = ((c + 1) * M) mod P, P = 2^31 - 1 prime, M = A^(1 + (id mod 64))
+// mod P for the vertex's id, A = 1580030173: distinct labels get distinct
+// ranks, and the pick changes with the vertex like a random one.  Ranks are
+// turned back into labels with the inverse multiplier (A^-1 = 1989098352).
+constexpr uint32_t TIE_P = 2147483647u;
+constexpr uint32_t TIE_A = 1580030173u;
+constexpr uint32_t TIE_A_INV = 1989098352u;
+
+struct TieTables {
+  uint32_t mult[64], inv[64];
+};
+constexpr TieTables make_tie_tables() {
+  TieTables t{};
+  u64 m = 1, i = 1;
+  for (int k = 0; k < 64; ++k) {
+    m = m * TIE_A % TIE_P;
+    i = i * TIE_A_INV % TIE_P;
+    t.mult[k] = (uint32_t)m;
+    t.inv[k] = (uint32_t)i;
+  }
+  return t;
 }
-__device__ __forceinline__ uint32_t key_label(u64 key) { return ~(uint32_t)key; }
+static_assert((u64)TIE_A * TIE_A_INV % TIE_P == 1, "inverse multiplier");
+
+// a * b mod 2^31 - 1 for a, b < 2^31 (Mersenne reduction)
+__device__ __forceinline__ uint32_t mulmod_p(uint32_t a, uint32_t b) {
+  u64 x = (u64)a * b;
+  x = (x & TIE_P) + (x >> 31);
+  x = (x & TIE_P) + (x >> 31);
+  return (uint32_t)(x >= TIE_P ? x - TIE_P : x);
+}
+
+// mult = 0: strict rule
+struct TieRule {
+  uint32_t mult, inv;
+};
+
+__device__ __forceinline__ uint32_t tie_rank(uint32_t lbl, TieRule t) {
+  if (!t.mult) return lbl;
+  const uint32_t c1 = lbl + 1u;  // in [1, 2^31 - 1]
+  return mulmod_p(c1 >= TIE_P ? c1 - TIE_P : c1, t.mult);
+}
+__device__ __forceinline__ uint32_t rank_label(uint32_t r, TieRule t) {
+  if (!t.mult) return r;
+  const uint32_t c1 = mulmod_p(r, t.inv);
+  return (c1 == 0 ? TIE_P : c1) - 1u;
+}
+
+// Argmax key: weight in the high word, ~rank in the low word, so the
+// largest key is the heaviest label and, among equals, the smallest id
+// (strict) or rank (non-strict).  0 means "no candidate" (~rank >= 2^31 for
+// every valid rank).
+__device__ __forceinline__ u64 entry_key(u64 slot, TieRule t) {
+  return (slot << 32) | (u64)(~tie_rank((uint32_t)(slot >> 32), t));
+}
+__device__ __forceinline__ uint32_t key_label(u64 key, TieRule t) { return rank_label(~(uint32_t)key, t); }
 
 // Fibonacci hashing of a label into 2^bits slots.
 __device__ __forceinline__ uint32_t slot_hash(uint32_t label, int bits) {
@@ -207,7 +262,17 @@ struct ScanArgs {
   int bin;
   uint8_t *chg;  // batched runs: set to 1 for every vertex that changes (per-graph dN)
   FeatArgs f;    // gate features and traces (kernels built with FEAT)
+  int nonstrict;        // 1: non-strict tie rule (tie_rank)
+  const int32_t *orig;  // vertex id at each storage position (NULL: positions are ids)
 };
+
+// Tie rule of the vertex at storage position v.
+static __device__ __constant__ TieTables c_tie = make_tie_tables();
+__device__ __forceinline__ TieRule tie_rule_of(const ScanArgs &a, int v) {
+  if (!a.nonstrict || v < 0) return TieRule{0u, 0u};
+  const uint32_t k = (uint32_t)(a.orig ? a.orig[v] : v) & 63u;
+  return TieRule{c_tie.mult[k], c_tie.inv[k]};
+}
 
 // Hub metadata (per hub, sorted by id) and per-step scratch.
 struct HubArgs {

@@ -86,6 +86,7 @@ struct lpa_graph {
   } sched[3];  // early, late, verification (one step: it changes few labels)
   int early_sweeps = 2;
   bool async_by_colour = true;      // steps made of consecutive colour classes (else a hash of the id)
+  bool hubs_last = false;           // a step runs the hub bin after the others (else first)
   // deterministic schedule
   int32_t *color = nullptr;
   int32_t ncol = 0;
@@ -129,6 +130,7 @@ struct lpa_graph {
   // (mode, prune, sweeps per launch, features, schedule)
   std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
   // learned gate
+  bool nonstrict = false;         // the sweeps being emitted use the non-strict tie rule
   bool feat_on = false;           // the sweeps being emitted write gate features
   FeatArgs cur_feat{};
   float *gate_f = nullptr;        // parameters rounded to bf16, held as fp32
@@ -619,6 +621,8 @@ ScanArgs base_args(lpa_graph *g, int prune) {
   a.F = g->F;
   a.ctl = g->ctl;
   a.prune = prune;
+  a.nonstrict = g->nonstrict ? 1 : 0;
+  a.orig = g->orig;
   return a;
 }
 
@@ -646,7 +650,9 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
   launch_compact(ca, grid_cap(len, 2048, 4096), st);
   tk_end(g, st, TK_COMPACT);
   const int max_blocks = g->cu_count * 8;
-  for (int b = NBINS - 1; b >= 0; --b) {
+  for (int k = 0; k < NBINS; ++k) {
+    // bins from the hubs down to degree 1, or (hubs_last) the hubs after the others
+    const int b = !g->hubs_last ? NBINS - 1 - k : (k < NBINS - 1 ? NBINS - 2 - k : HUB_BIN);
     const int64_t seg = bounds[b + 1] - bounds[b];
     if (seg <= 0) continue;
     ScanArgs a = base_args(g, prune);
@@ -713,7 +719,7 @@ hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps, int fi
                    : verify                       ? 2
                    : sweeps == 1                  ? (first >= g->early_sweeps ? 1 : 0)
                                                   : 3 + std::min(first, g->early_sweeps);
-  auto key = std::make_tuple(mode, prune, sweeps, fcode, fkey);
+  auto key = std::make_tuple(mode, prune, sweeps, fcode, fkey + (g->nonstrict ? 1000 : 0) + (g->hubs_last ? 2000 : 0));
   auto it = g->graphs.find(key);
   if (it != g->graphs.end()) return it->second;
   hipGraph_t graph = nullptr;
@@ -1250,6 +1256,26 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
     rc = lpa_set_async_schedule(g, cand[best][0], cand[best][1], cand[best][2], g->async_by_colour ? 1 : 0);
     if (rc != LPA_OK) return rc;
     if (schedule_out) std::memcpy(schedule_out, cand[best], sizeof(cand[best]));
+    // 1b. Order of the bins inside a step: hubs first (the default) or last,
+    //     after the other vertices have updated their labels (fewer distinct
+    //     labels reach the hubs' partitions).  Same acceptance rules.
+    if (g->n_hubs > 0) {
+      rc = lpa_set_bin_order(g, 1);
+      if (rc != LPA_OK) return rc;
+      double ms = 1e300, q = 0.0;
+      bool converged = true;
+      for (int rep = 0; rep < 2; ++rep) {
+        lpa_stats st;
+        rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
+        if (rc != LPA_OK) return rc;
+        ms = std::min(ms, st.total_ms);
+        converged = converged && st.converged;
+      }
+      rc = lpa_modularity(g, nullptr, 0, &q);
+      if (rc != LPA_OK) return rc;
+      if (!(converged && quality_ok(q) && ms < 0.97 * best_ms)) rc = lpa_set_bin_order(g, 0);
+      if (rc != LPA_OK) return rc;
+    }
   } else if (schedule_out) {
     schedule_out[0] = g->sched[0].nphase;
     schedule_out[1] = g->early_sweeps;
@@ -1373,6 +1399,27 @@ int lpa_set_async_phases(lpa_graph *g, int32_t phases, int32_t by_colour) {
   return lpa_set_async_schedule(g, phases, 0, phases, by_colour);
 }
 
+int lpa_set_bin_order(lpa_graph *g, int32_t hubs_last) {
+  return run_guarded(g, [&]() -> int {
+    if (hubs_last != 0 && hubs_last != 1) return LPA_ERR_INVALID_ARG;
+    if ((hubs_last != 0) != g->hubs_last) {
+      g->hubs_last = hubs_last != 0;
+      drop_graphs(g);
+    }
+    return LPA_OK;
+  });
+}
+
+int lpa_get_schedule(const lpa_graph *gc, int32_t *out) {
+  if (!gc || !out) return LPA_ERR_INVALID_ARG;
+  out[0] = gc->sched[0].nphase;
+  out[1] = gc->early_sweeps;
+  out[2] = gc->sched[1].nphase;
+  out[3] = gc->async_by_colour ? 1 : 0;
+  out[4] = gc->hubs_last ? 1 : 0;
+  return LPA_OK;
+}
+
 int lpa_color(lpa_graph *g, uint32_t seed, int32_t *colors_out, unsigned flags, int32_t *num_colors) {
   return run_guarded(g, [&]() -> int {
     ensure_colored(g, seed);
@@ -1429,6 +1476,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     // gate features: written while the gate is used or training traces are recorded
     const bool gate = flags & LPA_FLAG_GATE;
     const bool trace = flags & LPA_FLAG_TRACE;
+    g->nonstrict = flags & LPA_FLAG_NONSTRICT;
     g->feat_on = gate || trace;
     g->gate_active = gate;
     if (gate && !g->gskip) g->gskip = dalloc_n<uint8_t>(g, g->n);

@@ -111,9 +111,9 @@ __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   constexpr int BITS = __builtin_ctz(HUB_CHUNK_SLOTS);
   __shared__ u64 T[HUB_CHUNK_SLOTS];
-  extern __shared__ int32_t dyn[];  // 2 << max_pbits counters
+  extern __shared__ int32_t dyn[];  // 2 << min(max_pbits, HUB_LDS_PBITS) counters
   int32_t *hist = dyn;
-  int32_t *pbase = dyn + (1 << h.max_pbits);
+  int32_t *pbase = dyn + (1 << min(h.max_pbits, HUB_LDS_PBITS));
   const u64 total = a.ctl->hub_chunks;
   int err = 0;
   for (u64 c = blockIdx.x; c < total; c += gridDim.x) {
@@ -124,24 +124,50 @@ __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
     const int P = 1 << pb;
     const int64_t eb = a.off[v] + (int64_t)(c - h.cstart[i]) * HUB_CHUNK;
     const int64_t ee = min(a.off[v + 1], eb + (int64_t)HUB_CHUNK);
+    const bool lds_count = pb <= HUB_LDS_PBITS;
     for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) T[s] = EMPTY;
-    for (int p = threadIdx.x; p < P; p += 256) hist[p] = 0;
+    if (lds_count)
+      for (int p = threadIdx.x; p < P; p += 256) hist[p] = 0;
     __syncthreads();
     err |= scan_row<256, 8, BITS, WK>(a.idx, a.w, a.C, eb, ee, v, threadIdx.x, T);
     __syncthreads();
+    int32_t *cnt = h.pcnt + h.cnt_base[k];
+    u64 *dst = h.pairs + h.pair_base[k];
+    if (!lds_count) {
+      // a giant hub: every merged label reserves its partition slot directly
+      for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) {
+        const u64 x = T[s];
+        if (x == EMPTY) continue;
+        const uint32_t p = part_of((uint32_t)(x >> 32), pb);
+        const int pos = atomicAdd(&cnt[p], 1);
+        if (pos < h.part_cap) {
+          dst[(int64_t)p * HUB_PART_CAP + pos] = x;
+        } else {
+          const u64 q = atomicAdd(h.ovf_count, (u64)1);
+          if (q < (u64)HUB_OVERFLOW_CAP) {
+            uint32_t *o = h.ovf + 4 * q;
+            o[0] = (uint32_t)(h.pstart[i] + p);
+            o[1] = (uint32_t)(x >> 32);
+            o[2] = (uint32_t)x;
+          } else {
+            err |= 8;
+          }
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) {
       const u64 x = T[s];
       if (x != EMPTY) atomicAdd(&hist[part_of((uint32_t)(x >> 32), pb)], 1);
     }
     __syncthreads();
-    int32_t *cnt = h.pcnt + h.cnt_base[k];
     for (int p = threadIdx.x; p < P; p += 256) {
       const int n = hist[p];
       if (n) pbase[p] = atomicAdd(&cnt[p], n);
       hist[p] = 0;
     }
     __syncthreads();
-    u64 *dst = h.pairs + h.pair_base[k];
     for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) {
       const u64 x = T[s];
       if (x == EMPTY) continue;
@@ -179,10 +205,19 @@ __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
     const int i = h.part_owner[q];
     const int k = h.ord[i];
     const int p = (int)(q - h.pstart[i]);
-    for (int s = threadIdx.x; s < HUB_PART_SLOTS; s += 256) T[s] = EMPTY;
-    __syncthreads();
     int32_t *cnt = h.pcnt + h.cnt_base[k] + p;
-    const int n = min(*cnt, h.part_cap);
+    const int reserved = *cnt;  // every pair offered to the partition, spilled ones included
+    const int n = min(reserved, h.part_cap);
+    const bool spilled = reserved > h.part_cap;
+    // a table just large enough to stay at most half full (partitions of
+    // later sweeps hold few labels); a partition that spilled takes the full
+    // table and merges its entries of the overflow area
+    int tb = 6;
+    while (tb < BITS && (1 << tb) < 2 * n) ++tb;
+    if (spilled) tb = BITS;
+    const int slots = 1 << tb;
+    for (int s = threadIdx.x; s < slots; s += 256) T[s] = EMPTY;
+    __syncthreads();
     const u64 *src = h.pairs + h.pair_base[k] + (int64_t)p * HUB_PART_CAP;
     constexpr int R = (HUB_PART_CAP + 255) / 256;
     u64 x[R];
@@ -193,20 +228,22 @@ __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (x[r] != EMPTY) err |= !lds_insert<BITS>(T, (uint32_t)(x[r] >> 32), (uint32_t)x[r]);
-    for (u64 s = threadIdx.x; s < nov; s += 256) {
-      const uint32_t *o = h.ovf + 4 * s;
-      if (o[0] == (uint32_t)q) err |= !lds_insert<BITS>(T, o[1], o[2]);
-    }
+      if (x[r] != EMPTY) err |= !lds_insert_rt(T, tb, (uint32_t)(x[r] >> 32), (uint32_t)x[r]);
+    if (spilled)
+      for (u64 s = threadIdx.x; s < nov; s += 256) {
+        const uint32_t *o = h.ovf + 4 * s;
+        if (o[0] == (uint32_t)q) err |= !lds_insert_rt(T, tb, o[1], o[2]);
+      }
     __syncthreads();
-    const u64 best = block_max<256>(table_best<256, HUB_PART_SLOTS>(T, threadIdx.x), red);
+    const TieRule tr = tie_rule_of(a, a.front[i]);
+    const u64 best = block_max<256>(table_best_rt<256>(T, slots, threadIdx.x, tr), red);
     if (threadIdx.x == 0) {
       h.partbest[q] = best;
       *cnt = 0;  // partitions start empty at the next step
     }
     if constexpr (FEAT) {
       __shared__ TabStats tred[4];
-      const TabStats t = group_stats<64>(table_stats<256, HUB_PART_SLOTS>(T, threadIdx.x));
+      const TabStats t = group_stats<64>(table_stats_rt<256>(T, slots, threadIdx.x));
       if ((threadIdx.x & 63) == 0) tred[threadIdx.x >> 6] = t;
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -214,7 +251,7 @@ __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
         h.part_w2[q] = m.w2;
         h.part_nd[q] = m.nd;
         const uint32_t cur = (uint32_t)a.C[a.front[i]];
-        if ((int)part_of(cur, h.pbits[k]) == p) h.own_w[i] = table_lookup<BITS>(T, cur);
+        if ((int)part_of(cur, h.pbits[k]) == p) h.own_w[i] = table_lookup_rt(T, tb, cur);
       }
     }
     __syncthreads();
@@ -241,7 +278,7 @@ __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
     int changed = 0;
     const int32_t cur = a.C[v];
     if (best != 0) {
-      const int32_t cs = (int32_t)key_label(best);
+      const int32_t cs = (int32_t)key_label(best, tie_rule_of(a, v));
       if (cs != cur) {
         changed = 1;
         if (lane == 0) {
@@ -299,7 +336,7 @@ void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, hipStream_
 }
 
 void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h) {
-  const size_t lds = sizeof(int32_t) * (2u << h.max_pbits);
+  const size_t lds = sizeof(int32_t) * (2u << std::min(h.max_pbits, HUB_LDS_PBITS));
   if (wk == W_UNIT) hipLaunchKernelGGL(k_hub_chunk<W_UNIT>, dim3(blocks), dim3(256), lds, st, a, h);
   else if (wk == W_U8) hipLaunchKernelGGL(k_hub_chunk<W_U8>, dim3(blocks), dim3(256), lds, st, a, h);
   else hipLaunchKernelGGL(k_hub_chunk<W_U32>, dim3(blocks), dim3(256), lds, st, a, h);

@@ -140,7 +140,10 @@ __global__ void k_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_do
   }
   ctl->total_changed += dn;
   ctl->dense_prev = ctl->dense_cur;
-  ctl->dense_cur = ctl->dense_enabled && (double)dn > ctl->dense_frac * (double)ctl->n_active;
+  // A gated sweep writes exact marks: its flags, with those the gate kept,
+  // are all the verification sweep has to process (a dense sweep would flag
+  // every vertex and turn the verification into a full sweep).
+  ctl->dense_cur = ctl->dense_enabled && !ctl->gate_on && (double)dn > ctl->dense_frac * (double)ctl->n_active;
   ctl->iterations = it + 1;
   ctl->sweep = s + 1;
   if (ctl->batch) {
@@ -503,12 +506,13 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
     wave_lds_sync();
     TabStats ts{0u, 0u, 0};
     u64 lbest;
-    if constexpr (FEAT) lbest = table_best_stats<GROUP, SLOTS, TS>(T, lane, ts);
-    else lbest = table_best<GROUP, SLOTS, TS>(T, lane);
+    const TieRule tr = tie_rule_of(a, A.v);
+    if constexpr (FEAT) lbest = table_best_stats<GROUP, SLOTS, TS>(T, lane, ts, tr);
+    else lbest = table_best<GROUP, SLOTS, TS>(T, lane, tr);
     const u64 best = group_max<GROUP>(lbest);
     bool changed = false;
     if (best != 0) {
-      const int32_t cs = (int32_t)key_label(best);
+      const int32_t cs = (int32_t)key_label(best, tr);
       if (cs != A.cur) {
         changed = true;
         if (lane == 0) {
@@ -575,12 +579,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan_block(ScanArgs a) {
     __syncthreads();
     TabStats ts{0u, 0u, 0};
     u64 lbest;
-    if constexpr (FEAT) lbest = table_best_stats<BLOCK, SLOTS>(T, threadIdx.x, ts);
-    else lbest = table_best<BLOCK, SLOTS>(T, threadIdx.x);
+    const TieRule tr = tie_rule_of(a, A.v);
+    if constexpr (FEAT) lbest = table_best_stats<BLOCK, SLOTS>(T, threadIdx.x, ts, tr);
+    else lbest = table_best<BLOCK, SLOTS>(T, threadIdx.x, tr);
     const u64 best = block_max<BLOCK>(lbest, red);
     bool changed = false;
     if (best != 0) {
-      const int32_t cs = (int32_t)key_label(best);
+      const int32_t cs = (int32_t)key_label(best, tr);
       if (cs != A.cur) {
         changed = true;
         if (threadIdx.x == 0) {

@@ -34,6 +34,31 @@ __device__ __forceinline__ bool lds_insert(u64 *T, uint32_t lbl, uint32_t w) {
   return false;
 }
 
+// lds_insert for a table of 2^bits entries chosen at run time.
+__device__ __forceinline__ bool lds_insert_rt(u64 *T, int bits, uint32_t lbl, uint32_t w) {
+  const uint32_t mask = (1u << bits) - 1;
+  uint32_t h = slot_hash(lbl, bits);
+  const u64 mine = ((u64)lbl << 32) | w;
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    u64 *slot = &T[h];
+    const u64 cur = __atomic_load_n(slot, __ATOMIC_RELAXED);
+    if ((uint32_t)(cur >> 32) == lbl) {
+      atomicAdd(slot, (u64)w);
+      return true;
+    }
+    if (cur == EMPTY) {
+      const u64 old = atomicCAS(slot, EMPTY, mine);
+      if (old == EMPTY) return true;
+      if ((uint32_t)(old >> 32) == lbl) {
+        atomicAdd(slot, (u64)w);
+        return true;
+      }
+    }
+    h = (h + 1) & mask;
+  }
+  return false;
+}
+
 // Gathers the labels of the entries [b, e) of row v, lanes lane, lane+G, ...,
 // U entries per lane in flight, and adds them to table T.  The vertex itself
 // is skipped (scanCommunities of Algorithm 1).
@@ -109,15 +134,29 @@ __device__ __forceinline__ u64 mark_row(const int32_t *__restrict__ idx, uint8_t
   return marks;
 }
 
-// Largest argmax key among the slots lane, lane+G, ... of T.
+// Largest argmax key among the slots lane, lane+G, ... of T (tie rule t).
 template <int G, int SLOTS, int STRIDE = 1>
-__device__ __forceinline__ u64 table_best(const u64 *T, int lane) {
+__device__ __forceinline__ u64 table_best(const u64 *T, int lane, TieRule t) {
   u64 best = 0;
 #pragma unroll 4
   for (int s = lane; s < SLOTS; s += G) {
     const u64 x = T[s * STRIDE];
     if (x != EMPTY) {
-      const u64 kk = entry_key(x);
+      const u64 kk = entry_key(x, t);
+      best = kk > best ? kk : best;
+    }
+  }
+  return best;
+}
+
+// table_best over the first `slots` entries of T (a size chosen at run time).
+template <int G>
+__device__ __forceinline__ u64 table_best_rt(const u64 *T, int slots, int lane, TieRule t) {
+  u64 best = 0;
+  for (int s = lane; s < slots; s += G) {
+    const u64 x = T[s];
+    if (x != EMPTY) {
+      const u64 kk = entry_key(x, t);
       best = kk > best ? kk : best;
     }
   }
@@ -151,16 +190,35 @@ __device__ __forceinline__ TabStats table_stats(const u64 *T, int lane) {
   return r;
 }
 
+template <int G>
+__device__ __forceinline__ TabStats table_stats_rt(const u64 *T, int slots, int lane) {
+  TabStats r{0u, 0u, 0};
+  for (int s = lane; s < slots; s += G) {
+    const u64 x = T[s];
+    if (x != EMPTY) {
+      const uint32_t w = (uint32_t)x;
+      ++r.nd;
+      if (w > r.w1) {
+        r.w2 = r.w1;
+        r.w1 = w;
+      } else if (w > r.w2) {
+        r.w2 = w;
+      }
+    }
+  }
+  return r;
+}
+
 // table_best and table_stats in one pass over the slots.
 template <int G, int SLOTS, int STRIDE = 1>
-__device__ __forceinline__ u64 table_best_stats(const u64 *T, int lane, TabStats &r) {
+__device__ __forceinline__ u64 table_best_stats(const u64 *T, int lane, TabStats &r, TieRule t) {
   u64 best = 0;
   r = TabStats{0u, 0u, 0};
 #pragma unroll 4
   for (int s = lane; s < SLOTS; s += G) {
     const u64 x = T[s * STRIDE];
     if (x != EMPTY) {
-      const u64 kk = entry_key(x);
+      const u64 kk = entry_key(x, t);
       best = kk > best ? kk : best;
       const uint32_t w = (uint32_t)x;
       ++r.nd;
@@ -208,6 +266,19 @@ __device__ __forceinline__ uint32_t table_lookup(const u64 *T, uint32_t lbl) {
     if (x == EMPTY) return 0u;
     if ((uint32_t)(x >> 32) == lbl) return (uint32_t)x;
     h = (h + 1) & MASK;
+  }
+  return 0u;
+}
+
+// table_lookup for a table of 2^bits entries chosen at run time.
+__device__ __forceinline__ uint32_t table_lookup_rt(const u64 *T, int bits, uint32_t lbl) {
+  const uint32_t mask = (1u << bits) - 1;
+  uint32_t h = slot_hash(lbl, bits);
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const u64 x = T[h];
+    if (x == EMPTY) return 0u;
+    if ((uint32_t)(x >> 32) == lbl) return (uint32_t)x;
+    h = (h + 1) & mask;
   }
   return 0u;
 }

@@ -77,7 +77,7 @@ def train(X, y, epochs: int = 4, batch: int = 4096, lr: float = 1e-3, holdout: f
     pw = float((len(yt) - npos) / max(npos, 1))
     p0 = init_params(seed) if params is None else np.asarray(params, np.float32)
     order = None
-    if len(yt) * epochs <= (1 << 26):
+    if len(yt) * epochs <= (1 << 28):
         order = np.concatenate([rng.permutation(len(yt)) for _ in range(epochs)]).astype(np.int64)
     params, losses = abi.gate_train(p0, Xt, yt, epochs, batch, lr=lr, pos_weight=pw, order=order, device=device)
     Xh, yh = np.ascontiguousarray(X[ho]), np.ascontiguousarray(y[ho])

@@ -72,7 +72,8 @@ def fake_root(tmp_path, monkeypatch):
 def test_profiled_config_needs_matching_sources(fake_root):
     root, digest = fake_root
     _write_profile(root, digest, [0, 2, 2, 2, 2, 1], [1, 0, 1], [7, 31, 127, 511, 2047, 8191])
-    assert bench.profiled_config("rmat24") == ([0, 2, 2, 2, 2, 1], [1, 0, 1], [7, 31, 127, 511, 2047, 8191])
+    assert bench.profiled_config("rmat24") == {"variants": [0, 2, 2, 2, 2, 1], "schedule": [1, 0, 1],
+                                               "bins": [7, 31, 127, 511, 2047, 8191], "hubs_last": 0}
     _write_profile(root, "0" * 16, [0, 2, 2, 2, 2, 1], [1, 0, 1])
     assert bench.profiled_config("rmat24") is None
     assert bench.profiled_config("rmat26") is None  # no summary at all
@@ -81,7 +82,7 @@ def test_profiled_config_needs_matching_sources(fake_root):
 def test_profile_without_bins_means_default_bins(fake_root):
     root, digest = fake_root
     _write_profile(root, digest, [0] * 6, [16, 2, 4])
-    assert bench.profiled_config("rmat24")[2] == bench.DEFAULT_BINS
+    assert bench.profiled_config("rmat24")["bins"] == bench.DEFAULT_BINS
 
 
 def test_measured_traffic_only_for_the_profiled_configuration(fake_root):
@@ -91,7 +92,8 @@ def test_measured_traffic_only_for_the_profiled_configuration(fake_root):
     assert bench.measured_traffic("bin5", dict(cfg), "rmat24") == 3896665165
     assert bench.measured_traffic("bin4", dict(cfg), "rmat24") is None       # kernel not in the summary
     assert bench.measured_traffic("bin5", None, "rmat24") is None            # untuned run
-    for key, other in (("variants", [1] * 6), ("schedule", [16, 2, 4]), ("bins", bench.DEFAULT_BINS)):
+    for key, other in (("variants", [1] * 6), ("schedule", [16, 2, 4]), ("bins", bench.DEFAULT_BINS),
+                       ("hubs_last", 1)):
         changed = dict(cfg)
         changed[key] = other
         assert bench.measured_traffic("bin5", changed, "rmat24") is None

@@ -35,7 +35,11 @@ def star(L):
     return gg.from_edges(L + 1, [(0, i) for i in range(1, L + 1)])
 
 
-def check_det(g, tau=0.05, max_iters=20, prune=True, seed=0, bins=None, flags=0, variants=None, reorder=True):
+def check_det(g, tau=0.05, max_iters=20, prune=True, seed=0, bins=None, flags=0, variants=None, reorder=True,
+              hubs_last=False):
+    """Deterministic run vs the oracle in (colour, id) order; LPA_FLAG_NONSTRICT
+    in flags selects the non-strict tie rule on both sides."""
+    strict = not (flags & abi.LPA_FLAG_NONSTRICT)
     say(f"det parity n={g.n} m={g.m} tau={tau} iters={max_iters} prune={prune} bins={bins} flags={flags} "
         f"variants={variants} reorder={reorder}")
     G = abi.LPAGraph(g, reorder=reorder)
@@ -43,11 +47,14 @@ def check_det(g, tau=0.05, max_iters=20, prune=True, seed=0, bins=None, flags=0,
         G.set_bins(bins)
     if variants is not None:
         G.set_variants(variants)
+    if hubs_last:
+        G.set_bin_order(1)
     colors, nc = G.color(seed)
     ocol, onc = oracle.color(g, seed)
     assert nc == onc and np.array_equal(colors, ocol), "colouring differs from the greedy oracle"
     labels, st = G.run(tau, max_iters, DET, prune, flags=flags)
-    ref = oracle.lpa(g, order=oracle.color_order(ocol, onc), tau=tau, max_iters=max_iters, prune=prune)
+    ref = oracle.lpa(g, order=oracle.color_order(ocol, onc), tau=tau, max_iters=max_iters, prune=prune,
+                     strict=strict)
     assert np.array_equal(labels, ref["labels"])
     assert st["iterations"] == ref["iterations"] and st["converged"] == ref["converged"]
     assert st["changed"] == ref["changed"].tolist()
@@ -80,6 +87,52 @@ def test_rmat_deterministic(scale, ef, seed):
     check_det(g)
     if scale == 14:
         check_det(g, prune=False, max_iters=6, tau=0.0)
+
+
+NS = abi.LPA_FLAG_NONSTRICT
+
+
+@pytest.mark.parametrize("kind", ["sbm1k", "rmat14", "rmat16", "star", "cliques", "random"])
+def test_nonstrict_deterministic(kind):
+    """Non-strict LPA (the tie rule of Section 4.1.5 as read here) equals the
+    oracle with the same rule label for label, in every bin and the hub path."""
+    if kind == "sbm1k":
+        check_det(gg.sbm(1000, 10, 0.1, 0.002, seed=3), flags=NS)
+    elif kind == "rmat14":
+        g = gg.rmat(14, 16, seed=3, weighted=False)
+        check_det(g, flags=NS)
+        check_det(g, flags=NS, reorder=False)
+        check_det(g, flags=NS, bins=[0, 0, 0, 0, 0, 0])  # every vertex through the hub kernels
+    elif kind == "rmat16":
+        check_det(gg.rmat(16, 16, seed=4), flags=NS)
+    elif kind == "star":
+        check_det(star(5000), flags=NS)
+    elif kind == "cliques":
+        check_det(cliques(30, 9), flags=NS, tau=0.0, max_iters=30)
+    else:
+        rng = np.random.default_rng(17)
+        for t in range(12):
+            n = int(rng.integers(2, 80))
+            iu = np.triu_indices(n, 1)
+            keep = rng.random(len(iu[0])) < float(rng.uniform(0.05, 0.5))
+            edges = np.stack([iu[0][keep], iu[1][keep]], 1)
+            if len(edges) == 0:
+                edges = np.array([[0, 1]])
+            check_det(gg.from_edges(n, edges), flags=NS, tau=0.0, max_iters=int(rng.integers(1, 12)))
+
+
+def test_nonstrict_async_invariants():
+    """Asynchronous non-strict runs: labels stay in their components, the run
+    converges, and the result differs from the strict one on a tie-rich graph."""
+    g = gg.sbm(20000, 20, 0.02, 0.0002, seed=1, method="skip")
+    G = abi.LPAGraph(g)
+    a, sa = G.run(0.05, 20, ASYNC, True, flags=NS | abi.LPA_FLAG_VERIFY)
+    b, _ = G.run(0.05, 20, ASYNC, True)
+    comp = _components(g)
+    assert np.array_equal(comp[a], comp)
+    assert sa["converged"] and sa["verified"]
+    assert not np.array_equal(a, b)
+    G.close()
 
 
 def test_degenerate_inputs():
@@ -115,6 +168,23 @@ def test_bins_do_not_change_results():
         assert np.array_equal(r2["labels"], ref["labels"])
 
 
+def test_bin_order_does_not_change_deterministic_results():
+    """Hubs after the other bins inside each step: the same oracle labels
+    (the vertices of a colour class are never adjacent); also non-strict."""
+    g = gg.rmat(15, 16, seed=7)
+    check_det(g, bins=[2, 8, 32, 128, 256, 512], hubs_last=True)
+    check_det(g, bins=[2, 8, 32, 128, 256, 512], hubs_last=True, flags=NS)
+    G = abi.LPAGraph(g)
+    G.set_bin_order(1)
+    lab, st = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_VERIFY)
+    comp = _components(g)
+    assert np.array_equal(comp[lab], comp) and st["converged"] and st["verified"]
+    assert G.schedule()[4] == 1
+    with pytest.raises(abi.LPAError):
+        G.set_bin_order(2)
+    G.close()
+
+
 @pytest.mark.parametrize("variant", [1, 2])
 def test_kernel_shapes_do_not_change_results(variant):
     """Every bin's alternative kernel shapes (lanes per vertex, entries in
@@ -133,6 +203,8 @@ def test_autotune_installs_a_valid_choice():
     assert lim in [(4, 16, 64, 256, 1024, 4096), (2, 8, 32, 128, 512, 2048), (6, 24, 96, 384, 1536, 6144),
                    (7, 31, 127, 511, 2047, 8191)]
     assert sch in [(16, 0, 16), (16, 1, 4), (16, 2, 4), (16, 2, 8), (16, 3, 4), (16, 3, 8), (1, 0, 1)]
+    full = G.schedule()
+    assert full[:3] == sch and full[4] in (0, 1)
     colors, nc = G.color(0)
     ocol, onc = oracle.color(g, 0)
     assert nc == onc and np.array_equal(colors, ocol)
@@ -341,6 +413,25 @@ def test_big_hubs_many_partitions():
         members = rng.choice(np.arange(1, 60001), 12, replace=False)
         e2 += list(itertools.combinations(members.tolist(), 2))
     check_det(gg.from_edges(60001, e2, rng.integers(1, 9, len(e2))))
+
+
+def _star_csr(L):
+    """Star with centre 0 and leaves 1..L, built directly as CSR."""
+    off = np.empty(L + 2, np.int64)
+    off[0] = 0
+    off[1:] = L + np.arange(L + 1, dtype=np.int64)
+    idx = np.concatenate([np.arange(1, L + 1, dtype=np.int32), np.zeros(L, np.int32)])
+    return gg.CSR(L + 1, off, idx, None, name=f"star{L}")
+
+
+def test_giant_hub_beyond_lds_partition_counts():
+    """A hub with 10 M distinct neighbour labels (a star's centre in sweep 0)
+    needs 2^14 label partitions, beyond the chunk kernel's LDS counters: its
+    chunks reserve partition slots with global atomics.  Labels equal the
+    oracle (Appendix: every vertex ends on label 1, two sweeps)."""
+    g = _star_csr(10_000_000)
+    ref, st = check_det(g)
+    assert np.all(ref["labels"] == 1) and st["iterations"] == 2
 
 
 def test_hub_partition_spill_path(monkeypatch):
