@@ -50,6 +50,13 @@ constexpr int HUB_CHUNK_SLOTS = 4096;
 constexpr int HUB_PART_TARGET = 1024;
 constexpr int HUB_PART_CAP = 1536;
 constexpr int HUB_PART_SLOTS = 2048;
+constexpr int HUB_PART_GROUP = 16;       // partitions merged together when they hold few pairs
+constexpr int HUB_PART_GROUP_MAX = 1024;  // most pairs of a merged group
+
+// Merge work items of a hub with 2^pbits partitions.
+__host__ __device__ constexpr int hub_merge_groups(int pbits) {
+  return (1 << pbits) > HUB_PART_GROUP ? (1 << pbits) / HUB_PART_GROUP : 1;
+}
 constexpr int HUB_MAX_PBITS = 21;  // partitions for hubs of up to 2^31 entries
 constexpr int HUB_LDS_PBITS = 12;  // up to here the chunk kernel counts its partitions in LDS
 constexpr int64_t HUB_OVERFLOW_CAP = 1 << 22;  // shared spill area for over-full partitions
@@ -194,7 +201,7 @@ struct Ctl {
   double tau;
   int64_t n;
   u64 changed, processed, scanned, gated;  // current sweep
-  u64 hub_chunks, hub_parts;               // hub work items of the current step
+  u64 hub_chunks, hub_groups;              // hub work items of the current step
   u64 st_changed[MAX_REC], st_processed[MAX_REC], st_scanned[MAX_REC], st_gated[MAX_REC];
   u64 t_start, t_sweep[MAX_REC];
   u64 verify_changed, total_changed, verify_scanned;
@@ -291,13 +298,13 @@ struct HubArgs {
   int32_t *ord;              // per frontier entry: hub ordinal
   u64 *cstart;               // per frontier entry: first chunk id of the step
   u64 *pstart;               // per frontier entry: first partition id of the step
+  u64 *gstart;               // per frontier entry: first merge group id of the step
   int32_t *chunk_owner;      // per chunk id of the step: frontier entry
-  int32_t *part_owner;       // per partition id of the step: frontier entry
+  int32_t *group_owner;      // per merge group id of the step: frontier entry
   int32_t *changed;          // per frontier entry: 1 if the hub took a new label
   uint32_t *part_w2;         // FEAT: second largest label weight of each partition
   int32_t *part_nd;          // FEAT: distinct labels of each partition
   uint32_t *own_w;           // FEAT: per frontier entry, weight of the hub's own label
-  int32_t max_pbits;         // largest pbits of any hub (sizes the chunk kernel's LDS)
 };
 
 // Wave64 helpers.

@@ -104,7 +104,7 @@ struct lpa_graph {
   int32_t n_hubs = 0;
   int64_t hub_chunks_total = 0, hub_parts_total = 0;
   int32_t hub_part_cap = HUB_PART_CAP;
-  std::vector<int32_t> h_hub_ids, h_hub_chunks, h_hub_parts;
+  std::vector<int32_t> h_hub_ids, h_hub_chunks, h_hub_parts;  // h_hub_parts: merge groups of each hub
   std::vector<int64_t> col_hub_chunks, col_hub_parts;  // per colour class (deterministic grids)
   std::vector<int32_t> h_color;
   int32_t *hub_ids = nullptr, *hub_chunks = nullptr, *hub_pbits = nullptr;
@@ -115,11 +115,10 @@ struct lpa_graph {
   uint32_t *hub_ovf = nullptr;
   u64 *hub_ovf_count = nullptr;
   int32_t *hub_ord = nullptr;
-  u64 *hub_cstart = nullptr, *hub_pstart = nullptr;
-  int32_t *hub_chunk_owner = nullptr, *hub_part_owner = nullptr, *hub_changed = nullptr;
+  u64 *hub_cstart = nullptr, *hub_pstart = nullptr, *hub_gstart = nullptr;
+  int32_t *hub_chunk_owner = nullptr, *hub_group_owner = nullptr, *hub_changed = nullptr;
   uint32_t *hub_part_w2 = nullptr, *hub_own_w = nullptr;
   int32_t *hub_part_nd = nullptr;
-  int32_t hub_max_pbits = 0;
   // control
   Ctl *ctl = nullptr;
   int32_t *host_done = nullptr;
@@ -348,7 +347,8 @@ void build_hubs(lpa_graph *g) {
                    (void **)&g->hub_pair_base, (void **)&g->hub_cnt_base, (void **)&g->hub_pairs,
                    (void **)&g->hub_pcnt, (void **)&g->hub_partbest, (void **)&g->hub_ovf,
                    (void **)&g->hub_ovf_count, (void **)&g->hub_ord, (void **)&g->hub_cstart,
-                   (void **)&g->hub_pstart, (void **)&g->hub_chunk_owner, (void **)&g->hub_part_owner,
+                   (void **)&g->hub_pstart, (void **)&g->hub_gstart, (void **)&g->hub_chunk_owner,
+                   (void **)&g->hub_group_owner,
                    (void **)&g->hub_changed, (void **)&g->hub_part_w2, (void **)&g->hub_own_w,
                    (void **)&g->hub_part_nd};
   for (void **b : bufs) {
@@ -363,7 +363,7 @@ void build_hubs(lpa_graph *g) {
   g->n_hubs = (int32_t)nh;
   std::vector<int32_t> chunks(nh), pbits(nh);
   std::vector<int64_t> pair_base(nh), cnt_base(nh);
-  int64_t pairs = 0, parts = 0, nch = 0;
+  int64_t pairs = 0, parts = 0, groups = 0, nch = 0;
   for (size_t k = 0; k < nh; ++k) {
     const int64_t deg = g->h_off[ids[k] + 1] - g->h_off[ids[k]];
     chunks[k] = (int32_t)((deg + HUB_CHUNK - 1) / HUB_CHUNK);
@@ -374,18 +374,17 @@ void build_hubs(lpa_graph *g) {
     cnt_base[k] = parts;
     pairs += ((int64_t)1 << pb) * HUB_PART_CAP;
     parts += (int64_t)1 << pb;
+    groups += hub_merge_groups(pb);
     nch += chunks[k];
   }
   g->hub_chunks_total = nch;
   g->hub_parts_total = parts;
-  g->hub_max_pbits = 0;
-  for (int32_t pb : pbits) g->hub_max_pbits = std::max(g->hub_max_pbits, pb);
   g->hub_chunk_owner = dalloc_n<int32_t>(g, std::max<int64_t>(1, nch));
-  g->hub_part_owner = dalloc_n<int32_t>(g, std::max<int64_t>(1, parts));
+  g->hub_group_owner = dalloc_n<int32_t>(g, std::max<int64_t>(1, groups));
   g->h_hub_ids = ids;
   g->h_hub_chunks = chunks;
   g->h_hub_parts.resize(nh);
-  for (size_t k = 0; k < nh; ++k) g->h_hub_parts[k] = 1 << pbits[k];
+  for (size_t k = 0; k < nh; ++k) g->h_hub_parts[k] = hub_merge_groups(pbits[k]);
   const int64_t n1 = std::max<int64_t>(1, (int64_t)nh);
   g->hub_ids = dalloc_n<int32_t>(g, n1);
   g->hub_chunks = dalloc_n<int32_t>(g, n1);
@@ -395,6 +394,7 @@ void build_hubs(lpa_graph *g) {
   g->hub_ord = dalloc_n<int32_t>(g, n1);
   g->hub_cstart = dalloc_n<u64>(g, n1);
   g->hub_pstart = dalloc_n<u64>(g, n1);
+  g->hub_gstart = dalloc_n<u64>(g, n1);
   g->hub_changed = dalloc_n<int32_t>(g, n1);
   g->hub_own_w = dalloc_n<uint32_t>(g, n1);
   g->hub_part_w2 = dalloc_n<uint32_t>(g, std::max<int64_t>(1, parts));
@@ -436,12 +436,12 @@ HubArgs hub_args(lpa_graph *g) {
   h.cstart = g->hub_cstart;
   h.pstart = g->hub_pstart;
   h.chunk_owner = g->hub_chunk_owner;
-  h.part_owner = g->hub_part_owner;
+  h.gstart = g->hub_gstart;
+  h.group_owner = g->hub_group_owner;
   h.changed = g->hub_changed;
   h.part_w2 = g->hub_part_w2;
   h.part_nd = g->hub_part_nd;
   h.own_w = g->hub_own_w;
-  h.max_pbits = g->hub_max_pbits;
   return h;
 }
 

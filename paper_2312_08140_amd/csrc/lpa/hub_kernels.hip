@@ -7,9 +7,11 @@
 //   k_hub_chunk   per chunk of HUB_CHUNK entries: gather the neighbour
 //                 labels, merge equal labels in an LDS table, and append the
 //                 merged (label, weight) pairs to the hub's label partitions;
-//   k_hub_part    per (hub, partition): merge the partition's pairs in LDS and
-//                 keep its heaviest label (smallest id on ties);
-//   k_hub_decide  per hub: best over the partitions, update;
+//   k_hub_part    per group of a hub's partitions: merge the pairs in LDS
+//                 (the whole group at once when it holds few pairs) and keep
+//                 the heaviest label (smallest id on ties);
+//   k_hub_decide  per hub: best over the partitions, update, clear the
+//                 partition counters;
 //   k_hub_mark    per chunk of a hub that changed: flag the neighbours.
 // Every label falls in exactly one partition, so the per-partition maxima
 // combine into the strict argmax of Eq. (2).
@@ -24,10 +26,10 @@ __device__ __forceinline__ uint32_t part_of(uint32_t lbl, int pbits) {
 
 __global__ __launch_bounds__(1024) void k_hub_plan(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
-  __shared__ u64 wsum[2][16];
-  __shared__ u64 s_carry[2];
+  __shared__ u64 wsum[3][16];
+  __shared__ u64 s_carry[3];
   if (threadIdx.x == 0) {
-    s_carry[0] = s_carry[1] = 0;
+    s_carry[0] = s_carry[1] = s_carry[2] = 0;
     *h.ovf_count = 0;
   }
   __syncthreads();
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(1024) void k_hub_plan(ScanArgs a, HubArgs h) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int tile = 0; tile < count; tile += 1024) {
     const int i = tile + threadIdx.x;
-    u64 kc = 0, kp = 0;
+    u64 kc = 0, kp = 0, kg = 0;
     if (i < count) {
       const int v = a.front[i];
       int lo = 0, hi = h.n_hubs;  // lower bound of v among the sorted hub ids
@@ -50,70 +52,83 @@ __global__ __launch_bounds__(1024) void k_hub_plan(ScanArgs a, HubArgs h) {
       } else {
         kc = (u64)h.chunks[lo];
         kp = (u64)1 << h.pbits[lo];
+        kg = (u64)hub_merge_groups(h.pbits[lo]);
       }
       h.ord[i] = lo;
       if (h.own_w) h.own_w[i] = 0;
     }
-    u64 xc = kc, xp = kp;
+    u64 xc = kc, xp = kp, xg = kg;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const u64 yc = (u64)__shfl_up((unsigned long long)xc, d, 64);
       const u64 yp = (u64)__shfl_up((unsigned long long)xp, d, 64);
+      const u64 yg = (u64)__shfl_up((unsigned long long)xg, d, 64);
       if (lane >= d) {
         xc += yc;
         xp += yp;
+        xg += yg;
       }
     }
     if (lane == 63) {
       wsum[0][wv] = xc;
       wsum[1][wv] = xp;
+      wsum[2][wv] = xg;
     }
     __syncthreads();
-    u64 bc = 0, bp = 0;
+    u64 bc = 0, bp = 0, bg = 0;
     for (int k = 0; k < wv; ++k) {
       bc += wsum[0][k];
       bp += wsum[1][k];
+      bg += wsum[2][k];
     }
-    const u64 cc = s_carry[0], cp = s_carry[1];
+    const u64 cc = s_carry[0], cp = s_carry[1], cg = s_carry[2];
     if (i < count) {
       h.cstart[i] = cc + bc + xc - kc;
       h.pstart[i] = cp + bp + xp - kp;
+      h.gstart[i] = cg + bg + xg - kg;
     }
     __syncthreads();
     if (threadIdx.x == 1023) {
       s_carry[0] = cc + bc + xc;
       s_carry[1] = cp + bp + xp;
+      s_carry[2] = cg + bg + xg;
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     a.ctl->hub_chunks = s_carry[0];
-    a.ctl->hub_parts = s_carry[1];
+    a.ctl->hub_groups = s_carry[2];
   }
 }
 
-// Owner maps of the step's work items (chunk / partition -> frontier entry),
+// Owner maps of the step's work items (chunk / merge group -> frontier entry),
 // one workgroup per flagged hub.
 __global__ __launch_bounds__(256) void k_hub_owner(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   const int count = *a.fcount;
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const int k = h.ord[i];
-    const int kc = h.chunks[k], kp = 1 << h.pbits[k];
-    const u64 c0 = h.cstart[i], p0 = h.pstart[i];
+    const int kc = h.chunks[k], kg = hub_merge_groups(h.pbits[k]);
+    const u64 c0 = h.cstart[i], g0 = h.gstart[i];
     for (int c = threadIdx.x; c < kc; c += 256) h.chunk_owner[c0 + c] = i;
-    for (int p = threadIdx.x; p < kp; p += 256) h.part_owner[p0 + p] = i;
+    for (int gq = threadIdx.x; gq < kg; gq += 256) h.group_owner[g0 + gq] = i;
   }
 }
 
+// One LDS array per workgroup: first the chunk's label table, then - once
+// every thread holds its share of the table's slots in registers - the
+// partition counters (2 << pbits ints, never more than the table's bytes).
+// 32 KB per workgroup keeps five workgroups on a CU, which the gathers need
+// to keep enough loads in flight.
 template <int WK>
 __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   constexpr int BITS = __builtin_ctz(HUB_CHUNK_SLOTS);
+  constexpr int PER = HUB_CHUNK_SLOTS / 256;
+  static_assert(2 * (1 << HUB_LDS_PBITS) * sizeof(int32_t) <= HUB_CHUNK_SLOTS * sizeof(u64),
+                "the partition counters fit in the table's memory");
   __shared__ u64 T[HUB_CHUNK_SLOTS];
-  extern __shared__ int32_t dyn[];  // 2 << min(max_pbits, HUB_LDS_PBITS) counters
-  int32_t *hist = dyn;
-  int32_t *pbase = dyn + (1 << min(h.max_pbits, HUB_LDS_PBITS));
+  int32_t *hist = reinterpret_cast<int32_t *>(T);
   const u64 total = a.ctl->hub_chunks;
   int err = 0;
   for (u64 c = blockIdx.x; c < total; c += gridDim.x) {
@@ -124,43 +139,45 @@ __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
     const int P = 1 << pb;
     const int64_t eb = a.off[v] + (int64_t)(c - h.cstart[i]) * HUB_CHUNK;
     const int64_t ee = min(a.off[v + 1], eb + (int64_t)HUB_CHUNK);
-    const bool lds_count = pb <= HUB_LDS_PBITS;
     for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) T[s] = EMPTY;
-    if (lds_count)
-      for (int p = threadIdx.x; p < P; p += 256) hist[p] = 0;
     __syncthreads();
     err |= scan_row<256, 8, BITS, WK>(a.idx, a.w, a.C, eb, ee, v, threadIdx.x, T);
     __syncthreads();
+    u64 x[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) x[r] = T[threadIdx.x + r * 256];
+    __syncthreads();  // the table's memory is reused from here on
     int32_t *cnt = h.pcnt + h.cnt_base[k];
     u64 *dst = h.pairs + h.pair_base[k];
-    if (!lds_count) {
+    if (pb > HUB_LDS_PBITS) {
       // a giant hub: every merged label reserves its partition slot directly
-      for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) {
-        const u64 x = T[s];
-        if (x == EMPTY) continue;
-        const uint32_t p = part_of((uint32_t)(x >> 32), pb);
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        if (x[r] == EMPTY) continue;
+        const uint32_t p = part_of((uint32_t)(x[r] >> 32), pb);
         const int pos = atomicAdd(&cnt[p], 1);
         if (pos < h.part_cap) {
-          dst[(int64_t)p * HUB_PART_CAP + pos] = x;
+          dst[(int64_t)p * HUB_PART_CAP + pos] = x[r];
         } else {
           const u64 q = atomicAdd(h.ovf_count, (u64)1);
           if (q < (u64)HUB_OVERFLOW_CAP) {
             uint32_t *o = h.ovf + 4 * q;
             o[0] = (uint32_t)(h.pstart[i] + p);
-            o[1] = (uint32_t)(x >> 32);
-            o[2] = (uint32_t)x;
+            o[1] = (uint32_t)(x[r] >> 32);
+            o[2] = (uint32_t)x[r];
           } else {
             err |= 8;
           }
         }
       }
-      __syncthreads();
-      continue;
+      continue;  // no LDS use after the barrier above
     }
-    for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) {
-      const u64 x = T[s];
-      if (x != EMPTY) atomicAdd(&hist[part_of((uint32_t)(x >> 32), pb)], 1);
-    }
+    int32_t *pbase = hist + P;
+    for (int p = threadIdx.x; p < P; p += 256) hist[p] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+      if (x[r] != EMPTY) atomicAdd(&hist[part_of((uint32_t)(x[r] >> 32), pb)], 1);
     __syncthreads();
     for (int p = threadIdx.x; p < P; p += 256) {
       const int n = hist[p];
@@ -168,20 +185,20 @@ __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
       hist[p] = 0;
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) {
-      const u64 x = T[s];
-      if (x == EMPTY) continue;
-      const uint32_t p = part_of((uint32_t)(x >> 32), pb);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      if (x[r] == EMPTY) continue;
+      const uint32_t p = part_of((uint32_t)(x[r] >> 32), pb);
       const int pos = pbase[p] + atomicAdd(&hist[p], 1);
       if (pos < h.part_cap) {
-        dst[(int64_t)p * HUB_PART_CAP + pos] = x;
+        dst[(int64_t)p * HUB_PART_CAP + pos] = x[r];
       } else {  // partition full: spill (merged by the partition's workgroup)
         const u64 q = atomicAdd(h.ovf_count, (u64)1);
         if (q < (u64)HUB_OVERFLOW_CAP) {
           uint32_t *o = h.ovf + 4 * q;
           o[0] = (uint32_t)(h.pstart[i] + p);
-          o[1] = (uint32_t)(x >> 32);
-          o[2] = (uint32_t)x;
+          o[1] = (uint32_t)(x[r] >> 32);
+          o[2] = (uint32_t)x[r];
         } else {
           err |= 8;
         }
@@ -192,69 +209,123 @@ __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
   if (err) atomicOr(&a.ctl->error, err);
 }
 
+// Merges partitions [mb, mb + mc) of frontier hub i (ordinal k) in one LDS
+// table and stores the best key of the union in the first partition's slot
+// (zero in the others).  Partitions hold disjoint label sets, so the best of
+// the union is the best of the partitions.  n pairs in all; cm[m] pairs in
+// partition mb + m when mc > 1 (a merge of several partitions never includes
+// one that spilled); a single partition that spilled also merges its
+// entries of the overflow area.
+template <bool FEAT>
+__device__ __forceinline__ int merge_parts(const ScanArgs &a, const HubArgs &h, u64 *T, u64 *red, int i, int k,
+                                           int pb, int mb, int mc, int n, bool spilled,
+                                           const int (&cm)[HUB_PART_GROUP], u64 nov) {
+  constexpr int BITS = __builtin_ctz(HUB_PART_SLOTS);
+  int err = 0;
+  const u64 q0 = h.pstart[i] + (u64)mb;  // step-wide id of the first partition
+  // a table just large enough to stay at most half full (partitions of
+  // later sweeps hold few labels); a partition that spilled takes the full
+  // table
+  int tb = 6;
+  while (tb < BITS && (1 << tb) < 2 * n) ++tb;
+  if (spilled) tb = BITS;
+  const int slots = 1 << tb;
+  for (int s = threadIdx.x; s < slots; s += 256) T[s] = EMPTY;
+  __syncthreads();
+  // pair f of the merge: pair f - (pairs of the earlier partitions) of the
+  // partition it falls in; all loads are in flight at once
+  const u64 *src = h.pairs + h.pair_base[k] + (int64_t)mb * HUB_PART_CAP;
+  constexpr int R = (HUB_PART_CAP + 255) / 256;
+  u64 x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int f = threadIdx.x + r * 256;
+    x[r] = EMPTY;
+    if (f < n) {
+      int64_t at = f;
+      if (mc > 1) {
+        int base = 0;
+        at = -1;
+#pragma unroll
+        for (int m = 0; m < HUB_PART_GROUP; ++m) {
+          if (at < 0 && f < base + cm[m]) at = (int64_t)m * HUB_PART_CAP + (f - base);
+          base += cm[m];
+        }
+      }
+      x[r] = src[at];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (x[r] != EMPTY) err |= !lds_insert_rt(T, tb, (uint32_t)(x[r] >> 32), (uint32_t)x[r]);
+  if (spilled)
+    for (u64 s = threadIdx.x; s < nov; s += 256) {
+      const uint32_t *o = h.ovf + 4 * s;
+      if (o[0] == (uint32_t)q0) err |= !lds_insert_rt(T, tb, o[1], o[2]);
+    }
+  __syncthreads();
+  const TieRule tr = tie_rule_of(a, a.front[i]);
+  const u64 best = block_max<256>(table_best_rt<256>(T, slots, threadIdx.x, tr), red);
+  for (int m = threadIdx.x; m < mc; m += 256) h.partbest[q0 + m] = m == 0 ? best : 0ull;
+  if constexpr (FEAT) {
+    __shared__ TabStats tred[4];
+    const TabStats t = group_stats<64>(table_stats_rt<256>(T, slots, threadIdx.x));
+    if ((threadIdx.x & 63) == 0) tred[threadIdx.x >> 6] = t;
+    __syncthreads();
+    for (int m = threadIdx.x; m < mc; m += 256) {
+      const TabStats z = m == 0 ? merge_stats(merge_stats(tred[0], tred[1]), merge_stats(tred[2], tred[3]))
+                                : TabStats{0u, 0u, 0};
+      h.part_w2[q0 + m] = z.w2;
+      h.part_nd[q0 + m] = z.nd;
+    }
+    if (threadIdx.x == 0) {
+      const uint32_t cur = (uint32_t)a.C[a.front[i]];
+      const int pc = (int)part_of(cur, pb);
+      if (pc >= mb && pc < mb + mc) h.own_w[i] = table_lookup_rt(T, tb, cur);
+    }
+  }
+  __syncthreads();
+  return err;
+}
+
+// One work item per aligned group of HUB_PART_GROUP partitions of a hub (all
+// of its partitions, if it has fewer).  A group whose partitions did not
+// spill and hold at most HUB_PART_GROUP_MAX pairs together - the usual case
+// once labels have merged - is merged in one table; otherwise each of its
+// partitions is merged on its own.
 template <bool FEAT>
 __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
-  constexpr int BITS = __builtin_ctz(HUB_PART_SLOTS);
+  static_assert(2 * HUB_PART_GROUP_MAX <= HUB_PART_SLOTS, "a merged group keeps its table at most half full");
   __shared__ u64 T[HUB_PART_SLOTS];
   __shared__ u64 red[4];
-  const u64 total = a.ctl->hub_parts;
+  const u64 total = a.ctl->hub_groups;
   const u64 nov = min(*h.ovf_count, (u64)HUB_OVERFLOW_CAP);
   int err = 0;
-  for (u64 q = blockIdx.x; q < total; q += gridDim.x) {
-    const int i = h.part_owner[q];
+  for (u64 gq = blockIdx.x; gq < total; gq += gridDim.x) {
+    const int i = h.group_owner[gq];
     const int k = h.ord[i];
-    const int p = (int)(q - h.pstart[i]);
-    int32_t *cnt = h.pcnt + h.cnt_base[k] + p;
-    const int reserved = *cnt;  // every pair offered to the partition, spilled ones included
-    const int n = min(reserved, h.part_cap);
-    const bool spilled = reserved > h.part_cap;
-    // a table just large enough to stay at most half full (partitions of
-    // later sweeps hold few labels); a partition that spilled takes the full
-    // table and merges its entries of the overflow area
-    int tb = 6;
-    while (tb < BITS && (1 << tb) < 2 * n) ++tb;
-    if (spilled) tb = BITS;
-    const int slots = 1 << tb;
-    for (int s = threadIdx.x; s < slots; s += 256) T[s] = EMPTY;
-    __syncthreads();
-    const u64 *src = h.pairs + h.pair_base[k] + (int64_t)p * HUB_PART_CAP;
-    constexpr int R = (HUB_PART_CAP + 255) / 256;
-    u64 x[R];
+    const int pb = h.pbits[k];
+    const int G = min(HUB_PART_GROUP, 1 << pb);
+    const int g0 = (int)(gq - h.gstart[i]) * G;  // first partition of the group
+    const int32_t *cnt = h.pcnt + h.cnt_base[k] + g0;
+    int cm[HUB_PART_GROUP];  // pairs offered to each partition, spilled ones included
+    int tot = 0;
+    bool any_spill = false;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int s = threadIdx.x + r * 256;
-      x[r] = s < n ? src[s] : EMPTY;
+    for (int m = 0; m < HUB_PART_GROUP; ++m) {
+      cm[m] = m < G ? cnt[m] : 0;
+      tot += cm[m];
+      any_spill |= cm[m] > h.part_cap;
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (x[r] != EMPTY) err |= !lds_insert_rt(T, tb, (uint32_t)(x[r] >> 32), (uint32_t)x[r]);
-    if (spilled)
-      for (u64 s = threadIdx.x; s < nov; s += 256) {
-        const uint32_t *o = h.ovf + 4 * s;
-        if (o[0] == (uint32_t)q) err |= !lds_insert_rt(T, tb, o[1], o[2]);
-      }
-    __syncthreads();
-    const TieRule tr = tie_rule_of(a, a.front[i]);
-    const u64 best = block_max<256>(table_best_rt<256>(T, slots, threadIdx.x, tr), red);
-    if (threadIdx.x == 0) {
-      h.partbest[q] = best;
-      *cnt = 0;  // partitions start empty at the next step
-    }
-    if constexpr (FEAT) {
-      __shared__ TabStats tred[4];
-      const TabStats t = group_stats<64>(table_stats_rt<256>(T, slots, threadIdx.x));
-      if ((threadIdx.x & 63) == 0) tred[threadIdx.x >> 6] = t;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        const TabStats m = merge_stats(merge_stats(tred[0], tred[1]), merge_stats(tred[2], tred[3]));
-        h.part_w2[q] = m.w2;
-        h.part_nd[q] = m.nd;
-        const uint32_t cur = (uint32_t)a.C[a.front[i]];
-        if ((int)part_of(cur, h.pbits[k]) == p) h.own_w[i] = table_lookup_rt(T, tb, cur);
+    if (!any_spill && tot <= HUB_PART_GROUP_MAX) {
+      err |= merge_parts<FEAT>(a, h, T, red, i, k, pb, g0, G, tot, false, cm, nov);
+    } else {
+      for (int m = 0; m < G; ++m) {
+        const int r = cnt[m];
+        err |= merge_parts<FEAT>(a, h, T, red, i, k, pb, g0 + m, 1, min(r, h.part_cap), r > h.part_cap, cm, nov);
       }
     }
-    __syncthreads();
   }
   if (err) atomicOr(&a.ctl->error, 16);
 }
@@ -272,8 +343,12 @@ __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
     const int v = a.front[i];
     const int P = 1 << h.pbits[h.ord[i]];
     const u64 *pb = h.partbest + h.pstart[i];
+    int32_t *cnt = h.pcnt + h.cnt_base[h.ord[i]];
     u64 best = 0;
-    for (int p = lane; p < P; p += 64) best = pb[p] > best ? pb[p] : best;
+    for (int p = lane; p < P; p += 64) {
+      best = pb[p] > best ? pb[p] : best;
+      cnt[p] = 0;  // partitions start empty at the next step
+    }
     best = group_max<64>(best);
     int changed = 0;
     const int32_t cur = a.C[v];
@@ -336,10 +411,9 @@ void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, hipStream_
 }
 
 void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h) {
-  const size_t lds = sizeof(int32_t) * (2u << std::min(h.max_pbits, HUB_LDS_PBITS));
-  if (wk == W_UNIT) hipLaunchKernelGGL(k_hub_chunk<W_UNIT>, dim3(blocks), dim3(256), lds, st, a, h);
-  else if (wk == W_U8) hipLaunchKernelGGL(k_hub_chunk<W_U8>, dim3(blocks), dim3(256), lds, st, a, h);
-  else hipLaunchKernelGGL(k_hub_chunk<W_U32>, dim3(blocks), dim3(256), lds, st, a, h);
+  if (wk == W_UNIT) hipLaunchKernelGGL(k_hub_chunk<W_UNIT>, dim3(blocks), dim3(256), 0, st, a, h);
+  else if (wk == W_U8) hipLaunchKernelGGL(k_hub_chunk<W_U8>, dim3(blocks), dim3(256), 0, st, a, h);
+  else hipLaunchKernelGGL(k_hub_chunk<W_U32>, dim3(blocks), dim3(256), 0, st, a, h);
 }
 
 void launch_hub_part(int blocks, bool feat, hipStream_t st, const ScanArgs &a, const HubArgs &h) {

@@ -57,7 +57,7 @@ __global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int6
     ctl->tau = tau;
     ctl->n = n;
     ctl->changed = ctl->processed = ctl->scanned = ctl->gated = 0;
-    ctl->hub_chunks = ctl->hub_parts = 0;
+    ctl->hub_chunks = ctl->hub_groups = 0;
     ctl->verify_changed = ctl->total_changed = ctl->verify_scanned = 0;
     for (int k = 0; k < MAX_REC; ++k)
       ctl->st_changed[k] = ctl->st_processed[k] = ctl->st_scanned[k] = ctl->st_gated[k] = ctl->t_sweep[k] = 0;
