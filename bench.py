@@ -42,11 +42,11 @@ def library_digest():
 
 
 DEFAULT_BINS = [4, 16, 64, 256, 1024, 4096]  # the library's default degree limits of bins 0-5
-DEFAULT_CONFIG = {"variants": [0] * 6, "schedule": [16, 2, 4], "bins": DEFAULT_BINS, "hubs_last": 0}
+DEFAULT_CONFIG = {"variants": [0] * 6, "schedule": [16, 2, 4], "bins": DEFAULT_BINS, "hubs_last": 0, "snapshot": 0}
 
 
 def profiled_config(workload):
-    """The configuration (variants, schedule, bins, hubs_last) the committed byte
+    """The configuration (variants, schedule, bins, hubs_last, snapshot) the committed byte
     counters were taken with, when the library sources still match them; else None."""
     try:
         for line in (ROOT / "profiles" / f"{workload}_async_hbm_traffic.md").read_text().splitlines():
@@ -54,13 +54,13 @@ def profiled_config(workload):
                 d = json.loads(line[len("machine-readable: "):])
                 if d.get("sources") == library_digest():
                     return {"variants": d["variants"], "schedule": d["schedule"], "bins": d.get("bins", DEFAULT_BINS),
-                            "hubs_last": d.get("hubs_last", 0)}
+                            "hubs_last": d.get("hubs_last", 0), "snapshot": d.get("snapshot", 0)}
     except OSError:
         pass
     return None
 
 
-CONFIG_KEYS = ("variants", "schedule", "bins", "hubs_last")
+CONFIG_KEYS = ("variants", "schedule", "bins", "hubs_last", "snapshot")
 
 
 def same_config(a, b):
@@ -95,7 +95,9 @@ def kernel_bytes(st):
     own label 4; per stored entry: index 4 + weight (packed size) + gathered
     neighbour label 4; per changed vertex: label write 4; per neighbour mark 1.
     Compaction: list entry 4 + flag 1 per listed vertex, flag clear 1 +
-    frontier write 4 per taken vertex.
+    frontier write 4 per taken vertex.  Snapshot first sweep ("first"): as a
+    scan kernel, except that a neighbour id (4) is read only where the kernel
+    read one.
     """
     wb = st["weight_bytes"]
     out = {}
@@ -104,6 +106,8 @@ def kernel_bytes(st):
                st["bin_marks"][b])
         out["hub_chunk" if b == 6 else f"bin{b}"] = byt
     out["compact"] = st["compact_listed"] * 5 + st["compact_taken"] * 5
+    out["first"] = (st.get("first_vertices", 0) * 16 + st.get("first_edges", 0) * (4 + wb) +
+                    st.get("first_reads", 0) * 4 + st.get("first_changed", 0) * 4 + st.get("first_marks", 0))
     return out
 
 
@@ -312,6 +316,7 @@ def _apply(G, cfg):
     G.set_async_schedule(*cfg["schedule"])
     G.set_bins(cfg["bins"])
     G.set_bin_order(cfg.get("hubs_last", 0))
+    G.set_first_sweep(cfg.get("snapshot", 0))
 
 
 def tune_async(args, G, workload):
@@ -320,11 +325,12 @@ def tune_async(args, G, workload):
     configuration the committed byte counters of this workload were taken
     with, that one is timed instead so the counters apply."""
     from paper_2312_08140_amd import abi
-    if args.variants or args.schedule or args.bins or args.hubs_last:
+    if args.variants or args.schedule or args.bins or args.hubs_last or args.snapshot:
         v = [int(x) for x in args.variants.split(",")] if args.variants else [0] * 6
         s = [int(x) for x in args.schedule.split(",")] if args.schedule else [16, 2, 4]
         lim = [int(x) for x in args.bins.split(",")] if args.bins else list(DEFAULT_BINS)
-        tuned = {"variants": v, "schedule": s, "bins": lim, "hubs_last": int(args.hubs_last), "seconds": 0.0,
+        tuned = {"variants": v, "schedule": s, "bins": lim, "hubs_last": int(args.hubs_last),
+                 "snapshot": int(args.snapshot), "seconds": 0.0,
                  "given": True}
         _apply(G, tuned)
         return tuned
@@ -333,7 +339,8 @@ def tune_async(args, G, workload):
     t = time.time()
     variants, bin_ms, sched, lim = G.autotune(args.tau, args.max_iters, abi.LPA_MODE_ASYNC)
     tuned = {"variants": [int(v) for v in variants], "schedule": list(sched), "bins": list(lim),
-             "hubs_last": G.schedule()[4], "seconds": round(time.time() - t, 2), "source": "autotune"}
+             "hubs_last": G.schedule()[4], "snapshot": G.schedule()[5], "seconds": round(time.time() - t, 2),
+             "source": "autotune"}
     prof = profiled_config(workload)
     if prof is not None and not same_config(prof, tuned):
         tuned["autotune_pick"] = {k: tuned[k] for k in CONFIG_KEYS}
@@ -456,7 +463,8 @@ def secondary_rmat(args):
     wl = f"rmat{args.secondary_scale}"
     res = {"workload": f"rmat{args.secondary_scale}_ef{args.secondary_edge_factor}_w1-8_seed{args.seed}", "n": d.n,
            "m": d.m, "generate_and_create_s": round(time.time() - t, 2)}
-    sub = argparse.Namespace(**{**vars(args), "variants": None, "schedule": None, "bins": None, "hubs_last": 0})
+    sub = argparse.Namespace(**{**vars(args), "variants": None, "schedule": None, "bins": None, "hubs_last": 0,
+                                "snapshot": 0})
     tuned = tune_async(sub, G, wl)
     out = torch.empty(d.n, dtype=torch.int32, device="cuda:0")
     runs, wall = timed_async(G, args, out, 10, 2)
@@ -584,6 +592,8 @@ def main():
     ap.add_argument("--schedule", default=None,
                     help="asynchronous schedule early_steps,early_sweeps,late_steps (instead of autotuning)")
     ap.add_argument("--hubs-last", type=int, default=0, help="with the options above: the hub bin runs last (1)")
+    ap.add_argument("--snapshot", type=int, default=0,
+                    help="with the options above: the first sweep reads a snapshot of the initial labels (1)")
     ap.add_argument("--no-gate", action="store_true", help="skip the plain-vs-gated comparison")
     ap.add_argument("--batch", type=int, default=4096,
                     help="batched workload of this many uneven SBMs (4096 = the benchmark batch; 0: skip)")

@@ -106,7 +106,8 @@ typedef struct {
   double setup_ms;                                /* one-off work done by this call (colouring, capture) */
   /* LPA_FLAG_KERNEL_TIMING: summed HIP-event time and launch count per kernel kind:
      0 compaction, 1..6 degree bins 0..5, 7..9 hub plan/scan/finish, 10 end of sweep,
-     11 hub partition merge, 12 other, 13 gate decisions */
+     11 hub partition merge, 12 other, 13 gate decisions, 14 scan kernels of a snapshot
+     first sweep (lpa_set_first_sweep; bins and hub chunks) */
   double kernel_ms[LPA_NUM_TIMED_KERNELS];
   int64_t kernel_launches[LPA_NUM_TIMED_KERNELS];
   /* run totals per degree bin (bin 6 = hubs): vertices processed, stored entries
@@ -119,6 +120,10 @@ typedef struct {
   int32_t weight_bytes;
   int32_t reserved;
   int64_t verify_edges_scanned;  /* stored entries scanned by the verification sweep(s) */
+  /* snapshot first sweep (lpa_set_first_sweep), when it ran: vertices processed,
+     stored entries scanned, labels changed and neighbour marks written by its
+     kernels, and neighbour ids they read (counted in none of the bin totals) */
+  int64_t first_vertices, first_edges, first_changed, first_marks, first_reads;
 } lpa_stats;
 
 /*
@@ -197,7 +202,10 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
  * converge (a batch: every graph) and whose modularity stays within 0.002 of
  * the first's; the first stays when no other qualifies (schedule_out: int32[3],
  * may be NULL); then, on a graph with hubs, whether the hub bin runs last in
- * each step (lpa_set_bin_order; read it back with lpa_get_schedule).  Then the
+ * each step (lpa_set_bin_order), and, where the rows allow it, how many
+ * kernels of each step of the first sweep read the initial labels (none, 1,
+ * 2, 3 or all; lpa_set_first_sweep; read both back with lpa_get_schedule).
+ * Then the
  * degree limits of the bins (lpa_set_bins): each
  * bin's LDS table has a fixed size (8, 32, 128, 512, 2048, 8192 slots), and
  * the candidates let it fill to at most 1/2 (the default), 1/4, 3/4 or all of
@@ -257,9 +265,31 @@ int lpa_set_bin_order(lpa_graph *g, int32_t hubs_last);
 int lpa_set_bins(lpa_graph *g, const int32_t *max_degree, int32_t count);
 
 /*
+ * lpa_set_first_sweep - snapshot first sweep (asynchronous mode): in the
+ * first sweep of a run that starts from the initial labels (no init_labels),
+ * the first `kernels` kernels of every step - in processing order, one per
+ * degree bin and one for the hubs (lpa_set_bin_order) - read every label as
+ * it was when the sweep began, which is one interleaving of an asynchronous
+ * sweep (Section 4.1): their reads precede the writes of the sweep.  Those
+ * labels are the vertex ids (Algorithm 1 starts from C[v] = v) and each occurs
+ * once in a row without repeated neighbours, so Eq. (2) becomes the heaviest
+ * entry (smallest id, or rank in non-strict LPA, among the heaviest): these
+ * kernels need no label table and read a neighbour's id only for entries of
+ * the running maximum weight.  kernels: 0 (the default) to 7 (every kernel of
+ * the sweep); other values give LPA_ERR_INVALID_ARG.  Applies only when
+ * every row's neighbours are strictly increasing (lpa_get_schedule reports
+ * it) and no gate or trace is on; otherwise the first sweep runs like the
+ * others.  Deterministic runs never use it.  Takes effect for the next
+ * lpa_run.
+ */
+int lpa_set_first_sweep(lpa_graph *g, int32_t kernels);
+
+/*
  * lpa_get_schedule - the handle's current asynchronous configuration, as
- * lpa_autotune leaves it: out int32[5] = early steps, early sweeps, late
- * steps, steps by colour (1) or by hash (0), hubs last (1) or first (0).
+ * lpa_autotune leaves it: out int32[7] = early steps, early sweeps, late
+ * steps, steps by colour (1) or by hash (0), hubs last (1) or first (0),
+ * kernels of the snapshot first sweep (lpa_set_first_sweep), and whether the
+ * rows allow it (1: every row's neighbours strictly increase).
  */
 int lpa_get_schedule(const lpa_graph *g, int32_t *out);
 

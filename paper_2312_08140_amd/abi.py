@@ -52,7 +52,7 @@ GATE_NOALLOC_MAX_SAMPLES = 262144
 MAX_SWEEPS_RECORDED = 64
 NUM_TIMED_KERNELS = 16
 KERNEL_NAMES = ["compact", "bin0", "bin1", "bin2", "bin3", "bin4", "bin5", "hub_plan", "hub_chunk", "hub_finish",
-                "end_sweep", "hub_part", "other", "gate_pass", "k14", "k15"]
+                "end_sweep", "hub_part", "other", "gate_pass", "first", "k15"]
 
 
 class lpa_stats(ctypes.Structure):
@@ -81,6 +81,11 @@ class lpa_stats(ctypes.Structure):
         ("weight_bytes", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("verify_edges_scanned", ctypes.c_int64),
+        ("first_vertices", ctypes.c_int64),
+        ("first_edges", ctypes.c_int64),
+        ("first_changed", ctypes.c_int64),
+        ("first_marks", ctypes.c_int64),
+        ("first_reads", ctypes.c_int64),
     ]
 
     def to_dict(self) -> dict:
@@ -98,6 +103,8 @@ class lpa_stats(ctypes.Structure):
             bin_changed=list(self.bin_changed[:7]), bin_marks=list(self.bin_marks[:7]),
             compact_listed=self.compact_listed, compact_taken=self.compact_taken, weight_bytes=self.weight_bytes,
             verify_edges_scanned=self.verify_edges_scanned,
+            first_vertices=self.first_vertices, first_edges=self.first_edges, first_changed=self.first_changed,
+            first_marks=self.first_marks, first_reads=self.first_reads,
         )
 
 
@@ -118,6 +125,7 @@ SIGNATURES = {
     "lpa_set_async_schedule": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32]),
     "lpa_set_variants": (ctypes.c_int, [_vp, _vp, _i32]),
     "lpa_set_bin_order": (ctypes.c_int, [_vp, _i32]),
+    "lpa_set_first_sweep": (ctypes.c_int, [_vp, _i32]),
     "lpa_get_schedule": (ctypes.c_int, [_vp, _vp]),
     "lpa_autotune": (ctypes.c_int, [_vp, _f64, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "lpa_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_uint]),
@@ -236,6 +244,10 @@ def lpa_set_async_schedule(handle, early_phases, early_sweeps, late_phases, by_c
 
 def lpa_set_bin_order(handle, hubs_last):
     return load().lpa_set_bin_order(handle, int(hubs_last))
+
+
+def lpa_set_first_sweep(handle, kernels):
+    return load().lpa_set_first_sweep(handle, int(kernels))
 
 
 def lpa_get_schedule(handle, out):
@@ -434,9 +446,14 @@ class LPAGraph:
     def set_bin_order(self, hubs_last):
         _check(lpa_set_bin_order(self.handle, hubs_last), "lpa_set_bin_order")
 
+    def set_first_sweep(self, kernels):
+        """Kernels of each step of the first sweep that read the initial labels (0-7)."""
+        _check(lpa_set_first_sweep(self.handle, kernels), "lpa_set_first_sweep")
+
     def schedule(self):
-        """(early steps, early sweeps, late steps, by colour, hubs last) of the handle."""
-        out = np.zeros(5, np.int32)
+        """(early steps, early sweeps, late steps, by colour, hubs last, snapshot kernels of the first sweep,
+        rows allow it) of the handle."""
+        out = np.zeros(7, np.int32)
         _check(lpa_get_schedule(self.handle, out), "lpa_get_schedule")
         return tuple(int(x) for x in out)
 

@@ -171,9 +171,14 @@ constexpr int MAX_REC = 64;
 // 64-byte line per copy and slot) rather than into one address: thousands of
 // workgroups adding to a single counter serialise on it.  Slots 0..NBINS-1
 // belong to the scan kernels of a bin (changed, scanned entries, vertices,
-// marks), slot NBINS to the compaction (processed, gated, listed, unused).
+// marks), slot NBINS to the compaction (processed, gated, listed, unused),
+// FIRST_SLOT to the kernels of a snapshot first sweep (changed, scanned
+// entries, vertices, marks) and READS_SLOT to the neighbour ids they read.
 // k_end_sweep folds and clears them.
 constexpr int NSHARD = 64;
+constexpr int FIRST_SLOT = NBINS + 1;
+constexpr int READS_SLOT = NBINS + 2;
+constexpr int NSLOT = NBINS + 3;
 struct alignas(64) Shard {
   u64 c[4];
   u64 pad[4];
@@ -208,7 +213,9 @@ struct Ctl {
   // run totals per bin (byte accounting of the kernels)
   u64 bin_vertices[NBINS], bin_edges[NBINS], bin_changed[NBINS], bin_marks[NBINS];
   u64 compact_listed, compact_taken;
-  Shard shard[NSHARD][NBINS + 1];
+  // run totals of the snapshot first sweep's kernels
+  u64 first_vertices, first_edges, first_changed, first_marks, first_reads;
+  Shard shard[NSHARD][NSLOT];
 };
 
 // ---------------------------------------------------------------- gate
@@ -305,6 +312,7 @@ struct HubArgs {
   uint32_t *part_w2;         // FEAT: second largest label weight of each partition
   int32_t *part_nd;          // FEAT: distinct labels of each partition
   uint32_t *own_w;           // FEAT: per frontier entry, weight of the hub's own label
+  int32_t first;             // snapshot first sweep: k_hub_owner zeroes the partition maxima
 };
 
 // Wave64 helpers.

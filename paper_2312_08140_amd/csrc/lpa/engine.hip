@@ -50,7 +50,8 @@ enum TimedKind {
   TK_END_SWEEP = 10,
   TK_HUB_PART = 11,
   TK_OTHER = 12,
-  TK_GATE = 13
+  TK_GATE = 13,
+  TK_FIRST = 14  // scan kernels of a snapshot first sweep (bins and hub chunks)
 };
 
 }  // namespace
@@ -87,6 +88,9 @@ struct lpa_graph {
   int early_sweeps = 2;
   bool async_by_colour = true;      // steps made of consecutive colour classes (else a hash of the id)
   bool hubs_last = false;           // a step runs the hub bin after the others (else first)
+  int32_t snapshot_kernels = 0;     // leading kernels of each step of a run's first sweep that read the
+                                    // initial labels (snapshot first sweep; 0 = none, NBINS = all)
+  bool rows_strict = false;         // every row's neighbours strictly increase (no repeated neighbour)
   // deterministic schedule
   int32_t *color = nullptr;
   int32_t ncol = 0;
@@ -629,7 +633,7 @@ ScanArgs base_args(lpa_graph *g, int prune) {
 // One step: compact the flagged vertices of `list` (bin segments given by
 // absolute `bounds` into list/front), then process the bins, hubs first.
 void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t *bounds, int32_t *fcount, int prune,
-               int64_t hub_chunks, int64_t hub_parts) {
+               int64_t hub_chunks, int64_t hub_parts, int snap_kernels = 0) {
   const int64_t base = bounds[0];
   const int64_t len = bounds[NBINS] - base;
   if (len <= 0) return;
@@ -655,11 +659,27 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
     const int b = !g->hubs_last ? NBINS - 1 - k : (k < NBINS - 1 ? NBINS - 2 - k : HUB_BIN);
     const int64_t seg = bounds[b + 1] - bounds[b];
     if (seg <= 0) continue;
+    const bool first = k < snap_kernels;  // this kernel reads the initial labels
     ScanArgs a = base_args(g, prune);
     a.bin = b;
     a.front = g->front + bounds[b];
     a.fcount = fcount + b;
-    if (b == HUB_BIN) {
+    if (b == HUB_BIN && first) {
+      // snapshot first sweep: one best key per chunk, maximum per hub
+      HubArgs h = hub_args(g);
+      h.first = 1;
+      tk_begin(g, st);
+      launch_hub_plan(a, h, grid_cap(seg, 1, max_blocks), st);
+      tk_end(g, st, TK_HUB_PLAN);
+      tk_begin(g, st);
+      launch_hub_first_chunk(g->wk, grid_cap(hub_chunks, 1, max_blocks * 2), st, a, h);
+      tk_end(g, st, TK_FIRST);
+      a.bin = FIRST_SLOT;
+      tk_begin(g, st);
+      launch_hub_finish(grid_cap(seg, 4, max_blocks), grid_cap(hub_chunks, 1, max_blocks * 2), prune, false, st, a,
+                        h);
+      tk_end(g, st, TK_HUB_FINISH);
+    } else if (b == HUB_BIN) {
       const HubArgs h = hub_args(g);
       tk_begin(g, st);
       launch_hub_plan(a, h, grid_cap(seg, 1, max_blocks), st);
@@ -674,6 +694,11 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
       launch_hub_finish(grid_cap(seg, 4, max_blocks), grid_cap(hub_chunks, 1, max_blocks * 2), prune, g->feat_on, st,
                         a, h);
       tk_end(g, st, TK_HUB_FINISH);
+    } else if (first) {
+      const int per_block = bin_vertices_per_block(b, g->variant[b]);
+      tk_begin(g, st);
+      launch_first_bin(b, g->variant[b], g->wk, grid_cap(seg, per_block, max_blocks), st, a);
+      tk_end(g, st, TK_FIRST);
     } else {
       const int per_block = bin_vertices_per_block(b, g->variant[b]);
       tk_begin(g, st);
@@ -683,7 +708,10 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
   }
 }
 
-void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late) {
+// snap_kernels: leading kernels of every step that read the initial labels
+// (a run's first sweep in the asynchronous mode; the caller checks that the
+// run starts from the initial labels and that the rows allow it).
+void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late, int snap_kernels = 0) {
   if (g->gate_active) {
     tk_begin(g, st);
     launch_gate_pass(g->ctl, g->gate_f, g->gate_z, g->cur_feat, g->F, g->gskip, g->n, g->cu_count, st);
@@ -697,7 +725,7 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late) {
     const lpa_graph::AsyncSched &sc = async_sched(g, late);
     for (int ph = 0; ph < sc.nphase; ++ph)
       emit_step(g, st, sc.list, &sc.start[(size_t)ph * NBINS], g->fcount + (size_t)ph * NBINS, prune,
-                sc.hub_chunks[ph], sc.hub_parts[ph]);
+                sc.hub_chunks[ph], sc.hub_parts[ph], snap_kernels);
   }
   const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : max_phases(g) * NBINS;
   tk_begin(g, st);
@@ -711,7 +739,8 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late) {
 // once after the stop test holds), captured once per (mode, prune, sweeps).
 // A graph of `sweeps` consecutive sweeps starting at sweep `first` (which
 // selects the asynchronous schedule of each).
-hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps, int first, int verify = 0) {
+hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps, int first, int verify = 0,
+                           int snap = 0) {
   // captured kernels embed the feature arguments (trace switch, sweep cap)
   const int fcode = g->feat_on ? 1 + 2 * g->cur_feat.trace + 4 * g->gate_active + 8 * g->cur_feat.max_iters : 0;
   // only the early/late split of the covered sweeps matters
@@ -719,13 +748,15 @@ hipGraphExec_t sweep_graph(lpa_graph *g, int mode, int prune, int sweeps, int fi
                    : verify                       ? 2
                    : sweeps == 1                  ? (first >= g->early_sweeps ? 1 : 0)
                                                   : 3 + std::min(first, g->early_sweeps);
-  auto key = std::make_tuple(mode, prune, sweeps, fcode, fkey + (g->nonstrict ? 1000 : 0) + (g->hubs_last ? 2000 : 0));
+  if (first != 0 || verify) snap = 0;
+  auto key = std::make_tuple(mode, prune, sweeps, fcode,
+                             fkey + (g->nonstrict ? 1000 : 0) + (g->hubs_last ? 2000 : 0) + 4000 * snap);
   auto it = g->graphs.find(key);
   if (it != g->graphs.end()) return it->second;
   hipGraph_t graph = nullptr;
   HIP_OK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
   for (int s = 0; s < sweeps; ++s)
-    emit_sweep(g, g->cap_stream, mode, prune, verify ? 2 : (first + s >= g->early_sweeps ? 1 : 0));
+    emit_sweep(g, g->cap_stream, mode, prune, verify ? 2 : (first + s >= g->early_sweeps ? 1 : 0), s == 0 ? snap : 0);
   HIP_OK(hipStreamEndCapture(g->cap_stream, &graph));
   hipGraphExec_t exec = nullptr;
   hipError_t e = hipGraphInstantiateWithFlags(&exec, graph, 0);
@@ -1014,6 +1045,7 @@ static int create_graph(lpa_graph **out, int64_t n, int64_t m, const int64_t *of
     }
     g->K = dalloc_n<uint32_t>(g, n);
     launch_weighted_degree(g->off, g->w, g->wk, n, g->K, chk, g->stream);
+    if (n) launch_check_rows(g->off, g->idx, n, chk, g->stream);
     const bool dev_sym = dev && (flags & LPA_FLAG_CHECK_SYMMETRIC);
     if (dev_sym) launch_check_symmetric(g->off, g->idx, g->w, g->wk, n, chk, g->stream);
     u64 sums[2] = {0, 0};
@@ -1021,6 +1053,7 @@ static int create_graph(lpa_graph **out, int64_t n, int64_t m, const int64_t *of
     HIP_OK(hipMemcpyAsync(sums, (u64 *)(chk + 1), sizeof(sums), hipMemcpyDeviceToHost, g->stream));
     HIP_OK(hipStreamSynchronize(g->stream));
     if (h.big_degree) return LPA_ERR_TOO_LARGE;
+    g->rows_strict = !h.rows_not_strict;
     if (dev_sym && sums[0] != sums[1]) return LPA_ERR_INVALID_CSR;
     int64_t act = 0;
     for (int64_t v = 0; v < n; ++v) act += g->h_off[v + 1] > g->h_off[v];
@@ -1221,6 +1254,9 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
   double q_ref = 0.0;
   bool have_ref = false;
   auto quality_ok = [&](double q) { return !have_ref || q >= q_ref - 0.002; };
+  // the reference runs read labels as the schedule delivers them
+  rc = lpa_set_first_sweep(g, 0);
+  if (rc != LPA_OK) return rc;
   // 1. Asynchronous schedule: the fastest candidate whose runs converge (for
   //    a batch: every graph) and whose modularity stays within 0.002 of the
   //    all-16-step schedule's.
@@ -1273,7 +1309,38 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
       }
       rc = lpa_modularity(g, nullptr, 0, &q);
       if (rc != LPA_OK) return rc;
-      if (!(converged && quality_ok(q) && ms < 0.97 * best_ms)) rc = lpa_set_bin_order(g, 0);
+      if (converged && quality_ok(q) && ms < 0.97 * best_ms) best_ms = ms;
+      else rc = lpa_set_bin_order(g, 0);
+      if (rc != LPA_OK) return rc;
+    }
+    // 1c. The snapshot first sweep (lpa_set_first_sweep), where the rows
+    //     allow it: the first 1, 2, 3 or all kernels of each step of the first
+    //     sweep read the initial labels.  Reading them is cheap (no table,
+    //     few reads), but a sweep whose vertices all read them merges fewer
+    //     labels, which can cost a sweep later on.  Same acceptance rules.
+    if (g->rows_strict) {
+      static const int32_t snap_cand[] = {1, 2, 3, NBINS};
+      int32_t best_snap = 0;
+      for (int32_t c : snap_cand) {
+        rc = lpa_set_first_sweep(g, c);
+        if (rc != LPA_OK) return rc;
+        double ms = 1e300, q = 0.0;
+        bool converged = true;
+        for (int rep = 0; rep < 2; ++rep) {
+          lpa_stats st;
+          rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
+          if (rc != LPA_OK) return rc;
+          ms = std::min(ms, st.total_ms);
+          converged = converged && st.converged;
+        }
+        rc = lpa_modularity(g, nullptr, 0, &q);
+        if (rc != LPA_OK) return rc;
+        if (converged && quality_ok(q) && ms < 0.97 * best_ms) {
+          best_ms = ms;
+          best_snap = c;
+        }
+      }
+      rc = lpa_set_first_sweep(g, best_snap);
       if (rc != LPA_OK) return rc;
     }
   } else if (schedule_out) {
@@ -1410,6 +1477,14 @@ int lpa_set_bin_order(lpa_graph *g, int32_t hubs_last) {
   });
 }
 
+int lpa_set_first_sweep(lpa_graph *g, int32_t kernels) {
+  return run_guarded(g, [&]() -> int {
+    if (kernels < 0 || kernels > NBINS) return LPA_ERR_INVALID_ARG;
+    g->snapshot_kernels = kernels;
+    return LPA_OK;
+  });
+}
+
 int lpa_get_schedule(const lpa_graph *gc, int32_t *out) {
   if (!gc || !out) return LPA_ERR_INVALID_ARG;
   out[0] = gc->sched[0].nphase;
@@ -1417,6 +1492,8 @@ int lpa_get_schedule(const lpa_graph *gc, int32_t *out) {
   out[2] = gc->sched[1].nphase;
   out[3] = gc->async_by_colour ? 1 : 0;
   out[4] = gc->hubs_last ? 1 : 0;
+  out[5] = gc->snapshot_kernels;
+  out[6] = gc->rows_strict ? 1 : 0;
   return LPA_OK;
 }
 
@@ -1487,16 +1564,22 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       launch_feat_reset(g->feat, g->n, g->stream);
     }
     g->cur_feat = feat_args(g, max_iters, trace);
+    // snapshot first sweep: asynchronous runs from the initial labels over
+    // rows without repeated neighbours (no gate features to write)
+    const int snap =
+        mode == LPA_MODE_ASYNC && g->rows_strict && !init_labels && !g->feat_on ? g->snapshot_kernels : 0;
     // per-sweep graphs of the early and the late asynchronous schedule
-    hipGraphExec_t exec = nullptr, exec_late = nullptr;
+    hipGraphExec_t exec = nullptr, exec_late = nullptr, exec_first = nullptr;
     if (use_graph && max_iters > 0) {
-      exec = sweep_graph(g, mode, prune, one_launch ? max_iters : 1, 0);
+      exec = sweep_graph(g, mode, prune, one_launch ? max_iters : 1, 0, 0, one_launch ? snap : 0);
       exec_late = one_launch ? exec : sweep_graph(g, mode, prune, 1, g->early_sweeps);
+      if (snap && !one_launch) exec_first = sweep_graph(g, mode, prune, 1, 0, 0, snap);
     }
     auto launch_sweep = [&](int s) {
       const int late = s >= g->early_sweeps;
-      if (exec) HIP_OK(hipGraphLaunch(late ? exec_late : exec, g->stream));
-      else emit_sweep(g, g->stream, mode, prune, late ? 1 : 0);
+      const bool first = snap && s == 0;
+      if (exec) HIP_OK(hipGraphLaunch(first ? exec_first : late ? exec_late : exec, g->stream));
+      else emit_sweep(g, g->stream, mode, prune, late ? 1 : 0, first ? snap : 0);
     };
     HIP_OK(hipEventRecord(e1, g->stream));
     HIP_OK(hipEventSynchronize(e1));
@@ -1601,6 +1684,11 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       }
       stats->compact_listed = (int64_t)h.compact_listed;
       stats->compact_taken = (int64_t)h.compact_taken;
+      stats->first_vertices = (int64_t)h.first_vertices;
+      stats->first_edges = (int64_t)h.first_edges;
+      stats->first_changed = (int64_t)h.first_changed;
+      stats->first_marks = (int64_t)h.first_marks;
+      stats->first_reads = (int64_t)h.first_reads;
       stats->weight_bytes = g->wk == W_UNIT ? 0 : (g->wk == W_U8 ? 1 : 4);
       if (timing) {
         for (size_t k = 0; k < g->ev_used; ++k) {

@@ -112,6 +112,8 @@ __global__ __launch_bounds__(256) void k_hub_owner(ScanArgs a, HubArgs h) {
     const u64 c0 = h.cstart[i], g0 = h.gstart[i];
     for (int c = threadIdx.x; c < kc; c += 256) h.chunk_owner[c0 + c] = i;
     for (int gq = threadIdx.x; gq < kg; gq += 256) h.group_owner[g0 + gq] = i;
+    if (h.first)
+      for (int p = threadIdx.x; p < (1 << h.pbits[k]); p += 256) h.partbest[h.pstart[i] + p] = 0;
   }
 }
 
@@ -212,14 +214,14 @@ __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
 // Merges partitions [mb, mb + mc) of frontier hub i (ordinal k) in one LDS
 // table and stores the best key of the union in the first partition's slot
 // (zero in the others).  Partitions hold disjoint label sets, so the best of
-// the union is the best of the partitions.  n pairs in all; cm[m] pairs in
-// partition mb + m when mc > 1 (a merge of several partitions never includes
-// one that spilled); a single partition that spilled also merges its
+// the union is the best of the partitions.  n pairs in all; cm[m] (in LDS)
+// pairs in partition mb + m when mc > 1 (a merge of several partitions never
+// includes one that spilled); a single partition that spilled also merges its
 // entries of the overflow area.
 template <bool FEAT>
 __device__ __forceinline__ int merge_parts(const ScanArgs &a, const HubArgs &h, u64 *T, u64 *red, int i, int k,
-                                           int pb, int mb, int mc, int n, bool spilled,
-                                           const int (&cm)[HUB_PART_GROUP], u64 nov) {
+                                           int pb, int mb, int mc, int n, bool spilled, const int *cm,
+                                           u64 nov) {
   constexpr int BITS = __builtin_ctz(HUB_PART_SLOTS);
   int err = 0;
   const u64 q0 = h.pstart[i] + (u64)mb;  // step-wide id of the first partition
@@ -244,13 +246,9 @@ __device__ __forceinline__ int merge_parts(const ScanArgs &a, const HubArgs &h, 
     if (f < n) {
       int64_t at = f;
       if (mc > 1) {
-        int base = 0;
-        at = -1;
-#pragma unroll
-        for (int m = 0; m < HUB_PART_GROUP; ++m) {
-          if (at < 0 && f < base + cm[m]) at = (int64_t)m * HUB_PART_CAP + (f - base);
-          base += cm[m];
-        }
+        int m = 0, base = 0;
+        while (f >= base + cm[m]) base += cm[m++];
+        at = (int64_t)m * HUB_PART_CAP + (f - base);
       }
       x[r] = src[at];
     }
@@ -289,16 +287,18 @@ __device__ __forceinline__ int merge_parts(const ScanArgs &a, const HubArgs &h, 
 }
 
 // One work item per aligned group of HUB_PART_GROUP partitions of a hub (all
-// of its partitions, if it has fewer).  A group whose partitions did not
-// spill and hold at most HUB_PART_GROUP_MAX pairs together - the usual case
-// once labels have merged - is merged in one table; otherwise each of its
-// partitions is merged on its own.
+// of its partitions, if it has fewer).  Consecutive partitions that did not
+// spill are merged together while their pairs stay within
+// HUB_PART_GROUP_MAX (once labels have merged, usually the whole group in one
+// table); a partition that spilled is merged on its own.
 template <bool FEAT>
 __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
-  static_assert(2 * HUB_PART_GROUP_MAX <= HUB_PART_SLOTS, "a merged group keeps its table at most half full");
+  static_assert(2 * HUB_PART_GROUP_MAX <= HUB_PART_SLOTS, "a merged batch keeps its table at most half full");
+  static_assert(HUB_PART_GROUP_MAX <= HUB_PART_CAP, "a batch's pairs fit the per-thread load registers");
   __shared__ u64 T[HUB_PART_SLOTS];
   __shared__ u64 red[4];
+  __shared__ int s_cm[HUB_PART_GROUP];  // pairs offered to each partition of the group, spilled ones included
   const u64 total = a.ctl->hub_groups;
   const u64 nov = min(*h.ovf_count, (u64)HUB_OVERFLOW_CAP);
   int err = 0;
@@ -308,23 +308,15 @@ __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
     const int pb = h.pbits[k];
     const int G = min(HUB_PART_GROUP, 1 << pb);
     const int g0 = (int)(gq - h.gstart[i]) * G;  // first partition of the group
-    const int32_t *cnt = h.pcnt + h.cnt_base[k] + g0;
-    int cm[HUB_PART_GROUP];  // pairs offered to each partition, spilled ones included
-    int tot = 0;
-    bool any_spill = false;
-#pragma unroll
-    for (int m = 0; m < HUB_PART_GROUP; ++m) {
-      cm[m] = m < G ? cnt[m] : 0;
-      tot += cm[m];
-      any_spill |= cm[m] > h.part_cap;
-    }
-    if (!any_spill && tot <= HUB_PART_GROUP_MAX) {
-      err |= merge_parts<FEAT>(a, h, T, red, i, k, pb, g0, G, tot, false, cm, nov);
-    } else {
-      for (int m = 0; m < G; ++m) {
-        const int r = cnt[m];
-        err |= merge_parts<FEAT>(a, h, T, red, i, k, pb, g0 + m, 1, min(r, h.part_cap), r > h.part_cap, cm, nov);
-      }
+    if ((int)threadIdx.x < G) s_cm[threadIdx.x] = h.pcnt[h.cnt_base[k] + g0 + threadIdx.x];
+    __syncthreads();
+    for (int m = 0; m < G;) {
+      const bool spilled = s_cm[m] > h.part_cap;
+      int e = m + 1, n = min(s_cm[m], h.part_cap);
+      if (!spilled)
+        while (e < G && s_cm[e] <= h.part_cap && n + s_cm[e] <= HUB_PART_GROUP_MAX) n += s_cm[e++];
+      err |= merge_parts<FEAT>(a, h, T, red, i, k, pb, g0 + m, e - m, n, spilled, s_cm + m, nov);
+      m = e;
     }
   }
   if (err) atomicOr(&a.ctl->error, 16);

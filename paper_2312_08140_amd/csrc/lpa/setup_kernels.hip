@@ -46,6 +46,15 @@ __global__ void k_check_edges(const int32_t *idx, const float *w, int64_t m, int
   if (wmax) atomicMax(&chk->max_weight, wmax);
 }
 
+// Flags a row whose neighbours are not strictly increasing: one wave per row.
+__global__ __launch_bounds__(256) void k_check_rows(const int64_t *off, const int32_t *idx, int64_t n, CsrCheck *chk) {
+  const int lane = threadIdx.x & 63;
+  int bad = 0;
+  for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n; r += (int64_t)gridDim.x * 4)
+    for (int64_t k = off[r] + lane; k + 1 < off[r + 1]; k += 64) bad |= idx[k] >= idx[k + 1];
+  if (bad) atomicOr(&chk->rows_not_strict, 1);
+}
+
 __global__ void k_convert_weights(const float *w, int64_t m, int wk, void *out) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t u = (uint32_t)w[e];
@@ -305,6 +314,9 @@ void launch_check_offsets(const int64_t *off, int64_t n, CsrCheck *chk, hipStrea
 }
 void launch_check_edges(const int32_t *idx, const float *w, int64_t m, int64_t n, CsrCheck *chk, hipStream_t st) {
   hipLaunchKernelGGL(k_check_edges, dim3(grid_for(m, 256)), dim3(256), 0, st, idx, w, m, n, chk);
+}
+void launch_check_rows(const int64_t *off, const int32_t *idx, int64_t n, CsrCheck *chk, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_rows, dim3(grid_for(n, 4)), dim3(256), 0, st, off, idx, n, chk);
 }
 void launch_convert_weights(const float *w, int64_t m, int wk, void *out, hipStream_t st) {
   hipLaunchKernelGGL(k_convert_weights, dim3(grid_for(m, 256)), dim3(256), 0, st, w, m, wk, out);

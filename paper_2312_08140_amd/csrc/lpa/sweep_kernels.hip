@@ -36,8 +36,7 @@ __global__ void k_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t
 __global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount,
                             int nfc, int32_t *host_done, int dense_enabled, int dense_first, int gate_on) {
   for (int k = threadIdx.x; k < nfc; k += blockDim.x) fcount[k] = 0;
-  for (int k = threadIdx.x; k < NSHARD * (NBINS + 1) * 4; k += blockDim.x)
-    ctl->shard[k / ((NBINS + 1) * 4)][(k >> 2) % (NBINS + 1)].c[k & 3] = 0;
+  for (int k = threadIdx.x; k < NSHARD * NSLOT * 4; k += blockDim.x) ctl->shard[k / (NSLOT * 4)][(k >> 2) % NSLOT].c[k & 3] = 0;
   if (threadIdx.x == 0) {
     ctl->dense_enabled = dense_enabled;
     ctl->dense_cur = dense_enabled && dense_first;
@@ -64,6 +63,7 @@ __global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int6
     for (int k = 0; k < NBINS; ++k)
       ctl->bin_vertices[k] = ctl->bin_edges[k] = ctl->bin_changed[k] = ctl->bin_marks[k] = 0;
     ctl->compact_listed = ctl->compact_taken = 0;
+    ctl->first_vertices = ctl->first_edges = ctl->first_changed = ctl->first_marks = ctl->first_reads = 0;
     ctl->t_start = wall_clock64();
     if (host_done) {
       __atomic_store_n(host_done, ctl->done, __ATOMIC_RELAXED);
@@ -75,11 +75,11 @@ __global__ void k_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int6
 // Folds the sweep's counter shards into the sweep totals (ctl->changed,
 // processed, scanned, gated) and the run totals per bin, clearing them.
 __device__ void fold_shards(Ctl *ctl) {
-  __shared__ u64 red[NBINS + 1][4];
-  for (int k = threadIdx.x; k < (NBINS + 1) * 4; k += blockDim.x) red[k >> 2][k & 3] = 0;
+  __shared__ u64 red[NSLOT][4];
+  for (int k = threadIdx.x; k < NSLOT * 4; k += blockDim.x) red[k >> 2][k & 3] = 0;
   __syncthreads();
-  for (int k = threadIdx.x; k < NSHARD * (NBINS + 1) * 4; k += blockDim.x) {
-    const int q = k & 3, slot = (k >> 2) % (NBINS + 1), sh = k / ((NBINS + 1) * 4);
+  for (int k = threadIdx.x; k < NSHARD * NSLOT * 4; k += blockDim.x) {
+    const int q = k & 3, slot = (k >> 2) % NSLOT, sh = k / (NSLOT * 4);
     const u64 x = ctl->shard[sh][slot].c[q];
     if (x) {
       atomicAdd(&red[slot][q], x);
@@ -97,6 +97,13 @@ __device__ void fold_shards(Ctl *ctl) {
       ctl->bin_vertices[b] += red[b][2];
       ctl->bin_marks[b] += red[b][3];
     }
+    changed += red[FIRST_SLOT][0];
+    scanned += red[FIRST_SLOT][1];
+    ctl->first_changed += red[FIRST_SLOT][0];
+    ctl->first_edges += red[FIRST_SLOT][1];
+    ctl->first_vertices += red[FIRST_SLOT][2];
+    ctl->first_marks += red[FIRST_SLOT][3];
+    ctl->first_reads += red[READS_SLOT][0];
     ctl->changed = changed;
     ctl->scanned = scanned;
     ctl->processed = red[NBINS][0];

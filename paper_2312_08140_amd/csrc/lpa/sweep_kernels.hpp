@@ -33,6 +33,9 @@ void launch_scan_bin(int bin, int variant, int wk, bool feat, int blocks, hipStr
 int bin_vertices_per_block(int bin, int variant);
 void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, hipStream_t st);
 void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
+// snapshot first sweep (first_sweep.hip)
+void launch_first_bin(int bin, int variant, int wk, int blocks, hipStream_t st, const ScanArgs &a);
+void launch_hub_first_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
 void launch_hub_part(int blocks, bool feat, hipStream_t st, const ScanArgs &a, const HubArgs &h);
 void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, bool feat, hipStream_t st, const ScanArgs &a,
                        const HubArgs &h);
@@ -68,10 +71,11 @@ struct CsrCheck {
   uint32_t max_weight;
   int32_t not_all_ones;
   int32_t asym;           // LPA_FLAG_CHECK_SYMMETRIC: a missing or different reverse entry
-  int32_t pad;
+  int32_t rows_not_strict;  // a row whose neighbours are not strictly increasing (unsorted or repeated)
 };
 void launch_check_offsets(const int64_t *off, int64_t n, CsrCheck *chk, hipStream_t st);
 void launch_check_edges(const int32_t *idx, const float *w, int64_t m, int64_t n, CsrCheck *chk, hipStream_t st);
+void launch_check_rows(const int64_t *off, const int32_t *idx, int64_t n, CsrCheck *chk, hipStream_t st);
 void launch_convert_weights(const float *w, int64_t m, int wk, void *out, hipStream_t st);
 void launch_weighted_degree(const int64_t *off, const void *w, int wk, int64_t n, uint32_t *K, CsrCheck *chk,
                             hipStream_t st);

@@ -30,7 +30,8 @@ def _stats(weight_bytes=1):
 def test_kernel_bytes_model():
     """Per processed vertex 16 B, per scanned entry 8 B + the packed weight,
     per change 4 B, per mark 1 B; compaction 5 B per listed and per taken
-    vertex; bin 6 is reported as the hub scan."""
+    vertex; bin 6 is reported as the hub scan; the snapshot first sweep
+    counts 4 B + the weight per entry and 4 B per neighbour id it read."""
     st = _stats(weight_bytes=1)
     st["bin_vertices"][2] = 10
     st["bin_edges"][2] = 100
@@ -46,6 +47,9 @@ def test_kernel_bytes_model():
     assert b["bin0"] == 0
     assert b["compact"] == 11 * 5 + 4 * 5
     assert bench.kernel_bytes(_stats(weight_bytes=0))["bin3"] == 0
+    assert b["first"] == 0
+    st["first_vertices"], st["first_edges"], st["first_reads"], st["first_changed"], st["first_marks"] = 3, 40, 6, 2, 5
+    assert bench.kernel_bytes(st)["first"] == 3 * 16 + 40 * 5 + 6 * 4 + 2 * 4 + 5
     st4 = _stats(weight_bytes=4)
     st4["bin_edges"][4] = 10
     assert bench.kernel_bytes(st4)["bin4"] == 10 * 12
@@ -73,7 +77,8 @@ def test_profiled_config_needs_matching_sources(fake_root):
     root, digest = fake_root
     _write_profile(root, digest, [0, 2, 2, 2, 2, 1], [1, 0, 1], [7, 31, 127, 511, 2047, 8191])
     assert bench.profiled_config("rmat24") == {"variants": [0, 2, 2, 2, 2, 1], "schedule": [1, 0, 1],
-                                               "bins": [7, 31, 127, 511, 2047, 8191], "hubs_last": 0}
+                                               "bins": [7, 31, 127, 511, 2047, 8191], "hubs_last": 0,
+                                               "snapshot": 0}
     _write_profile(root, "0" * 16, [0, 2, 2, 2, 2, 1], [1, 0, 1])
     assert bench.profiled_config("rmat24") is None
     assert bench.profiled_config("rmat26") is None  # no summary at all
@@ -93,7 +98,7 @@ def test_measured_traffic_only_for_the_profiled_configuration(fake_root):
     assert bench.measured_traffic("bin4", dict(cfg), "rmat24") is None       # kernel not in the summary
     assert bench.measured_traffic("bin5", None, "rmat24") is None            # untuned run
     for key, other in (("variants", [1] * 6), ("schedule", [16, 2, 4]), ("bins", bench.DEFAULT_BINS),
-                       ("hubs_last", 1)):
+                       ("hubs_last", 1), ("snapshot", 1)):
         changed = dict(cfg)
         changed[key] = other
         assert bench.measured_traffic("bin5", changed, "rmat24") is None

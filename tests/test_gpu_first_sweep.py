@@ -1,0 +1,226 @@
+"""Snapshot first sweep (lpa_set_first_sweep) on the GPU.
+
+In the first sweep of a run from the initial labels, with every read seeing
+the labels as the sweep began, each label is a vertex id and occurs once in a
+row without repeated neighbours; Eq. (2) then picks the heaviest entry and,
+among the heaviest, the smallest id (strict) or the smallest rank (non-strict,
+Section 4.1.5).  That result is unique, so one sweep is compared exactly with
+a brute-force reference written here from that definition; whole runs are
+checked like every asynchronous run (components, verified fixed point,
+modularity next to the deterministic run).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_08140_amd import abi, graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+DET, ASYNC = abi.LPA_MODE_DETERMINISTIC, abi.LPA_MODE_ASYNC
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def snapshot_reference(g, nonstrict=False):
+    """Labels after one sweep in which every vertex reads the initial labels
+    (vertex ids): per row, the largest (weight, -id) over the entries that
+    are not the vertex itself; non-strict: the largest (weight, -rank) with
+    rank ((id + 1) * A^(1 + v mod 64)) mod P.  A row without such an entry
+    keeps its own id."""
+    n = g.n
+    off = np.asarray(g.offsets, np.int64)
+    idx = np.asarray(g.indices, np.int64)
+    w = np.ones(idx.shape[0], np.int64) if g.weights is None else np.asarray(g.weights).astype(np.int64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
+    keep = idx != rows
+    rows, idx, w = rows[keep], idx[keep], w[keep]
+    if nonstrict:
+        mult = np.array([pow(oracle.TIE_A, 1 + k, oracle.TIE_P) for k in range(64)], np.int64)
+        tie = ((idx + 1) % oracle.TIE_P) * mult[rows % 64] % oracle.TIE_P
+    else:
+        tie = idx
+    # last entry of each row after sorting by (row, weight, -tie)
+    order = np.lexsort((-tie, w, rows))
+    rows_s = rows[order]
+    last = np.ones(rows_s.shape[0], bool)
+    last[:-1] = rows_s[1:] != rows_s[:-1]
+    labels = np.arange(n, dtype=np.int64)
+    labels[rows_s[last]] = idx[order][last]
+    return labels.astype(np.int32)
+
+
+def _components(g):
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as csg
+    a = sp.csr_matrix((np.ones(g.m), g.indices, g.offsets), shape=(g.n, g.n))
+    return csg.connected_components(a, directed=False)[1]
+
+
+ALL = 7  # every kernel of the first sweep reads the snapshot
+
+
+def one_snapshot_sweep(G, flags=0):
+    G.set_first_sweep(ALL)
+    labels, st = G.run(0.0, 1, ASYNC, True, flags=flags)
+    return labels, st
+
+
+def _u32_weighted(n, m_pairs, seed):
+    rng = np.random.default_rng(seed)
+    e = rng.integers(0, n, size=(m_pairs, 2))
+    w = rng.integers(1, 1000, size=m_pairs)
+    return gg.from_edges(n, e, weights=w)
+
+
+CASES = {
+    "rmat14_u8": lambda: gg.rmat(14, 16, seed=21, weighted=True),
+    "rmat13_unit": lambda: gg.rmat(13, 8, seed=22, weighted=False),
+    "random_u32": lambda: _u32_weighted(6000, 60000, 23),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("nonstrict", [False, True])
+def test_snapshot_sweep_equals_reference(case, nonstrict):
+    """One snapshot sweep: labels equal the brute-force reference, with small
+    bins so that hubs (chunked rows) take part; the sweep's counters are
+    those of its own kernels."""
+    g = CASES[case]()
+    say(f"{case} n={g.n} m={g.m} nonstrict={nonstrict}")
+    ref = snapshot_reference(g, nonstrict)
+    flags = abi.LPA_FLAG_NONSTRICT if nonstrict else 0
+    for bins in ([2, 8, 32, 128, 256, 512], None):
+        G = abi.LPAGraph(g)
+        G.set_bins(bins)
+        assert G.schedule()[6] == 1  # sorted rows without repeats
+        labels, st = one_snapshot_sweep(G, flags)
+        assert np.array_equal(labels, ref), (case, bins)
+        assert st["iterations"] == 1
+        assert st["first_vertices"] == st["frontier"][0]
+        assert st["first_edges"] == st["edges_scanned"][0]
+        assert st["first_changed"] == st["changed"][0] == int(np.count_nonzero(ref != np.arange(g.n)))
+        assert 0 < st["first_reads"] <= st["first_edges"]
+        if g.weights is not None:
+            assert st["first_reads"] < st["first_edges"]  # ids read only at the running maximum weight
+        assert sum(st["bin_edges"]) == 0  # no plain scan kernel ran
+        G.close()
+
+
+def test_snapshot_sweep_without_reorder():
+    """Rows kept in id order (no storage permutation): the generator's rows
+    are sorted, so the sweep applies, reading labels by position."""
+    g = gg.rmat(13, 16, seed=24, weighted=True)
+    off = np.asarray(g.offsets)
+    d = np.diff(g.indices.astype(np.int64))
+    row_start = np.zeros(g.m, bool)
+    row_start[off[:-1][np.diff(off) > 0]] = True
+    strict = bool(np.all(d[~row_start[1:]] > 0))
+    G = abi.LPAGraph(g, reorder=False)
+    assert G.schedule()[6] == int(strict)
+    labels, st = one_snapshot_sweep(G)
+    if strict:
+        assert np.array_equal(labels, snapshot_reference(g)) and st["first_edges"] == st["edges_scanned"][0]
+    G.close()
+
+
+def test_repeated_neighbours_disable_the_snapshot():
+    """A row that lists a neighbour twice sums both entries for that label,
+    so the table-free sweep does not apply: the first sweep runs the plain
+    kernels and the result is the oracle's."""
+    # 0-1 listed twice in both directions, plus a triangle 1-2-3
+    off = np.array([0, 2, 6, 8, 10], np.int64)
+    idx = np.array([1, 1, 0, 0, 2, 3, 1, 3, 1, 2], np.int32)
+    g = gg.CSR(4, off, idx, None)
+    G = abi.LPAGraph(g)
+    assert G.schedule()[6] == 0
+    G.set_first_sweep(ALL)
+    assert G.schedule()[5] == ALL
+    labels, st = G.run(0.05, 20, DET, True)
+    ref = oracle.lpa(g, order=oracle.color_order(*oracle.color(g, 0)), tau=0.05, max_iters=20)
+    assert np.array_equal(labels, ref["labels"])
+    labels, st = G.run(0.0, 1, ASYNC, True)
+    assert st["first_edges"] == 0 and st["edges_scanned"][0] == g.m
+    G.close()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_snapshot_runs_keep_quality(seed):
+    """Whole asynchronous runs with the snapshot first sweep: labels inside
+    components, a verified fixed point, modularity within 0.01 of the
+    deterministic run (SBM with communities, and an R-MAT with hubs)."""
+    for g in (gg.sbm(20000, 40, 0.05, 0.00005, seed=seed, weighted=True), gg.rmat(14, 16, seed=30 + seed)):
+        G = abi.LPAGraph(g)
+        G.set_bins([2, 8, 32, 128, 256, 512])
+        G.set_first_sweep(ALL if seed == 1 else 5)  # 5: hubs and bins 5 down to 2 (the SBM rows sit in bin 2)
+        for tie in (0, abi.LPA_FLAG_NONSTRICT):
+            det, _ = G.run(0.05, 20, DET, True, flags=tie)  # the same tie rule, deterministic order
+            q_det = G.modularity(det)
+            flags = abi.LPA_FLAG_VERIFY | tie
+            lab, st = G.run(0.05, 20, ASYNC, True, flags=flags)
+            comp = _components(g)
+            assert np.array_equal(comp[lab], comp)
+            assert st["converged"] and st["verified"] and 0 < st["first_edges"] <= st["edges_scanned"][0]
+            q = G.modularity(lab)
+            say(f"n={g.n} flags={flags} q_async={q:.4f} q_det={q_det:.4f} sweeps={st['iterations']}")
+            assert abs(q - q_det) <= 0.01
+        # the gate's features are not written by the snapshot kernels: a trace run falls back
+        lab, st = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_TRACE)
+        assert st["first_edges"] == 0
+        G.close()
+
+
+def test_snapshot_in_a_batch():
+    """A batched handle replays the whole run as one graph launch; its first
+    sweep is the snapshot sweep of every graph at once."""
+    g, vptr = gg.sbm_batch(count=30, master_seed=5, seed_base=900, n_range=(100, 3000))
+    B = abi.LPABatch(g, vptr)
+    B.set_first_sweep(ALL)
+    labels, st = B.run(0.0, 1, ASYNC, True)
+    assert np.array_equal(labels, snapshot_reference(g))
+    labels, st = B.run(0.05, 20, ASYNC, True)
+    gid = np.searchsorted(vptr, np.arange(g.n), side="right") - 1
+    assert np.array_equal(gid[labels], gid)
+    it, cv = B.graph_stats()
+    assert cv.all() and st["first_edges"] > 0
+    B.close()
+
+
+def test_autotune_reports_the_snapshot_choice():
+    g = gg.rmat(14, 16, seed=40)
+    G = abi.LPAGraph(g)
+    G.autotune(0.05, 20, ASYNC)
+    sch = G.schedule()
+    assert sch[5] in (0, 1, 2, 3, ALL) and sch[6] == 1
+    lab, st = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_VERIFY)
+    assert st["converged"] and st["verified"]
+    assert (st["first_edges"] > 0) == bool(sch[5])
+    with pytest.raises(abi.LPAError):
+        G.set_first_sweep(ALL + 1)
+    G.close()
+
+
+def test_snapshot_of_the_leading_kernel_only():
+    """kernels = 1 with the hubs first in a one-step schedule: the hub kernel
+    reads the initial labels - its vertices get exactly the reference labels,
+    whatever the later kernels of the sweep do - and the bins read the labels
+    as they find them."""
+    g = gg.rmat(14, 16, seed=41, weighted=True)
+    ref = snapshot_reference(g)
+    G = abi.LPAGraph(g)
+    G.set_bins([2, 8, 32, 128, 256, 512])
+    G.set_async_schedule(1, 0, 1)
+    G.set_first_sweep(1)
+    labels, st = G.run(0.0, 1, ASYNC, True)
+    hubs = np.diff(g.offsets) > 512
+    assert hubs.any()
+    assert np.array_equal(labels[hubs], ref[hubs])
+    assert st["first_vertices"] == int(hubs.sum())
+    assert st["first_edges"] == int(np.diff(g.offsets)[hubs].sum()) < st["edges_scanned"][0]
+    assert sum(st["bin_edges"]) == st["edges_scanned"][0] - st["first_edges"]
+    G.close()
