@@ -313,6 +313,7 @@ struct HubArgs {
   int32_t *part_nd;          // FEAT: distinct labels of each partition
   uint32_t *own_w;           // FEAT: per frontier entry, weight of the hub's own label
   int32_t first;             // snapshot first sweep: k_hub_owner zeroes the partition maxima
+  u64 *blk;                  // per tile of frontier hubs: work items (chunks, partitions, groups), then offsets
 };
 
 // Wave64 helpers.

@@ -119,7 +119,7 @@ struct lpa_graph {
   uint32_t *hub_ovf = nullptr;
   u64 *hub_ovf_count = nullptr;
   int32_t *hub_ord = nullptr;
-  u64 *hub_cstart = nullptr, *hub_pstart = nullptr, *hub_gstart = nullptr;
+  u64 *hub_cstart = nullptr, *hub_pstart = nullptr, *hub_gstart = nullptr, *hub_blk = nullptr;
   int32_t *hub_chunk_owner = nullptr, *hub_group_owner = nullptr, *hub_changed = nullptr;
   uint32_t *hub_part_w2 = nullptr, *hub_own_w = nullptr;
   int32_t *hub_part_nd = nullptr;
@@ -351,7 +351,7 @@ void build_hubs(lpa_graph *g) {
                    (void **)&g->hub_pair_base, (void **)&g->hub_cnt_base, (void **)&g->hub_pairs,
                    (void **)&g->hub_pcnt, (void **)&g->hub_partbest, (void **)&g->hub_ovf,
                    (void **)&g->hub_ovf_count, (void **)&g->hub_ord, (void **)&g->hub_cstart,
-                   (void **)&g->hub_pstart, (void **)&g->hub_gstart, (void **)&g->hub_chunk_owner,
+                   (void **)&g->hub_pstart, (void **)&g->hub_gstart, (void **)&g->hub_blk, (void **)&g->hub_chunk_owner,
                    (void **)&g->hub_group_owner,
                    (void **)&g->hub_changed, (void **)&g->hub_part_w2, (void **)&g->hub_own_w,
                    (void **)&g->hub_part_nd};
@@ -399,6 +399,7 @@ void build_hubs(lpa_graph *g) {
   g->hub_cstart = dalloc_n<u64>(g, n1);
   g->hub_pstart = dalloc_n<u64>(g, n1);
   g->hub_gstart = dalloc_n<u64>(g, n1);
+  g->hub_blk = dalloc_n<u64>(g, 3 * (hub_plan_tiles(n1) + 1));
   g->hub_changed = dalloc_n<int32_t>(g, n1);
   g->hub_own_w = dalloc_n<uint32_t>(g, n1);
   g->hub_part_w2 = dalloc_n<uint32_t>(g, std::max<int64_t>(1, parts));
@@ -441,6 +442,7 @@ HubArgs hub_args(lpa_graph *g) {
   h.pstart = g->hub_pstart;
   h.chunk_owner = g->hub_chunk_owner;
   h.gstart = g->hub_gstart;
+  h.blk = g->hub_blk;
   h.group_owner = g->hub_group_owner;
   h.changed = g->hub_changed;
   h.part_w2 = g->hub_part_w2;
@@ -669,7 +671,7 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
       HubArgs h = hub_args(g);
       h.first = 1;
       tk_begin(g, st);
-      launch_hub_plan(a, h, grid_cap(seg, 1, max_blocks), st);
+      launch_hub_plan(a, h, grid_cap(seg, 1, max_blocks), std::max(1, std::min(hub_plan_tiles(seg), max_blocks)), st);
       tk_end(g, st, TK_HUB_PLAN);
       tk_begin(g, st);
       launch_hub_first_chunk(g->wk, grid_cap(hub_chunks, 1, max_blocks * 2), st, a, h);
@@ -682,7 +684,7 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
     } else if (b == HUB_BIN) {
       const HubArgs h = hub_args(g);
       tk_begin(g, st);
-      launch_hub_plan(a, h, grid_cap(seg, 1, max_blocks), st);
+      launch_hub_plan(a, h, grid_cap(seg, 1, max_blocks), std::max(1, std::min(hub_plan_tiles(seg), max_blocks)), st);
       tk_end(g, st, TK_HUB_PLAN);
       tk_begin(g, st);
       launch_hub_chunk(g->wk, grid_cap(hub_chunks, 1, max_blocks * 2), st, a, h);

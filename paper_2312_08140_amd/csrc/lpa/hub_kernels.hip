@@ -2,7 +2,8 @@
 //
 // A hub's scan (scanCommunities of Algorithm 1) is spread over many
 // workgroups without any table in HBM:
-//   k_hub_plan    per flagged hub: work items (chunks, label partitions);
+//   k_hub_plan_*  per flagged hub: work items (chunks, label partitions,
+//                 merge groups) and their numbering in the step;
 //   k_hub_owner   work item -> hub maps;
 //   k_hub_chunk   per chunk of HUB_CHUNK entries: gather the neighbour
 //                 labels, merge equal labels in an LDS table, and append the
@@ -24,19 +25,22 @@ __device__ __forceinline__ uint32_t part_of(uint32_t lbl, int pbits) {
   return pbits ? (fmix32(lbl) >> (32 - pbits)) : 0u;
 }
 
-__global__ __launch_bounds__(1024) void k_hub_plan(ScanArgs a, HubArgs h) {
+// Work items of the step's flagged hubs (chunks, partitions, merge groups),
+// numbered hub after hub in frontier order.  Three passes: k_hub_plan_tile
+// finds each frontier hub's ordinal and the exclusive prefix of its work
+// items inside its tile of PLAN_TILE entries (plus the tile's totals);
+// k_hub_plan_top turns the tile totals into tile offsets; k_hub_owner adds
+// the offset of its tile to each hub's starts.
+constexpr int PLAN_TILE = 256;
+
+__global__ __launch_bounds__(PLAN_TILE) void k_hub_plan_tile(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
-  __shared__ u64 wsum[3][16];
-  __shared__ u64 s_carry[3];
-  if (threadIdx.x == 0) {
-    s_carry[0] = s_carry[1] = s_carry[2] = 0;
-    *h.ovf_count = 0;
-  }
-  __syncthreads();
+  __shared__ u64 wsum[3][PLAN_TILE / 64];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *h.ovf_count = 0;
   const int count = *a.fcount;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int tile = 0; tile < count; tile += 1024) {
-    const int i = tile + threadIdx.x;
+  for (int tile = blockIdx.x; tile * PLAN_TILE < count; tile += gridDim.x) {
+    const int i = tile * PLAN_TILE + threadIdx.x;
     u64 kc = 0, kp = 0, kg = 0;
     if (i < count) {
       const int v = a.front[i];
@@ -81,23 +85,62 @@ __global__ __launch_bounds__(1024) void k_hub_plan(ScanArgs a, HubArgs h) {
       bp += wsum[1][k];
       bg += wsum[2][k];
     }
-    const u64 cc = s_carry[0], cp = s_carry[1], cg = s_carry[2];
     if (i < count) {
-      h.cstart[i] = cc + bc + xc - kc;
-      h.pstart[i] = cp + bp + xp - kp;
-      h.gstart[i] = cg + bg + xg - kg;
+      h.cstart[i] = bc + xc - kc;
+      h.pstart[i] = bp + xp - kp;
+      h.gstart[i] = bg + xg - kg;
     }
+    if (threadIdx.x == PLAN_TILE - 1) {
+      h.blk[3 * tile + 0] = bc + xc;
+      h.blk[3 * tile + 1] = bp + xp;
+      h.blk[3 * tile + 2] = bg + xg;
+    }
+    __syncthreads();  // wsum is reused by the next tile
+  }
+}
+
+// Exclusive offsets of the tiles (in place) and the step's totals.
+__global__ __launch_bounds__(1024) void k_hub_plan_top(ScanArgs a, HubArgs h) {
+  if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
+  __shared__ u64 wsum[3][16];
+  __shared__ u64 carry[3];
+  const int tiles = (*a.fcount + PLAN_TILE - 1) / PLAN_TILE;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x < 3) carry[threadIdx.x] = 0;
+  __syncthreads();
+  for (int base = 0; base < tiles; base += 1024) {
+    const int t = base + threadIdx.x;
+    u64 x[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) x[q] = t < tiles ? h.blk[3 * t + q] : 0;
+    u64 y[3] = {x[0], x[1], x[2]};
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const u64 z = (u64)__shfl_up((unsigned long long)y[q], d, 64);
+        if (lane >= d) y[q] += z;
+      }
+    if (lane == 63)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) wsum[q][wv] = y[q];
     __syncthreads();
-    if (threadIdx.x == 1023) {
-      s_carry[0] = cc + bc + xc;
-      s_carry[1] = cp + bp + xp;
-      s_carry[2] = cg + bg + xg;
-    }
+    u64 b[3] = {carry[0], carry[1], carry[2]};
+    for (int k = 0; k < wv; ++k)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) b[q] += wsum[q][k];
+    if (t < tiles)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) h.blk[3 * t + q] = b[q] + y[q] - x[q];
+    __syncthreads();
+    if (threadIdx.x == 1023)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) carry[q] = b[q] + y[q];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    a.ctl->hub_chunks = s_carry[0];
-    a.ctl->hub_groups = s_carry[2];
+    a.ctl->hub_chunks = carry[0];
+    a.ctl->hub_groups = carry[2];
   }
 }
 
@@ -109,11 +152,18 @@ __global__ __launch_bounds__(256) void k_hub_owner(ScanArgs a, HubArgs h) {
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const int k = h.ord[i];
     const int kc = h.chunks[k], kg = hub_merge_groups(h.pbits[k]);
-    const u64 c0 = h.cstart[i], g0 = h.gstart[i];
+    const u64 *off = h.blk + 3 * (i / PLAN_TILE);
+    const u64 c0 = h.cstart[i] + off[0], p0 = h.pstart[i] + off[1], g0 = h.gstart[i] + off[2];
+    __syncthreads();  // every thread has read the tile-relative starts
+    if (threadIdx.x == 0) {
+      h.cstart[i] = c0;
+      h.pstart[i] = p0;
+      h.gstart[i] = g0;
+    }
     for (int c = threadIdx.x; c < kc; c += 256) h.chunk_owner[c0 + c] = i;
     for (int gq = threadIdx.x; gq < kg; gq += 256) h.group_owner[g0 + gq] = i;
     if (h.first)
-      for (int p = threadIdx.x; p < (1 << h.pbits[k]); p += 256) h.partbest[h.pstart[i] + p] = 0;
+      for (int p = threadIdx.x; p < (1 << h.pbits[k]); p += 256) h.partbest[p0 + p] = 0;
   }
 }
 
@@ -397,10 +447,13 @@ __global__ __launch_bounds__(256) void k_hub_mark(ScanArgs a, HubArgs h) {
   block_accum<256>(0, 0, 0, n_marks, 0, a.ctl, a.bin);
 }
 
-void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(1024), 0, st, a, h);
+void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, int tile_blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_hub_plan_tile, dim3(tile_blocks), dim3(PLAN_TILE), 0, st, a, h);
+  hipLaunchKernelGGL(k_hub_plan_top, dim3(1), dim3(1024), 0, st, a, h);
   hipLaunchKernelGGL(k_hub_owner, dim3(blocks), dim3(256), 0, st, a, h);
 }
+
+int hub_plan_tiles(int64_t entries) { return (int)((entries + PLAN_TILE - 1) / PLAN_TILE); }
 
 void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h) {
   if (wk == W_UNIT) hipLaunchKernelGGL(k_hub_chunk<W_UNIT>, dim3(blocks), dim3(256), 0, st, a, h);
