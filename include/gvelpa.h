@@ -202,10 +202,10 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
  * converge (a batch: every graph) and whose modularity stays within 0.002 of
  * the first's; the first stays when no other qualifies (schedule_out: int32[3],
  * may be NULL); then, on a graph with hubs, whether the hub bin runs last in
- * each step (lpa_set_bin_order), and, where the rows allow it, how many
- * kernels of each step of the first sweep read the initial labels (none, 1,
- * 2, 3 or all; lpa_set_first_sweep; read both back with lpa_get_schedule).
- * Then the
+ * each step (lpa_set_bin_order) together with, where the rows allow it, how
+ * many kernels of each step of the first sweep read the initial labels (none,
+ * 1, 2, 3, 4 or all; lpa_set_first_sweep; read both back with
+ * lpa_get_schedule).  Then the
  * degree limits of the bins (lpa_set_bins): each
  * bin's LDS table has a fixed size (8, 32, 128, 512, 2048, 8192 slots), and
  * the candidates let it fill to at most 1/2 (the default), 1/4, 3/4 or all of

@@ -661,7 +661,9 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
     const int b = !g->hubs_last ? NBINS - 1 - k : (k < NBINS - 1 ? NBINS - 2 - k : HUB_BIN);
     const int64_t seg = bounds[b + 1] - bounds[b];
     if (seg <= 0) continue;
-    const bool first = k < snap_kernels;  // this kernel reads the initial labels
+    // this kernel reads the initial labels (with the gate's features on, only
+    // the bin kernels do: the hub kernels' features need their partitions)
+    const bool first = k < snap_kernels && !(b == HUB_BIN && g->feat_on);
     ScanArgs a = base_args(g, prune);
     a.bin = b;
     a.front = g->front + bounds[b];
@@ -699,7 +701,7 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
     } else if (first) {
       const int per_block = bin_vertices_per_block(b, g->variant[b]);
       tk_begin(g, st);
-      launch_first_bin(b, g->variant[b], g->wk, grid_cap(seg, per_block, max_blocks), st, a);
+      launch_first_bin(b, g->variant[b], g->wk, g->feat_on, grid_cap(seg, per_block, max_blocks), st, a);
       tk_end(g, st, TK_FIRST);
     } else {
       const int per_block = bin_vertices_per_block(b, g->variant[b]);
@@ -1256,8 +1258,9 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
   double q_ref = 0.0;
   bool have_ref = false;
   auto quality_ok = [&](double q) { return !have_ref || q >= q_ref - 0.002; };
-  // the reference runs read labels as the schedule delivers them
+  // the reference runs: hubs first, labels read as the schedule delivers them
   rc = lpa_set_first_sweep(g, 0);
+  if (rc == LPA_OK && mode == LPA_MODE_ASYNC) rc = lpa_set_bin_order(g, 0);
   if (rc != LPA_OK) return rc;
   // 1. Asynchronous schedule: the fastest candidate whose runs converge (for
   //    a batch: every graph) and whose modularity stays within 0.002 of the
@@ -1294,55 +1297,43 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
     rc = lpa_set_async_schedule(g, cand[best][0], cand[best][1], cand[best][2], g->async_by_colour ? 1 : 0);
     if (rc != LPA_OK) return rc;
     if (schedule_out) std::memcpy(schedule_out, cand[best], sizeof(cand[best]));
-    // 1b. Order of the bins inside a step: hubs first (the default) or last,
+    // 1b. Order of the bins inside a step - hubs first (the default) or last,
     //     after the other vertices have updated their labels (fewer distinct
-    //     labels reach the hubs' partitions).  Same acceptance rules.
-    if (g->n_hubs > 0) {
-      rc = lpa_set_bin_order(g, 1);
-      if (rc != LPA_OK) return rc;
-      double ms = 1e300, q = 0.0;
-      bool converged = true;
-      for (int rep = 0; rep < 2; ++rep) {
-        lpa_stats st;
-        rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
-        if (rc != LPA_OK) return rc;
-        ms = std::min(ms, st.total_ms);
-        converged = converged && st.converged;
-      }
-      rc = lpa_modularity(g, nullptr, 0, &q);
-      if (rc != LPA_OK) return rc;
-      if (converged && quality_ok(q) && ms < 0.97 * best_ms) best_ms = ms;
-      else rc = lpa_set_bin_order(g, 0);
-      if (rc != LPA_OK) return rc;
-    }
-    // 1c. The snapshot first sweep (lpa_set_first_sweep), where the rows
-    //     allow it: the first 1, 2, 3 or all kernels of each step of the first
-    //     sweep read the initial labels.  Reading them is cheap (no table,
-    //     few reads), but a sweep whose vertices all read them merges fewer
-    //     labels, which can cost a sweep later on.  Same acceptance rules.
-    if (g->rows_strict) {
-      static const int32_t snap_cand[] = {1, 2, 3, NBINS};
-      int32_t best_snap = 0;
-      for (int32_t c : snap_cand) {
-        rc = lpa_set_first_sweep(g, c);
-        if (rc != LPA_OK) return rc;
-        double ms = 1e300, q = 0.0;
-        bool converged = true;
-        for (int rep = 0; rep < 2; ++rep) {
-          lpa_stats st;
-          rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
+    //     labels reach the hubs' partitions) - together with the snapshot
+    //     first sweep where the rows allow it (lpa_set_first_sweep: the first
+    //     1, 2, 3, 4 or all kernels of each step of the first sweep read the
+    //     initial labels; cheap to read, but a sweep whose vertices all read
+    //     them merges fewer labels, which can cost a sweep later on).  Same
+    //     acceptance rules, in this order.
+    {
+      static const int32_t snap_cand[] = {0, 1, 2, 3, 4, NBINS};
+      const int n_snap = g->rows_strict ? (int)(sizeof(snap_cand) / sizeof(snap_cand[0])) : 1;
+      int32_t best_order = 0, best_snap = 0;
+      for (int32_t order = 0; order <= (g->n_hubs > 0 ? 1 : 0); ++order)
+        for (int c = 0; c < n_snap; ++c) {
+          if (order == 0 && snap_cand[c] == 0) continue;  // the configuration of step 1
+          rc = lpa_set_bin_order(g, order);
+          if (rc == LPA_OK) rc = lpa_set_first_sweep(g, snap_cand[c]);
           if (rc != LPA_OK) return rc;
-          ms = std::min(ms, st.total_ms);
-          converged = converged && st.converged;
+          double ms = 1e300, q = 0.0;
+          bool converged = true;
+          for (int rep = 0; rep < 2; ++rep) {
+            lpa_stats st;
+            rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
+            if (rc != LPA_OK) return rc;
+            ms = std::min(ms, st.total_ms);
+            converged = converged && st.converged;
+          }
+          rc = lpa_modularity(g, nullptr, 0, &q);
+          if (rc != LPA_OK) return rc;
+          if (converged && quality_ok(q) && ms < 0.97 * best_ms) {
+            best_ms = ms;
+            best_order = order;
+            best_snap = snap_cand[c];
+          }
         }
-        rc = lpa_modularity(g, nullptr, 0, &q);
-        if (rc != LPA_OK) return rc;
-        if (converged && quality_ok(q) && ms < 0.97 * best_ms) {
-          best_ms = ms;
-          best_snap = c;
-        }
-      }
-      rc = lpa_set_first_sweep(g, best_snap);
+      rc = lpa_set_bin_order(g, best_order);
+      if (rc == LPA_OK) rc = lpa_set_first_sweep(g, best_snap);
       if (rc != LPA_OK) return rc;
     }
   } else if (schedule_out) {
@@ -1567,9 +1558,8 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     }
     g->cur_feat = feat_args(g, max_iters, trace);
     // snapshot first sweep: asynchronous runs from the initial labels over
-    // rows without repeated neighbours (no gate features to write)
-    const int snap =
-        mode == LPA_MODE_ASYNC && g->rows_strict && !init_labels && !g->feat_on ? g->snapshot_kernels : 0;
+    // rows without repeated neighbours
+    const int snap = mode == LPA_MODE_ASYNC && g->rows_strict && !init_labels ? g->snapshot_kernels : 0;
     // per-sweep graphs of the early and the late asynchronous schedule
     hipGraphExec_t exec = nullptr, exec_late = nullptr, exec_first = nullptr;
     if (use_graph && max_iters > 0) {

@@ -14,7 +14,10 @@
 // reaches the running maximum weight of the lane that holds it.  The engine
 // uses these kernels only when every row's neighbours are strictly increasing
 // (sorted rows, hence no repeated neighbour) and the run starts from the
-// initial labels.
+// initial labels.  With the gate's features on (FEAT), the bin kernels also
+// record them: with every label distinct, the two largest label weights are
+// the two largest entry weights, the distinct labels are the entries other
+// than the vertex itself, and the vertex's own label (its id) has weight 0.
 #include "sweep_kernels.hpp"
 #include "tables.hpp"
 
@@ -22,10 +25,11 @@ namespace gvelpa {
 
 // Lane `lane` of a group of STRIDE lanes: the largest argmax key among the
 // entries lane, lane + STRIDE, ... of [b, e) (vertex v itself skipped), with
-// U entries in flight; counts the ids it reads.
-template <int STRIDE, int U, int WK>
+// U entries in flight; counts the ids it reads; FEAT: the lane's two largest
+// entry weights and its entries in ts.
+template <int STRIDE, int U, int WK, bool FEAT = false>
 __device__ __forceinline__ u64 first_row(const ScanArgs &a, int64_t b, int64_t e, int v, int lane, TieRule tr,
-                                         u64 &reads) {
+                                         u64 &reads, TabStats &ts) {
   u64 best = 0;
   uint32_t bw = 0;  // the lane's largest weight so far
   for (int64_t base = b + lane; base < e; base += (int64_t)STRIDE * U) {
@@ -41,7 +45,18 @@ __device__ __forceinline__ u64 first_row(const ScanArgs &a, int64_t b, int64_t e
     uint32_t mw = bw;
 #pragma unroll
     for (int r = 0; r < U; ++r)
-      if (j[r] >= 0 && j[r] != v) mw = w[r] > mw ? w[r] : mw;
+      if (j[r] >= 0 && j[r] != v) {
+        mw = w[r] > mw ? w[r] : mw;
+        if constexpr (FEAT) {
+          ++ts.nd;
+          if (w[r] > ts.w1) {
+            ts.w2 = ts.w1;
+            ts.w1 = w[r];
+          } else if (w[r] > ts.w2) {
+            ts.w2 = w[r];
+          }
+        }
+      }
     uint32_t lb[U];
 #pragma unroll
     for (int r = 0; r < U; ++r)
@@ -60,12 +75,13 @@ __device__ __forceinline__ u64 first_row(const ScanArgs &a, int64_t b, int64_t e
 
 // One vertex per GROUP lanes (GROUP <= 64: lanes of one wave; GROUP == BLOCK:
 // the whole workgroup).  Counters go to the first-sweep shard slots.
-template <int GROUP, int BLOCK, int U, int WK>
+template <int GROUP, int BLOCK, int U, int WK, bool FEAT>
 __global__ __launch_bounds__(BLOCK) void k_first_scan(ScanArgs a) {
   static_assert(GROUP <= 64 || GROUP == BLOCK, "a vertex takes lanes of one wave or the whole workgroup");
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   constexpr int GPB = BLOCK / GROUP;
   __shared__ u64 red[BLOCK / 64];
+  __shared__ TabStats tred[FEAT && GROUP > 64 ? BLOCK / 64 : 1];
   const int lane = threadIdx.x % GROUP;
   const int grp = threadIdx.x / GROUP;
   const int count = *a.fcount;
@@ -76,12 +92,15 @@ __global__ __launch_bounds__(BLOCK) void k_first_scan(ScanArgs a) {
     const int v = a.front[i];
     const int64_t b = a.off[v], e = a.off[v + 1];
     const TieRule tr = tie_rule_of(a, v);
-    u64 best = first_row<GROUP, U, WK>(a, b, e, v, lane, tr, n_reads);
+    TabStats ts{0u, 0u, 0};
+    u64 best = first_row<GROUP, U, WK, FEAT>(a, b, e, v, lane, tr, n_reads, ts);
     if constexpr (GROUP == BLOCK && BLOCK > 64) best = block_max<BLOCK>(best, red);
     else best = group_max<GROUP>(best);
+    bool changed = false;
     if (best != 0) {
       const int32_t cs = (int32_t)key_label(best, tr);
       if (cs != a.C[v]) {
+        changed = true;
         if (lane == 0) {
           a.C[v] = cs;
           ++n_changed;
@@ -89,6 +108,18 @@ __global__ __launch_bounds__(BLOCK) void k_first_scan(ScanArgs a) {
         }
         if (mark_now) n_marks += mark_row<GROUP, U>(a.idx, a.F, b, e, v, lane);
       }
+    }
+    if constexpr (FEAT) {
+      TabStats t = group_stats<(GROUP < 64 ? GROUP : 64)>(ts);
+      if constexpr (GROUP > 64) {
+        if ((threadIdx.x & 63) == 0) tred[threadIdx.x >> 6] = t;
+        __syncthreads();
+        t = tred[0];
+        for (int q = 1; q < BLOCK / 64; ++q) t = merge_stats(t, tred[q]);
+      }
+      if (lane == 0)
+        write_features(a.f, v, a.ctl->sweep, e - b, t, 0u, changed, a.f.K[v],
+                       record_lastp(a.f.feat + (int64_t)v * FEAT_STRIDE));
     }
     if (lane == 0) {
       n_scanned += (u64)(e - b);
@@ -116,7 +147,8 @@ __global__ __launch_bounds__(256) void k_hub_first_chunk(ScanArgs a, HubArgs h) 
     const int64_t eb = a.off[v] + (int64_t)(c - h.cstart[i]) * HUB_CHUNK;
     const int64_t ee = min(a.off[v + 1], eb + (int64_t)HUB_CHUNK);
     const TieRule tr = tie_rule_of(a, v);
-    const u64 best = block_max<256>(first_row<256, 8, WK>(a, eb, ee, v, threadIdx.x, tr, n_reads), red);
+    TabStats ts{0u, 0u, 0};
+    const u64 best = block_max<256>(first_row<256, 8, WK>(a, eb, ee, v, threadIdx.x, tr, n_reads, ts), red);
     if (threadIdx.x == 0 && best != 0) atomicMax((unsigned long long *)&h.partbest[h.pstart[i]], best);
     __syncthreads();  // red is reused by the next chunk
   }
@@ -125,39 +157,46 @@ __global__ __launch_bounds__(256) void k_hub_first_chunk(ScanArgs a, HubArgs h) 
 
 // ---------------------------------------------------------------- launchers
 
-template <int B, int V, int WK>
+template <int B, int V, int WK, bool FEAT>
 static void launch_first_shape(dim3 grid, hipStream_t st, const ScanArgs &a) {
   constexpr BinShape sh = BIN_SHAPES[B][V];
-  if constexpr (B <= 3) hipLaunchKernelGGL((k_first_scan<sh.group, 256, sh.unroll, WK>), grid, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((k_first_scan<sh.group, sh.group, sh.unroll, WK>), grid, dim3(sh.group), 0, st, a);
+  if constexpr (B <= 3)
+    hipLaunchKernelGGL((k_first_scan<sh.group, 256, sh.unroll, WK, FEAT>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_first_scan<sh.group, sh.group, sh.unroll, WK, FEAT>), grid, dim3(sh.group), 0, st, a);
 }
 
-template <int B, int WK>
+template <int B, int WK, bool FEAT>
 static void launch_first_v(int variant, dim3 grid, hipStream_t st, const ScanArgs &a) {
   switch (variant) {
-    case 1: launch_first_shape<B, 1, WK>(grid, st, a); break;
-    case 2: launch_first_shape<B, 2, WK>(grid, st, a); break;
-    default: launch_first_shape<B, 0, WK>(grid, st, a); break;
+    case 1: launch_first_shape<B, 1, WK, FEAT>(grid, st, a); break;
+    case 2: launch_first_shape<B, 2, WK, FEAT>(grid, st, a); break;
+    default: launch_first_shape<B, 0, WK, FEAT>(grid, st, a); break;
   }
 }
 
-template <int WK>
+template <int WK, bool FEAT>
 static void launch_first_wk(int bin, int variant, dim3 grid, hipStream_t st, const ScanArgs &a) {
   switch (bin) {
-    case 0: launch_first_v<0, WK>(variant, grid, st, a); break;
-    case 1: launch_first_v<1, WK>(variant, grid, st, a); break;
-    case 2: launch_first_v<2, WK>(variant, grid, st, a); break;
-    case 3: launch_first_v<3, WK>(variant, grid, st, a); break;
-    case 4: launch_first_v<4, WK>(variant, grid, st, a); break;
-    case 5: launch_first_v<5, WK>(variant, grid, st, a); break;
+    case 0: launch_first_v<0, WK, FEAT>(variant, grid, st, a); break;
+    case 1: launch_first_v<1, WK, FEAT>(variant, grid, st, a); break;
+    case 2: launch_first_v<2, WK, FEAT>(variant, grid, st, a); break;
+    case 3: launch_first_v<3, WK, FEAT>(variant, grid, st, a); break;
+    case 4: launch_first_v<4, WK, FEAT>(variant, grid, st, a); break;
+    case 5: launch_first_v<5, WK, FEAT>(variant, grid, st, a); break;
     default: break;
   }
 }
 
-void launch_first_bin(int bin, int variant, int wk, int blocks, hipStream_t st, const ScanArgs &a) {
-  if (wk == W_UNIT) launch_first_wk<W_UNIT>(bin, variant, dim3(blocks), st, a);
-  else if (wk == W_U8) launch_first_wk<W_U8>(bin, variant, dim3(blocks), st, a);
-  else launch_first_wk<W_U32>(bin, variant, dim3(blocks), st, a);
+void launch_first_bin(int bin, int variant, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a) {
+  if (feat) {
+    if (wk == W_UNIT) launch_first_wk<W_UNIT, true>(bin, variant, dim3(blocks), st, a);
+    else if (wk == W_U8) launch_first_wk<W_U8, true>(bin, variant, dim3(blocks), st, a);
+    else launch_first_wk<W_U32, true>(bin, variant, dim3(blocks), st, a);
+  } else {
+    if (wk == W_UNIT) launch_first_wk<W_UNIT, false>(bin, variant, dim3(blocks), st, a);
+    else if (wk == W_U8) launch_first_wk<W_U8, false>(bin, variant, dim3(blocks), st, a);
+    else launch_first_wk<W_U32, false>(bin, variant, dim3(blocks), st, a);
+  }
 }
 
 void launch_hub_first_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h) {

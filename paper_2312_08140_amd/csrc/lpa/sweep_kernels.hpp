@@ -35,7 +35,7 @@ void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, int tile_b
 int hub_plan_tiles(int64_t entries);  // tiles of the hub plan for that many frontier hubs
 void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
 // snapshot first sweep (first_sweep.hip)
-void launch_first_bin(int bin, int variant, int wk, int blocks, hipStream_t st, const ScanArgs &a);
+void launch_first_bin(int bin, int variant, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a);
 void launch_hub_first_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
 void launch_hub_part(int blocks, bool feat, hipStream_t st, const ScanArgs &a, const HubArgs &h);
 void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, bool feat, hipStream_t st, const ScanArgs &a,

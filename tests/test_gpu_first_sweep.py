@@ -169,9 +169,12 @@ def test_snapshot_runs_keep_quality(seed):
             q = G.modularity(lab)
             say(f"n={g.n} flags={flags} q_async={q:.4f} q_det={q_det:.4f} sweeps={st['iterations']}")
             assert abs(q - q_det) <= 0.01
-        # the gate's features are not written by the snapshot kernels: a trace run falls back
+        # with the gate's features on, the bin kernels still read the snapshot; hubs keep their kernels
         lab, st = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_TRACE)
-        assert st["first_edges"] == 0
+        hubs = int(np.count_nonzero(np.diff(g.offsets) > 512))
+        assert 0 < st["first_vertices"]
+        if seed == 1:  # every kernel but the hubs'
+            assert st["first_vertices"] + hubs == st["frontier"][0]
         G.close()
 
 
@@ -196,10 +199,12 @@ def test_autotune_reports_the_snapshot_choice():
     G = abi.LPAGraph(g)
     G.autotune(0.05, 20, ASYNC)
     sch = G.schedule()
-    assert sch[5] in (0, 1, 2, 3, ALL) and sch[6] == 1
+    assert sch[5] in (0, 1, 2, 3, 4, ALL) and sch[6] == 1
     lab, st = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_VERIFY)
     assert st["converged"] and st["verified"]
-    assert (st["first_edges"] > 0) == bool(sch[5])
+    assert st["first_edges"] <= st["edges_scanned"][0]
+    if sch[5] == 0:
+        assert st["first_edges"] == 0
     with pytest.raises(abi.LPAError):
         G.set_first_sweep(ALL + 1)
     G.close()
@@ -224,3 +229,69 @@ def test_snapshot_of_the_leading_kernel_only():
     assert st["first_edges"] == int(np.diff(g.offsets)[hubs].sum()) < st["edges_scanned"][0]
     assert sum(st["bin_edges"]) == st["edges_scanned"][0] - st["first_edges"]
     G.close()
+
+
+def test_snapshot_sweep_writes_gate_features():
+    """With the gate's features on, the snapshot bin kernels record them: the
+    samples of sweep 1 (every vertex, each from its sweep-0 record) equal the
+    features of the snapshot definition - log2(1 + deg), (W1 - W2) / K, 0 for
+    the own label, changed, W1 / K, distinct / deg with W1 >= W2 the two largest
+    entry weights - as a multiset of rows.  One step with the hubs first, so the
+    hub path (which keeps its own kernels here) also reads the initial labels."""
+    g = gg.rmat(12, 8, seed=43, weighted=True)
+    ref_lab = snapshot_reference(g)
+    off = np.asarray(g.offsets, np.int64)
+    idx = np.asarray(g.indices, np.int64)
+    w = np.asarray(g.weights).astype(np.int64)
+    rows = []
+    for v in range(g.n):
+        b, e = off[v], off[v + 1]
+        if e == b:
+            continue
+        ws = np.sort(w[b:e][idx[b:e] != v])[::-1]
+        K = float(w[b:e].sum())
+        w1 = float(ws[0]) if len(ws) else 0.0
+        w2 = float(ws[1]) if len(ws) > 1 else 0.0
+        rows.append([np.log2(1.0 + (e - b)), (w1 - w2) / K, 0.0, float(ref_lab[v] != v), 0.5, w1 / K,
+                     len(ws) / (e - b), 0.125])
+    ref = np.array(rows)
+    G = abi.LPAGraph(g)
+    G.set_bins([2, 8, 32, 128, 256, 512])
+    G.set_async_schedule(1, 0, 1)
+    G.set_first_sweep(ALL)
+    G.set_trace(1 << 20, 1.0)
+    labels, st = G.run(0.0, 2, ASYNC, True, flags=abi.LPA_FLAG_TRACE)
+    X, _ = G.gate_trace()
+    assert st["first_edges"] > 0 and st["first_edges"] < st["edges_scanned"][0]  # hubs kept their kernels
+    assert len(X) == len(ref)
+
+    assert rows_match(X.astype(np.float64), ref)
+    G.close()
+
+
+def rows_match(a, b, tol=1e-5):
+    """The rows of a and b are equal as multisets, within tol per entry.  Rows
+    are grouped by the integers the features encode (degree, changed, distinct
+    labels) and each row of b is matched with an unused row of a in its group
+    (near the same place once both are sorted), so that float rounding - W1 / K
+    of 2/5 and 4/10 differ in the last bit on the GPU - cannot misalign them."""
+    def keyed(x):
+        deg = np.rint(np.exp2(x[:, 0]) - 1.0)
+        nd = np.rint(x[:, 6] * deg)
+        o = np.lexsort((np.round(x[:, 1], 3), np.round(x[:, 5], 3), nd, x[:, 3], deg))
+        return x[o], np.column_stack([deg, x[:, 3], nd])[o]
+    if a.shape != b.shape:
+        return False
+    a, ka = keyed(a)
+    b, kb = keyed(b)
+    if not np.array_equal(ka, kb):
+        return False
+    used = np.zeros(len(a), bool)
+    for i in range(len(b)):
+        for j in range(max(0, i - 16), min(len(a), i + 17)):
+            if not used[j] and np.array_equal(ka[j], kb[i]) and np.allclose(a[j], b[i], rtol=tol, atol=tol):
+                used[j] = True
+                break
+        else:
+            return False
+    return True
