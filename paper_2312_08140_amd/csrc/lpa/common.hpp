@@ -50,12 +50,13 @@ constexpr int HUB_CHUNK_SLOTS = 4096;
 constexpr int HUB_PART_TARGET = 1024;
 constexpr int HUB_PART_CAP = 1536;
 constexpr int HUB_PART_SLOTS = 2048;
-constexpr int HUB_PART_GROUP = 16;       // partitions merged together when they hold few pairs
+constexpr int HUB_PART_GROUP_BITS = 4;   // most partitions merged together when they hold few pairs: 16
+constexpr int HUB_PART_GROUP = 1 << HUB_PART_GROUP_BITS;
 constexpr int HUB_PART_GROUP_MAX = 1024;  // most pairs of a merged group
 
-// Merge work items of a hub with 2^pbits partitions.
-__host__ __device__ constexpr int hub_merge_groups(int pbits) {
-  return (1 << pbits) > HUB_PART_GROUP ? (1 << pbits) / HUB_PART_GROUP : 1;
+// Merge work items of a hub with 2^pbits partitions, in groups of 2^gbits.
+__host__ __device__ constexpr int hub_merge_groups(int pbits, int gbits) {
+  return pbits > gbits ? 1 << (pbits - gbits) : 1;
 }
 constexpr int HUB_MAX_PBITS = 21;  // partitions for hubs of up to 2^31 entries
 constexpr int HUB_LDS_PBITS = 12;  // up to here the chunk kernel counts its partitions in LDS
@@ -314,6 +315,7 @@ struct HubArgs {
   uint32_t *own_w;           // FEAT: per frontier entry, weight of the hub's own label
   int32_t first;             // snapshot first sweep: k_hub_owner zeroes the partition maxima
   u64 *blk;                  // per tile of frontier hubs: work items (chunks, partitions, groups), then offsets
+  int32_t gbits;             // log2 partitions per merge group (0: every partition its own work item)
 };
 
 // Wave64 helpers.

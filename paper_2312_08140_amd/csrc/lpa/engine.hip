@@ -106,9 +106,10 @@ struct lpa_graph {
   int fcount_cap = 0;
   // hubs (sorted by id) and per-step scratch
   int32_t n_hubs = 0;
+  int32_t hub_gbits = HUB_PART_GROUP_BITS;  // merge groups of the sweep being emitted
   int64_t hub_chunks_total = 0, hub_parts_total = 0;
   int32_t hub_part_cap = HUB_PART_CAP;
-  std::vector<int32_t> h_hub_ids, h_hub_chunks, h_hub_parts;  // h_hub_parts: merge groups of each hub
+  std::vector<int32_t> h_hub_ids, h_hub_chunks, h_hub_parts;
   std::vector<int64_t> col_hub_chunks, col_hub_parts;  // per colour class (deterministic grids)
   std::vector<int32_t> h_color;
   int32_t *hub_ids = nullptr, *hub_chunks = nullptr, *hub_pbits = nullptr;
@@ -367,7 +368,7 @@ void build_hubs(lpa_graph *g) {
   g->n_hubs = (int32_t)nh;
   std::vector<int32_t> chunks(nh), pbits(nh);
   std::vector<int64_t> pair_base(nh), cnt_base(nh);
-  int64_t pairs = 0, parts = 0, groups = 0, nch = 0;
+  int64_t pairs = 0, parts = 0, nch = 0;
   for (size_t k = 0; k < nh; ++k) {
     const int64_t deg = g->h_off[ids[k] + 1] - g->h_off[ids[k]];
     chunks[k] = (int32_t)((deg + HUB_CHUNK - 1) / HUB_CHUNK);
@@ -378,17 +379,16 @@ void build_hubs(lpa_graph *g) {
     cnt_base[k] = parts;
     pairs += ((int64_t)1 << pb) * HUB_PART_CAP;
     parts += (int64_t)1 << pb;
-    groups += hub_merge_groups(pb);
     nch += chunks[k];
   }
   g->hub_chunks_total = nch;
   g->hub_parts_total = parts;
   g->hub_chunk_owner = dalloc_n<int32_t>(g, std::max<int64_t>(1, nch));
-  g->hub_group_owner = dalloc_n<int32_t>(g, std::max<int64_t>(1, groups));
+  g->hub_group_owner = dalloc_n<int32_t>(g, std::max<int64_t>(1, parts));  // groups of one partition at most
   g->h_hub_ids = ids;
   g->h_hub_chunks = chunks;
   g->h_hub_parts.resize(nh);
-  for (size_t k = 0; k < nh; ++k) g->h_hub_parts[k] = hub_merge_groups(pbits[k]);
+  for (size_t k = 0; k < nh; ++k) g->h_hub_parts[k] = 1 << pbits[k];  // bounds the merge work items of any group size
   const int64_t n1 = std::max<int64_t>(1, (int64_t)nh);
   g->hub_ids = dalloc_n<int32_t>(g, n1);
   g->hub_chunks = dalloc_n<int32_t>(g, n1);
@@ -443,6 +443,7 @@ HubArgs hub_args(lpa_graph *g) {
   h.chunk_owner = g->hub_chunk_owner;
   h.gstart = g->hub_gstart;
   h.blk = g->hub_blk;
+  h.gbits = g->hub_gbits;
   h.group_owner = g->hub_group_owner;
   h.changed = g->hub_changed;
   h.part_w2 = g->hub_part_w2;
@@ -673,7 +674,8 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
       HubArgs h = hub_args(g);
       h.first = 1;
       tk_begin(g, st);
-      launch_hub_plan(a, h, grid_cap(seg, 1, max_blocks), std::max(1, std::min(hub_plan_tiles(seg), max_blocks)), st);
+      launch_hub_plan(a, h, seg, grid_cap(seg, 1, max_blocks), std::max(1, std::min(hub_plan_tiles(seg), max_blocks)),
+                      st);
       tk_end(g, st, TK_HUB_PLAN);
       tk_begin(g, st);
       launch_hub_first_chunk(g->wk, grid_cap(hub_chunks, 1, max_blocks * 2), st, a, h);
@@ -686,7 +688,8 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
     } else if (b == HUB_BIN) {
       const HubArgs h = hub_args(g);
       tk_begin(g, st);
-      launch_hub_plan(a, h, grid_cap(seg, 1, max_blocks), std::max(1, std::min(hub_plan_tiles(seg), max_blocks)), st);
+      launch_hub_plan(a, h, seg, grid_cap(seg, 1, max_blocks), std::max(1, std::min(hub_plan_tiles(seg), max_blocks)),
+                      st);
       tk_end(g, st, TK_HUB_PLAN);
       tk_begin(g, st);
       launch_hub_chunk(g->wk, grid_cap(hub_chunks, 1, max_blocks * 2), st, a, h);
@@ -716,6 +719,9 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
 // (a run's first sweep in the asynchronous mode; the caller checks that the
 // run starts from the initial labels and that the rows allow it).
 void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late, int snap_kernels = 0) {
+  // the deterministic mode's colour steps hold few hubs each: every partition
+  // its own merge work item, merged in parallel (its steps are latency-bound)
+  g->hub_gbits = mode == LPA_MODE_DETERMINISTIC ? 0 : HUB_PART_GROUP_BITS;
   if (g->gate_active) {
     tk_begin(g, st);
     launch_gate_pass(g->ctl, g->gate_f, g->gate_z, g->cur_feat, g->F, g->gskip, g->n, g->cu_count, st);

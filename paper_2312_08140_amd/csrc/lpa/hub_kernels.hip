@@ -56,7 +56,7 @@ __global__ __launch_bounds__(PLAN_TILE) void k_hub_plan_tile(ScanArgs a, HubArgs
       } else {
         kc = (u64)h.chunks[lo];
         kp = (u64)1 << h.pbits[lo];
-        kg = (u64)hub_merge_groups(h.pbits[lo]);
+        kg = (u64)hub_merge_groups(h.pbits[lo], h.gbits);
       }
       h.ord[i] = lo;
       if (h.own_w) h.own_w[i] = 0;
@@ -144,6 +144,83 @@ __global__ __launch_bounds__(1024) void k_hub_plan_top(ScanArgs a, HubArgs h) {
   }
 }
 
+// The whole plan in one workgroup for a step with at most PLAN_TILE flagged
+// hubs (the usual case in the deterministic mode's colour classes): ordinals,
+// starts, totals and owner maps, with no tile offsets to add.
+__global__ __launch_bounds__(PLAN_TILE) void k_hub_plan_small(ScanArgs a, HubArgs h) {
+  if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
+  __shared__ u64 wsum[3][PLAN_TILE / 64];
+  __shared__ int s_k[PLAN_TILE];
+  __shared__ u64 s_start[3][PLAN_TILE];
+  if (threadIdx.x == 0) *h.ovf_count = 0;
+  const int count = *a.fcount;  // at most PLAN_TILE (the host launches this kernel only then)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = threadIdx.x;
+  u64 kc = 0, kp = 0, kg = 0;
+  if (i < count) {
+    const int v = a.front[i];
+    int lo = 0, hi = h.n_hubs;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (h.ids[mid] < v) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo >= h.n_hubs || h.ids[lo] != v) {
+      atomicOr(&a.ctl->error, 4);
+      lo = 0;
+    } else {
+      kc = (u64)h.chunks[lo];
+      kp = (u64)1 << h.pbits[lo];
+      kg = (u64)hub_merge_groups(h.pbits[lo], h.gbits);
+    }
+    h.ord[i] = lo;
+    s_k[i] = lo;
+    if (h.own_w) h.own_w[i] = 0;
+  }
+  u64 xc = kc, xp = kp, xg = kg;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const u64 yc = (u64)__shfl_up((unsigned long long)xc, d, 64);
+    const u64 yp = (u64)__shfl_up((unsigned long long)xp, d, 64);
+    const u64 yg = (u64)__shfl_up((unsigned long long)xg, d, 64);
+    if (lane >= d) {
+      xc += yc;
+      xp += yp;
+      xg += yg;
+    }
+  }
+  if (lane == 63) {
+    wsum[0][wv] = xc;
+    wsum[1][wv] = xp;
+    wsum[2][wv] = xg;
+  }
+  __syncthreads();
+  u64 bc = 0, bp = 0, bg = 0;
+  for (int k = 0; k < wv; ++k) {
+    bc += wsum[0][k];
+    bp += wsum[1][k];
+    bg += wsum[2][k];
+  }
+  if (i < count) {
+    s_start[0][i] = h.cstart[i] = bc + xc - kc;
+    s_start[1][i] = h.pstart[i] = bp + xp - kp;
+    s_start[2][i] = h.gstart[i] = bg + xg - kg;
+  }
+  if (i == PLAN_TILE - 1) {
+    a.ctl->hub_chunks = bc + xc;
+    a.ctl->hub_groups = bg + xg;
+  }
+  __syncthreads();
+  for (int q = 0; q < count; ++q) {
+    const int k = s_k[q];
+    const int nc = h.chunks[k], ng = hub_merge_groups(h.pbits[k], h.gbits);
+    for (int c = threadIdx.x; c < nc; c += PLAN_TILE) h.chunk_owner[s_start[0][q] + c] = q;
+    for (int gq = threadIdx.x; gq < ng; gq += PLAN_TILE) h.group_owner[s_start[2][q] + gq] = q;
+    if (h.first)
+      for (int p = threadIdx.x; p < (1 << h.pbits[k]); p += PLAN_TILE) h.partbest[s_start[1][q] + p] = 0;
+  }
+}
+
 // Owner maps of the step's work items (chunk / merge group -> frontier entry),
 // one workgroup per flagged hub.
 __global__ __launch_bounds__(256) void k_hub_owner(ScanArgs a, HubArgs h) {
@@ -151,7 +228,7 @@ __global__ __launch_bounds__(256) void k_hub_owner(ScanArgs a, HubArgs h) {
   const int count = *a.fcount;
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const int k = h.ord[i];
-    const int kc = h.chunks[k], kg = hub_merge_groups(h.pbits[k]);
+    const int kc = h.chunks[k], kg = hub_merge_groups(h.pbits[k], h.gbits);
     const u64 *off = h.blk + 3 * (i / PLAN_TILE);
     const u64 c0 = h.cstart[i] + off[0], p0 = h.pstart[i] + off[1], g0 = h.gstart[i] + off[2];
     __syncthreads();  // every thread has read the tile-relative starts
@@ -336,8 +413,8 @@ __device__ __forceinline__ int merge_parts(const ScanArgs &a, const HubArgs &h, 
   return err;
 }
 
-// One work item per aligned group of HUB_PART_GROUP partitions of a hub (all
-// of its partitions, if it has fewer).  Consecutive partitions that did not
+// One work item per aligned group of 2^gbits (at most HUB_PART_GROUP)
+// partitions of a hub (all of its partitions, if it has fewer).  Consecutive partitions that did not
 // spill are merged together while their pairs stay within
 // HUB_PART_GROUP_MAX (once labels have merged, usually the whole group in one
 // table); a partition that spilled is merged on its own.
@@ -356,7 +433,7 @@ __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
     const int i = h.group_owner[gq];
     const int k = h.ord[i];
     const int pb = h.pbits[k];
-    const int G = min(HUB_PART_GROUP, 1 << pb);
+    const int G = 1 << min(h.gbits, pb);
     const int g0 = (int)(gq - h.gstart[i]) * G;  // first partition of the group
     if ((int)threadIdx.x < G) s_cm[threadIdx.x] = h.pcnt[h.cnt_base[k] + g0 + threadIdx.x];
     __syncthreads();
@@ -447,7 +524,12 @@ __global__ __launch_bounds__(256) void k_hub_mark(ScanArgs a, HubArgs h) {
   block_accum<256>(0, 0, 0, n_marks, 0, a.ctl, a.bin);
 }
 
-void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, int tile_blocks, hipStream_t st) {
+void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int64_t max_hubs, int blocks, int tile_blocks,
+                     hipStream_t st) {
+  if (max_hubs <= PLAN_TILE) {
+    hipLaunchKernelGGL(k_hub_plan_small, dim3(1), dim3(PLAN_TILE), 0, st, a, h);
+    return;
+  }
   hipLaunchKernelGGL(k_hub_plan_tile, dim3(tile_blocks), dim3(PLAN_TILE), 0, st, a, h);
   hipLaunchKernelGGL(k_hub_plan_top, dim3(1), dim3(1024), 0, st, a, h);
   hipLaunchKernelGGL(k_hub_owner, dim3(blocks), dim3(256), 0, st, a, h);

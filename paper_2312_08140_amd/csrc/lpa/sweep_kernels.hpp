@@ -31,7 +31,9 @@ void launch_gate_pass(const Ctl *ctl, const float *gate, float z, const FeatArgs
                       uint8_t *skip, int64_t n, int cu_count, hipStream_t st);
 void launch_scan_bin(int bin, int variant, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a);
 int bin_vertices_per_block(int bin, int variant);
-void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int blocks, int tile_blocks, hipStream_t st);
+// max_hubs: most flagged hubs the step can have (its hub-bin segment)
+void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int64_t max_hubs, int blocks, int tile_blocks,
+                     hipStream_t st);
 int hub_plan_tiles(int64_t entries);  // tiles of the hub plan for that many frontier hubs
 void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
 // snapshot first sweep (first_sweep.hip)
