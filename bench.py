@@ -141,7 +141,10 @@ def _compare(G, gate_info, tau, max_iters, out, truth=None, plain=None):
         p_ms, sp, lp, qp = plain
     pv_ms, spv = _median_runs(G, tau, max_iters, abi.LPA_FLAG_VERIFY, out, 5)
     G.gate_load(gate_info["params"], gate_info["threshold"])
+    snap = G.schedule()[5]
+    G.set_first_sweep(0)  # gated runs: the first sweep the gate was traced with
     g_ms, sg = _median_runs(G, tau, max_iters, abi.LPA_FLAG_GATE, out, 5)
+    G.set_first_sweep(snap)
     lg = out.clone()
     qg = G.modularity(lg)
     r = {"plain_ms": round(p_ms, 3), "plain_verified_ms": round(pv_ms, 3), "gated_ms": round(g_ms, 3),
@@ -178,23 +181,37 @@ def _traces(graphs, cfg, probability, tau, max_iters):
             H.autotune(tau, max_iters, abi.LPA_MODE_ASYNC)
         elif cfg is not None:
             _apply(H, cfg)
+        H.set_first_sweep(0)  # see gate_comparison
         H.set_trace(1 << 24, probability)
         H.run(tau, max_iters, abi.LPA_MODE_ASYNC, True, flags=abi.LPA_FLAG_TRACE)
         x, y = H.gate_trace()
         H.close()
-        del g
+        del g, H
+        _release_cached()
         xs.append(x)
         ys.append(y)
     return np.concatenate(xs), np.concatenate(ys)
+
+
+def _release_cached():
+    """Device memory torch keeps cached goes back to the driver, where the
+    library's own allocations can use it."""
+    import torch
+    torch.cuda.empty_cache()
 
 
 def gate_comparison(args, G, runs, out, tuned, sec=None):
     """Learned active-set gate vs plain pruning.  The gate is trained on traces
     of 64 seeded plain runs - 32 SBM-1M graphs (seeds 100-131, mixing cycling
     0.1-0.4) for the SBM network and 32 R-MAT scale-24 graphs (seeds 100-131)
-    for the R-MAT network - disjoint from the evaluation graphs; it is then
+    for each R-MAT network (one per configuration it gates, traced under that
+    configuration) - disjoint from the evaluation graphs; it is then
     compared with plain runs on SBM-1M (seed 1, mixing 0.1-0.4), on R-MAT-24
-    (seed 1) and on the headline graph.  Training is outside every timed run."""
+    (seed 1) and on the headline graph.  Training is outside every timed run.
+    Traces and gated runs leave the snapshot first sweep off (every first-sweep
+    kernel reads the labels as the schedule delivers them): after a snapshot
+    sweep most labels still change in the next sweep, which leaves the gate
+    little to skip; plain runs keep their tuned configuration."""
     import torch
     from paper_2312_08140_amd import abi, gate, graphgen
     res = {}
@@ -228,28 +245,44 @@ def gate_comparison(args, G, runs, out, tuned, sec=None):
         log(f"sbm1m mu={mu}: {r}")
         H.close()
     res["sbm1m"] = rows
-    t = time.time()
-    X, y = _traces([lambda i=i: graphgen.rmat_device(24, 16, seed=100 + i, weighted=True) for i in range(32)],
-                   sec["tuning"] if sec else tuned, 0.05, args.tau, args.max_iters)
-    t_tr = time.time() - t
-    info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
-    res["rmat_gate"] = {"train_runs": "32 R-MAT scale 24 edge factor 16, seeds 100-131",
-                        "trace_config": sec["tuning"] if sec else tuned, "samples": int(len(y)),
-                        "positive_share": round(float(y.mean()), 4), "threshold": round(info["threshold"], 6),
-                        "holdout_recall": round(info["holdout_recall"], 4),
-                        "holdout_skip": round(info["holdout_skip"], 4), "trace_seconds": round(t_tr, 2),
-                        "seconds": round(time.time() - t, 2)}
-    log(f"rmat gate: {res['rmat_gate']}")
+    # one R-MAT network per configuration it is deployed with: the traces are
+    # recorded under the configuration (bins, bin order, snapshot first sweep)
+    # of the runs it will gate, since those set the label dynamics it learns
+    rmat_cfgs = [("head", tuned)]
+    if sec is not None:
+        rmat_cfgs.insert(0, ("secondary", sec["tuning"]))
+    gates = {}
+    for name, cfg in rmat_cfgs:
+        same = next((k for k, (c, _) in gates.items() if c is not None and cfg is not None and same_config(c, cfg)),
+                    None)
+        if same is not None or (cfg is None and gates):
+            gates[name] = gates[same if same is not None else next(iter(gates))]
+            continue
+        t = time.time()
+        X, y = _traces([lambda i=i: graphgen.rmat_device(24, 16, seed=100 + i, weighted=True) for i in range(32)],
+                       cfg, 0.05, args.tau, args.max_iters)
+        t_tr = time.time() - t
+        info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
+        res[f"rmat_gate_{name}"] = {"train_runs": "32 R-MAT scale 24 edge factor 16, seeds 100-131",
+                                    "trace_config": cfg, "samples": int(len(y)),
+                                    "positive_share": round(float(y.mean()), 4),
+                                    "threshold": round(info["threshold"], 6),
+                                    "holdout_recall": round(info["holdout_recall"], 4),
+                                    "holdout_skip": round(info["holdout_skip"], 4), "trace_seconds": round(t_tr, 2),
+                                    "seconds": round(time.time() - t, 2)}
+        log(f"rmat gate ({name} configuration): {res[f'rmat_gate_{name}']}")
+        gates[name] = (cfg, info)
     if sec is not None:
         d = graphgen.rmat_device(args.secondary_scale, args.secondary_edge_factor, seed=args.seed, weighted=True)
         H = abi.LPAGraph(n=d.n, offsets=d.offsets, indices=d.indices, weights=d.weights)
         _apply(H, sec["tuning"])
         o = torch.empty(d.n, dtype=torch.int32, device="cuda:0")
-        r = _compare(H, info, args.tau, args.max_iters, o)
+        r = _compare(H, gates["secondary"][1], args.tau, args.max_iters, o)
         res[f"rmat{args.secondary_scale}"] = r
         log(f"rmat{args.secondary_scale} gated: {r}")
         H.close()
         del d
+    info = gates["head"][1]
     p_ms = float(np.median([r["total_ms"] for r in runs]))
     lp = out.clone()
     G.run(args.tau, args.max_iters, abi.LPA_MODE_ASYNC, True, labels_out=lp)
@@ -381,12 +414,49 @@ def roofline_of(G, args, out, tuned, workload):
             "per_kernel": per_kernel}
 
 
+def storage_order_indices(d):
+    """The neighbour indices as the library stores them: vertices renumbered
+    in decreasing degree order (ties by id) and every row sorted by neighbour
+    position.  Built with torch in chunks of at most 2^28 entries."""
+    import torch
+    n, m = d.n, d.m
+    off = d.offsets.long()
+    deg = off[1:] - off[:-1]
+    order = torch.argsort(-deg, stable=True)
+    rank = torch.empty(n, dtype=torch.int64, device=off.device)
+    rank[order] = torch.arange(n, device=off.device)
+    ndeg = deg[order]
+    noff = torch.zeros(n + 1, dtype=torch.int64, device=off.device)
+    noff[1:] = torch.cumsum(ndeg, 0)
+    shift = max(1, (n - 1).bit_length())
+    new_idx = torch.empty(m, dtype=torch.int32, device=off.device)
+    hoff = noff.cpu().numpy()
+    p = 0
+    while p < n:
+        q = max(p + 1, int(np.searchsorted(hoff, hoff[p] + (1 << 28), side="right")) - 1)
+        q = min(q, n)
+        e0, e1 = int(hoff[p]), int(hoff[q])
+        if e1 > e0:
+            row_of = torch.repeat_interleave(torch.arange(p, q, device=off.device), ndeg[p:q])
+            src = off[order[row_of]] + (torch.arange(e1 - e0, device=off.device) - (noff[row_of] - e0))
+            key = ((row_of - p) << shift) | rank[d.indices[src].long()]
+            del row_of, src
+            key = torch.sort(key)[0]
+            new_idx[e0:e1] = (key & ((1 << shift) - 1)).to(torch.int32)
+            del key
+        p = q
+    del rank, order, noff, deg, ndeg
+    return new_idx
+
+
 def gather_ceiling(d, reps=3):
     """What a label gather alone costs on this graph: torch's index_select of a
-    label array by the stored neighbour indices (4 B index read, 4 B label
-    gather, 4 B output write per entry), in the CSR order of the generator and
-    with the same indices sorted (every gather then walks the label array in
-    order).  A ceiling for any kernel that gathers one label per entry."""
+    label array by the neighbour indices (4 B index read, 4 B label gather,
+    4 B output write per entry) - in the generator's CSR order, in the order
+    the library stores the graph (decreasing degree, sorted rows: the order its
+    kernels gather in), and, where it fits, with all indices sorted (every
+    gather then walks the label array in order).  A ceiling for any kernel
+    that gathers one label per entry in that order."""
     import torch
     C = torch.arange(d.n, dtype=torch.int32, device="cuda:0")
     res = {}
@@ -405,6 +475,10 @@ def gather_ceiling(d, reps=3):
         return {"ms": round(ms, 3), "entries_per_s": round(d.m / (ms * 1e-3), 1),
                 "gb_per_s_12B_per_entry": round(12 * d.m / (ms * 1e-3) / 1e9, 1)}
     res["csr_order"] = timed(d.indices)
+    si = storage_order_indices(d)
+    res["storage_order"] = timed(si)
+    del si
+    torch.cuda.empty_cache()
     if d.m <= (1 << 30):
         srt = torch.sort(d.indices)[0]
         res["sorted_indices"] = timed(srt)

@@ -201,15 +201,15 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
  * step: every flagged vertex at once) it installs the fastest whose runs
  * converge (a batch: every graph) and whose modularity stays within 0.002 of
  * the first's; the first stays when no other qualifies (schedule_out: int32[3],
- * may be NULL); then, on a graph with hubs, whether the hub bin runs last in
- * each step (lpa_set_bin_order) together with, where the rows allow it, how
- * many kernels of each step of the first sweep read the initial labels (none,
- * 1, 2, 3, 4 or all; lpa_set_first_sweep; read both back with
- * lpa_get_schedule).  Then the
- * degree limits of the bins (lpa_set_bins): each
+ * may be NULL).  Then the degree limits of the bins (lpa_set_bins): each
  * bin's LDS table has a fixed size (8, 32, 128, 512, 2048, 8192 slots), and
  * the candidates let it fill to at most 1/2 (the default), 1/4, 3/4 or all of
- * them; the fastest is installed and returned in bins_out (int32[6], may be
+ * them; in the asynchronous mode each candidate is timed together with the
+ * order of the bins in a step (lpa_set_bin_order; on a graph with hubs) and,
+ * where the rows allow it, the kernels of each step of the first sweep that
+ * read the initial labels (lpa_set_first_sweep: none, 1, 3 or all, then 2 and
+ * 4 next to the best); the fastest combination is installed (read it back with
+ * lpa_get_schedule) and its limits returned in bins_out (int32[6], may be
  * NULL).  Then it times every kernel
  * shape variant (per-kernel timing), keeps for each bin the fastest and
  * returns it in variant_out (int32[6], may be NULL) with the chosen kernels'

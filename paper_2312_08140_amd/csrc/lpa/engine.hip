@@ -152,7 +152,7 @@ struct lpa_graph {
   int64_t tcap = 0;
   uint32_t tthresh = 0xFFFFFFFFu;
   // memory
-  std::vector<void *> owned;
+  std::vector<std::pair<void *, size_t>> owned;  // device allocations and their sizes
   size_t budget = 0, used = 0;
   int cu_count = 256;
   // batched handle (graph g owns vertices [bvptr[g], bvptr[g+1]))
@@ -178,15 +178,16 @@ void *dalloc(lpa_graph *g, size_t bytes) {
     (void)hipGetLastError();
     throw Status{LPA_ERR_OUT_OF_MEMORY};
   }
-  g->owned.push_back(p);
+  g->owned.emplace_back(p, bytes);
   g->used += bytes;
   return p;
 }
 
 void dfree(lpa_graph *g, void *p) {
   if (!p) return;
-  auto it = std::find(g->owned.begin(), g->owned.end(), p);
+  auto it = std::find_if(g->owned.begin(), g->owned.end(), [p](const auto &o) { return o.first == p; });
   if (it != g->owned.end()) {
+    g->used -= it->second;
     g->owned.erase(it);
     (void)hipFree(p);
   }
@@ -882,7 +883,7 @@ void lpa_destroy(lpa_graph *g) {
     (void)hipEventDestroy(p.first);
     (void)hipEventDestroy(p.second);
   }
-  for (void *p : g->owned) (void)hipFree(p);
+  for (auto &o : g->owned) (void)hipFree(o.first);
   if (g->host_done) (void)hipHostFree(g->host_done);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   delete g;
@@ -1264,8 +1265,9 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
   double q_ref = 0.0;
   bool have_ref = false;
   auto quality_ok = [&](double q) { return !have_ref || q >= q_ref - 0.002; };
-  // the reference runs: hubs first, labels read as the schedule delivers them
+  // the reference runs: default bins, hubs first, labels read as the schedule delivers them
   rc = lpa_set_first_sweep(g, 0);
+  if (rc == LPA_OK) rc = lpa_set_bins(g, nullptr, 0);
   if (rc == LPA_OK && mode == LPA_MODE_ASYNC) rc = lpa_set_bin_order(g, 0);
   if (rc != LPA_OK) return rc;
   // 1. Asynchronous schedule: the fastest candidate whose runs converge (for
@@ -1303,45 +1305,6 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
     rc = lpa_set_async_schedule(g, cand[best][0], cand[best][1], cand[best][2], g->async_by_colour ? 1 : 0);
     if (rc != LPA_OK) return rc;
     if (schedule_out) std::memcpy(schedule_out, cand[best], sizeof(cand[best]));
-    // 1b. Order of the bins inside a step - hubs first (the default) or last,
-    //     after the other vertices have updated their labels (fewer distinct
-    //     labels reach the hubs' partitions) - together with the snapshot
-    //     first sweep where the rows allow it (lpa_set_first_sweep: the first
-    //     1, 2, 3, 4 or all kernels of each step of the first sweep read the
-    //     initial labels; cheap to read, but a sweep whose vertices all read
-    //     them merges fewer labels, which can cost a sweep later on).  Same
-    //     acceptance rules, in this order.
-    {
-      static const int32_t snap_cand[] = {0, 1, 2, 3, 4, NBINS};
-      const int n_snap = g->rows_strict ? (int)(sizeof(snap_cand) / sizeof(snap_cand[0])) : 1;
-      int32_t best_order = 0, best_snap = 0;
-      for (int32_t order = 0; order <= (g->n_hubs > 0 ? 1 : 0); ++order)
-        for (int c = 0; c < n_snap; ++c) {
-          if (order == 0 && snap_cand[c] == 0) continue;  // the configuration of step 1
-          rc = lpa_set_bin_order(g, order);
-          if (rc == LPA_OK) rc = lpa_set_first_sweep(g, snap_cand[c]);
-          if (rc != LPA_OK) return rc;
-          double ms = 1e300, q = 0.0;
-          bool converged = true;
-          for (int rep = 0; rep < 2; ++rep) {
-            lpa_stats st;
-            rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
-            if (rc != LPA_OK) return rc;
-            ms = std::min(ms, st.total_ms);
-            converged = converged && st.converged;
-          }
-          rc = lpa_modularity(g, nullptr, 0, &q);
-          if (rc != LPA_OK) return rc;
-          if (converged && quality_ok(q) && ms < 0.97 * best_ms) {
-            best_ms = ms;
-            best_order = order;
-            best_snap = snap_cand[c];
-          }
-        }
-      rc = lpa_set_bin_order(g, best_order);
-      if (rc == LPA_OK) rc = lpa_set_first_sweep(g, best_snap);
-      if (rc != LPA_OK) return rc;
-    }
   } else if (schedule_out) {
     schedule_out[0] = g->sched[0].nphase;
     schedule_out[1] = g->early_sweeps;
@@ -1351,37 +1314,80 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
   //    limit sets how full the table can get: the candidates fill the tables
   //    to at most 1/2 (the default), 1/4, 3/4 or all of their slots.  A lower
   //    limit gives the bin's rows sparser tables (shorter probe chains) and
-  //    sends more rows to the next, wider bin.
+  //    sends more rows to the next, wider bin.  In the asynchronous mode the
+  //    limits also set which vertices a kernel processes together, and so
+  //    which labels they see; they are tuned together with the order of the
+  //    bins inside a step - hubs first (the default) or last, after the other
+  //    vertices have updated their labels (fewer distinct labels reach the
+  //    hubs' partitions) - and, where the rows allow it, the snapshot first
+  //    sweep (lpa_set_first_sweep: the first 1, 3 or all kernels of each step
+  //    of the first sweep read the initial labels; cheap to read, but a sweep
+  //    whose vertices all read them merges fewer labels, which can cost a
+  //    sweep later on; 2 and 4 kernels are then tried around the best).  Every
+  //    combination is timed in this order under the same acceptance rules.
   {
     static const int32_t lim_cand[][NBINS - 1] = {{4, 16, 64, 256, 1024, 4096},
                                                   {2, 8, 32, 128, 512, 2048},
                                                   {6, 24, 96, 384, 1536, 6144},
                                                   {7, 31, 127, 511, 2047, 8191}};
+    const bool async = mode == LPA_MODE_ASYNC;
+    static const int32_t snap_cand[] = {0, 1, 3, NBINS};
+    const int n_snap = async && g->rows_strict ? (int)(sizeof(snap_cand) / sizeof(snap_cand[0])) : 1;
+    const int n_order = async && g->n_hubs > 0 ? 2 : 1;
     double best_ms = 1e300;
-    int best = 0;
-    for (int c = 0; c < (int)(sizeof(lim_cand) / sizeof(lim_cand[0])); ++c) {
-      rc = lpa_set_bins(g, lim_cand[c], NBINS - 1);
-      if (rc != LPA_OK) return rc;
-      double ms = 1e300, q = 0.0;
+    int best = 0, best_order = 0, best_snap = 0;
+    // one configuration: converged (every graph of a batch) and within the
+    // quality bar in the asynchronous mode; its faster run of two
+    auto trial = [&](int c, int order, int snap, double &ms) -> int {
+      int r = lpa_set_bins(g, lim_cand[c], NBINS - 1);
+      if (r == LPA_OK && async) r = lpa_set_bin_order(g, order);
+      if (r == LPA_OK && async) r = lpa_set_first_sweep(g, snap);
+      if (r != LPA_OK) return r;
+      ms = 1e300;
       bool converged = true;
       for (int rep = 0; rep < 2; ++rep) {
         lpa_stats st;
-        rc = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
-        if (rc != LPA_OK) return rc;
+        r = lpa_run(g, tolerance, max_iters, mode, 1, 0, nullptr, nullptr, nullptr, &st);
+        if (r != LPA_OK) return r;
         ms = std::min(ms, st.total_ms);
         converged = converged && st.converged;
       }
-      if (mode == LPA_MODE_ASYNC) {
-        rc = lpa_modularity(g, nullptr, 0, &q);
+      double q = 0.0;
+      if (async) {
+        r = lpa_modularity(g, nullptr, 0, &q);
+        if (r != LPA_OK) return r;
+      }
+      const bool first = c == 0 && order == 0 && snap == 0;
+      if (!(first || (converged && (!async || quality_ok(q))))) ms = 1e300;
+      return LPA_OK;
+    };
+    for (int c = 0; c < (int)(sizeof(lim_cand) / sizeof(lim_cand[0])); ++c)
+      for (int order = 0; order < n_order; ++order)
+        for (int k = 0; k < n_snap; ++k) {
+          double ms = 0.0;
+          rc = trial(c, order, snap_cand[k], ms);
+          if (rc != LPA_OK) return rc;
+          if (ms < 0.97 * best_ms) {
+            best_ms = ms;
+            best = c;
+            best_order = order;
+            best_snap = snap_cand[k];
+          }
+        }
+    if (n_snap > 1)
+      for (int32_t snap : {best_snap - 1, best_snap + 1}) {
+        if (snap <= 0 || snap >= NBINS || snap == 1 || snap == 3) continue;  // 2 and 4 only
+        double ms = 0.0;
+        rc = trial(best, best_order, snap, ms);
         if (rc != LPA_OK) return rc;
+        if (ms < 0.97 * best_ms) {
+          best_ms = ms;
+          best_snap = snap;
+        }
       }
-      const bool ok = c == 0 || (converged && (mode != LPA_MODE_ASYNC || quality_ok(q)));
-      if (ok && ms < 0.97 * best_ms) {
-        best_ms = ms;
-        best = c;
-      }
-    }
     rc = lpa_set_bins(g, lim_cand[best], NBINS - 1);
+    if (rc == LPA_OK && async) rc = lpa_set_bin_order(g, best_order);
+    if (rc == LPA_OK && async) rc = lpa_set_first_sweep(g, best_snap);
     if (rc != LPA_OK) return rc;
     if (bins_out) std::memcpy(bins_out, lim_cand[best], sizeof(lim_cand[best]));
   }

@@ -83,6 +83,16 @@ class _Arrays:
         a, c = self.arrays[kind]
         return a[:c]
 
+    def take(self):
+        """The three arrays (offsets, indices, weights); drops the holder's own
+        references and its callback, which refers back to the holder, so the
+        arrays are freed with their last user rather than at a later garbage
+        collection."""
+        out = (self.get(0), self.get(1), self.get(2))
+        self.arrays = {}
+        self.cb = None
+        return out
+
 
 def _weighted_code(weighted) -> int:
     # 1: weights 1..8 from a hash of the unordered pair; 0: an all-ones fp32 array; -1: None (unit)
@@ -99,7 +109,7 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c:
                      ctypes.byref(n), ctypes.byref(m))
     if rc != 0:
         raise ValueError(f"gg_rmat failed ({rc})")
-    return CSR(n.value, arr.get(0), arr.get(1), arr.get(2),
+    return CSR(n.value, *arr.take(),
                name=f"rmat{scale}_ef{edge_factor}_s{seed}",
                meta=dict(kind="rmat", scale=scale, edge_factor=edge_factor, a=a, b=b, c=c, seed=seed))
 
@@ -118,7 +128,7 @@ def sbm(n: int, blocks: int, p_in: float, p_out: float, seed: int = 1, weighted=
     rc = lib.gg_sbm(n, blocks, p_in, p_out, seed, _weighted_code(weighted), direct, arr.cb, ctypes.byref(m))
     if rc != 0:
         raise ValueError(f"gg_sbm failed ({rc})")
-    g = CSR(n, arr.get(0), arr.get(1), arr.get(2), name=f"sbm{n}_k{blocks}_s{seed}",
+    g = CSR(n, *arr.take(), name=f"sbm{n}_k{blocks}_s{seed}",
             meta=dict(kind="sbm", blocks=blocks, p_in=p_in, p_out=p_out, seed=seed))
     return g
 
@@ -134,7 +144,7 @@ def grid(rows: int, cols: int, p_keep: float = 0.55, seed: int = 1, weighted=Fal
     rc = lib.gg_grid(rows, cols, p_keep, seed, _weighted_code(weighted), arr.cb, ctypes.byref(n), ctypes.byref(m))
     if rc != 0:
         raise ValueError(f"gg_grid failed ({rc})")
-    return CSR(n.value, arr.get(0), arr.get(1), arr.get(2), name=f"grid{rows}x{cols}_p{p_keep}_s{seed}",
+    return CSR(n.value, *arr.take(), name=f"grid{rows}x{cols}_p{p_keep}_s{seed}",
                meta=dict(kind="grid", rows=rows, cols=cols, p_keep=p_keep, seed=seed))
 
 
@@ -181,7 +191,7 @@ def sbm_batch(count: int = 4096, master_seed: int = 7, seed_base: int = 10000, n
                           ctypes.byref(n), ctypes.byref(m))
     if rc != 0:
         raise ValueError(f"gg_sbm_batch failed ({rc})")
-    g = CSR(n.value, arr.get(0), arr.get(1), arr.get(2), name=f"sbmbatch{count}_s{master_seed}",
+    g = CSR(n.value, *arr.take(), name=f"sbmbatch{count}_s{master_seed}",
             meta=dict(kind="sbm_batch", count=count, master_seed=master_seed, k_g=k_g))
     return g, vptr
 
@@ -278,6 +288,16 @@ class _DeviceArrays:
         a, c = self.arrays[kind]
         return a[:c]
 
+    def take(self):
+        """The three arrays (offsets, indices, weights); drops the holder's own
+        references and its callback, which refers back to the holder, so the
+        arrays are freed with their last user rather than at a later garbage
+        collection."""
+        out = (self.get(0), self.get(1), self.get(2))
+        self.arrays = {}
+        self.cb = None
+        return out
+
 
 def rmat_device(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
                 seed: int = 1, weighted=True, device: int = 0) -> DeviceCSR:
@@ -292,7 +312,7 @@ def rmat_device(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0
                         ctypes.byref(n), ctypes.byref(m))
     if rc != 0:
         raise RuntimeError(f"gvgen_rmat failed: {lib.gvgen_status_string(rc).decode()} ({rc})")
-    return DeviceCSR(n.value, arr.get(0), arr.get(1), arr.get(2), name=f"rmat{scale}_ef{edge_factor}_s{seed}",
+    return DeviceCSR(n.value, *arr.take(), name=f"rmat{scale}_ef{edge_factor}_s{seed}",
                      meta=dict(kind="rmat", scale=scale, edge_factor=edge_factor, a=a, b=b, c=c, seed=seed))
 
 

@@ -116,3 +116,23 @@ def test_committed_profiles_name_their_configuration():
         d = json.loads(lines[0][len("machine-readable: "):])
         assert len(d["sources"]) == 16 and len(d["variants"]) == 6 and len(d["schedule"]) == 3
         assert len(d["bins"]) == 6 and d["bytes_per_launch"]
+
+
+def test_storage_order_indices_match_the_library_layout():
+    """The gather ceiling's index order: vertices in decreasing degree (ties
+    by id), each row's neighbours renamed to positions and sorted - checked
+    against a plain numpy construction (torch on the CPU)."""
+    import types
+    import numpy as np
+    import torch
+    from paper_2312_08140_amd import graphgen as gg
+    g = gg.rmat(10, 8, seed=3, weighted=False)
+    d = types.SimpleNamespace(n=g.n, m=g.m, offsets=torch.from_numpy(g.offsets.astype(np.int64)),
+                              indices=torch.from_numpy(g.indices.astype(np.int32)))
+    got = bench.storage_order_indices(d).numpy()
+    deg = np.diff(g.offsets)
+    order = np.argsort(-deg, kind="stable")
+    pos = np.empty(g.n, np.int64)
+    pos[order] = np.arange(g.n)
+    want = np.concatenate([np.sort(pos[g.indices[g.offsets[v]:g.offsets[v + 1]]]) for v in order])
+    assert np.array_equal(got, want.astype(np.int32))
