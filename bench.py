@@ -414,7 +414,7 @@ def roofline_of(G, args, out, tuned, workload):
             "per_kernel": per_kernel}
 
 
-def storage_order_indices(d):
+def storage_order_indices(d, with_offsets=False):
     """The neighbour indices as the library stores them: vertices renumbered
     in decreasing degree order (ties by id) and every row sorted by neighbour
     position.  Built with torch in chunks of at most 2^28 entries."""
@@ -445,23 +445,28 @@ def storage_order_indices(d):
             new_idx[e0:e1] = (key & ((1 << shift) - 1)).to(torch.int32)
             del key
         p = q
-    del rank, order, noff, deg, ndeg
+    del rank, order, deg
+    if with_offsets:
+        return new_idx, noff, ndeg
     return new_idx
 
 
-def gather_ceiling(d, reps=3):
+def gather_ceiling(d, reps=3, bins=None):
     """What a label gather alone costs on this graph: torch's index_select of a
     label array by the neighbour indices (4 B index read, 4 B label gather,
     4 B output write per entry) - in the generator's CSR order, in the order
     the library stores the graph (decreasing degree, sorted rows: the order its
     kernels gather in), and, where it fits, with all indices sorted (every
     gather then walks the label array in order).  A ceiling for any kernel
-    that gathers one label per entry in that order."""
+    that gathers one label per entry in that order.  With the bin degree limits,
+    also the storage-order gather of each bin's entries on its own (the bins
+    are contiguous ranges of that order)."""
     import torch
     C = torch.arange(d.n, dtype=torch.int32, device="cuda:0")
     res = {}
 
-    def timed(idx):
+    def timed(idx, count=None):
+        count = d.m if count is None else count
         out = torch.index_select(C, 0, idx)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -472,12 +477,26 @@ def gather_ceiling(d, reps=3):
         torch.cuda.synchronize()
         del out
         ms = e0.elapsed_time(e1) / reps
-        return {"ms": round(ms, 3), "entries_per_s": round(d.m / (ms * 1e-3), 1),
-                "gb_per_s_12B_per_entry": round(12 * d.m / (ms * 1e-3) / 1e9, 1)}
+        return {"ms": round(ms, 3), "entries_per_s": round(count / (ms * 1e-3), 1),
+                "gb_per_s_12B_per_entry": round(12 * count / (ms * 1e-3) / 1e9, 1)}
     res["csr_order"] = timed(d.indices)
-    si = storage_order_indices(d)
+    si, noff, ndeg = storage_order_indices(d, with_offsets=True)
     res["storage_order"] = timed(si)
-    del si
+    if bins is not None:
+        # vertices of bin b: degree in (bins[b-1], bins[b]] (bin 0 from 1), hubs above bins[5]
+        lims = [0] + list(bins)
+        per = {}
+        for name, lo, hi in [("hubs", lims[-1], None)] + [(f"bin{b}", lims[b], lims[b + 1]) for b in range(5, -1, -1)]:
+            sel = (ndeg > lo) if hi is None else ((ndeg > lo) & (ndeg <= hi))
+            nz = torch.nonzero(sel).flatten()
+            if nz.numel() == 0:
+                continue
+            e0, e1 = int(noff[int(nz[0])]), int(noff[int(nz[-1]) + 1])
+            if e1 > e0:
+                per[name] = timed(si[e0:e1].contiguous(), e1 - e0)
+                per[name]["entries"] = e1 - e0
+        res["storage_order_by_bin"] = per
+    del si, noff, ndeg
     torch.cuda.empty_cache()
     if d.m <= (1 << 30):
         srt = torch.sort(d.indices)[0]
@@ -550,7 +569,7 @@ def secondary_rmat(args):
     res["verified"] = bool(sv["verified"])
     res["verify_changed"] = int(sv["verify_changed"])
     res["roofline"] = roofline_of(G, args, out, tuned, wl)
-    res["roofline"]["gather_ceiling"] = gather_ceiling(d)
+    res["roofline"]["gather_ceiling"] = gather_ceiling(d, bins=tuned["bins"] if tuned else None)
     if not args.no_det:
         res["deterministic"], q_det = deterministic_of(G, args, out, d.m, tuned)
         res["q_async_minus_det"] = round(res["modularity"] - q_det, 6)
@@ -719,7 +738,7 @@ def main():
               "modularity": round(G.modularity(out), 6)}
     roofline = roofline_of(G, args, out, tuned, workload)
     log(f"dominant kernel {roofline['kernel']}: {roofline['achieved']:.0f} GB/s ({roofline['frac'] * 100:.1f}% of peak)")
-    roofline["gather_ceiling"] = gather_ceiling(d)
+    roofline["gather_ceiling"] = gather_ceiling(d, bins=tuned["bins"] if tuned else None)
     log(f"gather ceiling: {roofline['gather_ceiling']}")
 
     det, q_det = (None, None)

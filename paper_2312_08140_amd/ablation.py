@@ -71,8 +71,9 @@ def gpu_rows(name, g, reps=3):
     out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
     t = time.time()
     v, _, sch, lim = G.autotune(BASE["tau"], BASE["max_iters"], abi.LPA_MODE_ASYNC)
-    tuning = {"variants": [int(x) for x in v], "schedule": list(sch), "bins": list(lim),
-              "seconds": round(time.time() - t, 2)}
+    full = G.schedule()
+    tuning = {"variants": [int(x) for x in v], "schedule": list(sch), "bins": list(lim), "hubs_last": full[4],
+              "snapshot": full[5], "seconds": round(time.time() - t, 2)}
     rows = {}
     for label, change in VARIANTS + [("untuned_defaults", {}), ("deterministic", {})]:
         p = dict(BASE, **change)
@@ -81,6 +82,8 @@ def gpu_rows(name, g, reps=3):
             G.set_variants(None)
             G.set_bins(None)
             G.set_async_schedule()
+            G.set_bin_order(0)
+            G.set_first_sweep(0)
         flags = 0 if p["strict"] else abi.LPA_FLAG_NONSTRICT
         G.run(p["tau"], p["max_iters"], mode, p["prune"], flags=flags, labels_out=out)  # warm-up
         ms, st = [], None
