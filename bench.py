@@ -222,7 +222,7 @@ def gate_comparison(args, G, runs, out, tuned, sec=None):
     X, y = _traces([lambda i=i, mu=mu: _sbm1m(mu, 100 + i) for i, mu in enumerate((0.1, 0.2, 0.3, 0.4) * 8)],
                    sbm_cfg, 0.1, args.tau, args.max_iters)
     t_tr = time.time() - t
-    info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
+    info = sbm_info = gate.train(X, y, epochs=4, batch=4096, lr=1e-3, recall=0.98, seed=0)
     res["sbm_gate"] = {"train_runs": 32, "trace_config": "each handle autotuned" if sbm_cfg else "default",
                        "samples": int(len(y)),
                        "positive_share": round(float(y.mean()), 4), "threshold": round(info["threshold"], 6),
@@ -289,13 +289,15 @@ def gate_comparison(args, G, runs, out, tuned, sec=None):
     r = _compare(G, info, args.tau, args.max_iters, out, plain=(p_ms, runs[-1], lp, G.modularity(lp)))
     res[f"rmat{args.scale}"] = r
     log(f"rmat{args.scale} gated: {r}")
-    return res
+    return res, sbm_info
 
 
-def batch_workload(args):
+def batch_workload(args, gate_info=None):
     """Many independent SBMs of uneven size in one handle (block-diagonal CSR,
     each graph with its own stop test, every run one HIP graph launch):
-    default tuning vs autotuned, asynchronous and deterministic."""
+    default tuning vs autotuned, asynchronous and deterministic; with a gate
+    (the SBM network of gate_comparison, trained on SBM-1M traces), plain vs
+    gated, every graph verified on its own."""
     import torch
     from paper_2312_08140_amd import abi, graphgen
     t = time.time()
@@ -327,6 +329,15 @@ def batch_workload(args):
         res["tuning"] = {"variants": [int(x) for x in v], "schedule": list(sch), "bins": list(lim),
                          "seconds": round(time.time() - t, 2)}
         res["async_tuned"] = timed(abi.LPA_MODE_ASYNC, "async tuned")
+    if gate_info is not None:
+        r = _compare(B, gate_info, args.tau, args.max_iters, out)
+        ok, vch = B.verify_stats()
+        it, conv = B.graph_stats()
+        r.update({"graphs_verified": int(ok.sum()), "graphs_converged": int(conv.sum()),
+                  "graph_sweeps_mean": round(float(it.mean()), 3)})
+        res["gated"] = r
+        log(f"batch gated: {r}")
+    if not args.no_tune:
         t = time.time()
         dv, _, _, dlim = B.autotune(args.tau, args.max_iters, abi.LPA_MODE_DETERMINISTIC)
         res["det_tuning"] = {"variants": [int(x) for x in dv], "bins": list(dlim), "seconds": round(time.time() - t, 2)}
@@ -750,13 +761,13 @@ def main():
     if args.secondary_scale:
         secondary, sec_dev, _ = secondary_rmat(args)
 
-    gated = None
+    gated, sbm_info = None, None
     if not args.no_gate:
-        gated = gate_comparison(args, G, runs, out, tuned, secondary)
+        gated, sbm_info = gate_comparison(args, G, runs, out, tuned, secondary)
 
     batch, batch_in = None, None
     if args.batch:
-        batch, batch_in = batch_workload(args)
+        batch, batch_in = batch_workload(args, sbm_info)
 
     head_host = None
     if not args.no_cpu:

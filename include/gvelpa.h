@@ -91,9 +91,11 @@ enum {
 
 /* Per-run statistics.  Per-sweep arrays hold the first 64 sweeps. */
 typedef struct {
-  int32_t iterations;  /* lpaMove() calls executed (Algorithm 1), verification sweeps excluded */
-  int32_t converged;   /* 1 if the stop test dN/N <= tau held */
-  int32_t verified;    /* LPA_FLAG_VERIFY: 1 if the verification sweep changed <= tau * n labels */
+  int32_t iterations;  /* lpaMove() calls executed (Algorithm 1), verification sweeps excluded (a batch:
+                          sweeps of the batch, every graph's verification sweeps included) */
+  int32_t converged;   /* 1 if the stop test dN/N <= tau held (a batch: for every graph) */
+  int32_t verified;    /* LPA_FLAG_VERIFY: 1 if the verification sweep changed <= tau * n labels (a batch:
+                          every graph's last verification sweep, judged by dN_g / N_g) */
   int32_t num_colors;  /* deterministic mode: colour classes */
   int64_t changed[LPA_MAX_SWEEPS_RECORDED];       /* dN of each sweep */
   int64_t frontier[LPA_MAX_SWEEPS_RECORDED];      /* vertices with >= 1 stored entry processed in each sweep */
@@ -119,7 +121,7 @@ typedef struct {
   int64_t compact_listed, compact_taken;
   int32_t weight_bytes;
   int32_t reserved;
-  int64_t verify_edges_scanned;  /* stored entries scanned by the verification sweep(s) */
+  int64_t verify_edges_scanned;  /* stored entries scanned by the verification sweep(s) (0 for a batch) */
   /* snapshot first sweep (lpa_set_first_sweep), when it ran: vertices processed,
      stored entries scanned, labels changed and neighbour marks written by its
      kernels, and neighbour ids they read (counted in none of the bin totals) */
@@ -311,7 +313,15 @@ int lpa_color(lpa_graph *g, uint32_t seed, int32_t *colors_out, unsigned flags, 
  * dN_g / N_g <= tolerance; a graph that stops keeps its labels and flags while
  * the others go on, and the whole run is one HIP graph launch.  Labels are
  * global vertex ids.  graph_vptr is int64[n_graphs+1] (host memory);
- * an entry joining two graphs gives LPA_ERR_INVALID_CSR.
+ * an entry joining two graphs gives LPA_ERR_INVALID_CSR.  Gated and verified
+ * runs (LPA_FLAG_GATE, LPA_FLAG_VERIFY, LPA_FLAG_VERIFY_FULL) apply the
+ * single-graph procedure to every graph on the device, in the same launch:
+ * after its stop test (or its max_iters sweeps) a graph runs its own
+ * verification sweep with the gate off; one that changes more than
+ * tolerance * N_g labels goes on with plain sweeps (at least one, at most
+ * max_iters, ending once the graph's sweeps, its verification included,
+ * reach 2 * max_iters) and a last verification sweep.  Dense sweeps (see LPA_FLAG_EXACT_MARKS) are then
+ * limited to the first sweep.
  */
 int lpa_batch_create(lpa_graph **out, int32_t n_graphs, const int64_t *graph_vptr, int64_t n, int64_t m,
                      const int64_t *offsets, const int32_t *indices, const float *weights, int device,
@@ -322,6 +332,17 @@ int lpa_batch_create(lpa_graph **out, int32_t n_graphs, const int64_t *graph_vpt
  * iterations[n_graphs] and converged[n_graphs] (host arrays, may be NULL).
  */
 int lpa_batch_stats(const lpa_graph *g, int32_t *iterations, int32_t *converged);
+
+/*
+ * lpa_batch_verify_stats - per-graph verification outcome of the last
+ * batched run with LPA_FLAG_GATE / LPA_FLAG_VERIFY / LPA_FLAG_VERIFY_FULL:
+ * verified[n_graphs] (1 if the graph's last verification sweep changed
+ * <= tolerance * N_g labels; empty graphs count as verified) and
+ * verify_changed[n_graphs] (labels changed by its verification sweeps); host
+ * arrays, may be NULL.  iterations from lpa_batch_stats exclude the
+ * verification sweeps.  LPA_ERR_INVALID_ARG for a handle that is no batch.
+ */
+int lpa_batch_verify_stats(const lpa_graph *g, int32_t *verified, int32_t *verify_changed);
 
 /*
  * Learned active-set gate.  Vertex pruning (Section 4.1.4) processes every

@@ -130,6 +130,7 @@ SIGNATURES = {
     "lpa_autotune": (ctypes.c_int, [_vp, _f64, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "lpa_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_uint]),
     "lpa_batch_stats": (ctypes.c_int, [_vp, _vp, _vp]),
+    "lpa_batch_verify_stats": (ctypes.c_int, [_vp, _vp, _vp]),
     "lpa_gate_load": (ctypes.c_int, [_vp, _vp, _f32]),
     "lpa_set_trace": (ctypes.c_int, [_vp, _i64, _f64]),
     "lpa_gate_trace": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(_i64), ctypes.c_uint]),
@@ -274,6 +275,10 @@ def lpa_batch_create(n_graphs, graph_vptr, n, m, offsets, indices, weights=None,
 
 def lpa_batch_stats(handle, iterations=None, converged=None):
     return load().lpa_batch_stats(handle, _ptr(iterations), _ptr(converged))
+
+
+def lpa_batch_verify_stats(handle, verified=None, verify_changed=None):
+    return load().lpa_batch_verify_stats(handle, _ptr(verified), _ptr(verify_changed))
 
 
 def lpa_destroy(handle):
@@ -587,3 +592,10 @@ class LPABatch(LPAGraph):
         cv = np.zeros(self.ngraphs, np.int32)
         _check(lpa_batch_stats(self.handle, it, cv), "lpa_batch_stats")
         return it, cv.astype(bool)
+
+    def verify_stats(self):
+        """Per graph: verified (bool) and labels changed by its verification sweeps."""
+        ok = np.zeros(self.ngraphs, np.int32)
+        ch = np.zeros(self.ngraphs, np.int32)
+        _check(lpa_batch_verify_stats(self.handle, ok, ch), "lpa_batch_verify_stats")
+        return ok.astype(bool), ch

@@ -200,8 +200,12 @@ struct Ctl {
   // flags are set once at its end (pruning is exact, so processing a vertex
   // that would not have been flagged changes nothing).
   int32_t dense_enabled, dense_cur, dense_prev, pad0;
-  // batched runs: graphs still running, and graphs stopped by the sweep cap
-  int32_t batch, batch_remaining, batch_capped, pad1;
+  // batched runs: graphs still running, graphs stopped without meeting the
+  // stop test, the verification mode (0 none, 1 over the flagged vertices, 2
+  // over all), the sweep cap of each graph's method, graphs whose last
+  // verification sweep failed
+  int32_t batch, batch_remaining, batch_capped, batch_mode;
+  int32_t batch_iters, batch_unverified, pad1, pad2;
   double dense_frac;
   int64_t n_active;
   double tau;

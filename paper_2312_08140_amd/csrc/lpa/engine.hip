@@ -160,6 +160,7 @@ struct lpa_graph {
   int32_t nlive = 0;
   int64_t *bvptr = nullptr;
   int32_t *bgid = nullptr, *bgdone = nullptr, *bgiters = nullptr, *bgconv = nullptr;
+  int32_t *bgphase = nullptr, *bgcap = nullptr, *bgverified = nullptr, *bgvchanged = nullptr;
   uint8_t *bchg = nullptr;
   // timing
   bool timing = false;
@@ -601,6 +602,12 @@ BatchArgs batch_args(lpa_graph *g) {
   b.gdone = g->bgdone;
   b.giters = g->bgiters;
   b.gconv = g->bgconv;
+  b.gphase = g->bgphase;
+  b.gcap = g->bgcap;
+  b.gverified = g->bgverified;
+  b.gvchanged = g->bgvchanged;
+  b.off = g->off;
+  b.F = g->F;
   return b;
 }
 
@@ -725,7 +732,8 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late, int
   g->hub_gbits = mode == LPA_MODE_DETERMINISTIC ? 0 : HUB_PART_GROUP_BITS;
   if (g->gate_active) {
     tk_begin(g, st);
-    launch_gate_pass(g->ctl, g->gate_f, g->gate_z, g->cur_feat, g->F, g->gskip, g->n, g->cu_count, st);
+    launch_gate_pass(g->ctl, g->gate_f, g->gate_z, g->cur_feat, g->F, g->gskip, g->n, g->cu_count,
+                     g->ngraphs ? g->bgid : nullptr, g->ngraphs ? g->bgphase : nullptr, st);
     tk_end(g, st, TK_GATE);
   }
   if (mode == LPA_MODE_DETERMINISTIC) {
@@ -1114,6 +1122,10 @@ int lpa_batch_create(lpa_graph **out, int32_t n_graphs, const int64_t *graph_vpt
     g->bgdone = dalloc_n<int32_t>(g, n_graphs);
     g->bgiters = dalloc_n<int32_t>(g, n_graphs);
     g->bgconv = dalloc_n<int32_t>(g, n_graphs);
+    g->bgphase = dalloc_n<int32_t>(g, n_graphs);
+    g->bgcap = dalloc_n<int32_t>(g, n_graphs);
+    g->bgverified = dalloc_n<int32_t>(g, n_graphs);
+    g->bgvchanged = dalloc_n<int32_t>(g, n_graphs);
     HIP_OK(hipMemcpyAsync(g->bvptr, graph_vptr, sizeof(int64_t) * (n_graphs + 1), hipMemcpyHostToDevice,
                           g->stream));
     launch_batch_gid(batch_args(g), g->stream);
@@ -1140,6 +1152,18 @@ int lpa_batch_stats(const lpa_graph *gc, int32_t *iterations, int32_t *converged
     if (iterations)
       HIP_OK(hipMemcpy(iterations, g->bgiters, sizeof(int32_t) * g->ngraphs, hipMemcpyDeviceToHost));
     if (converged) HIP_OK(hipMemcpy(converged, g->bgconv, sizeof(int32_t) * g->ngraphs, hipMemcpyDeviceToHost));
+    return LPA_OK;
+  });
+}
+
+int lpa_batch_verify_stats(const lpa_graph *gc, int32_t *verified, int32_t *verify_changed) {
+  lpa_graph *g = const_cast<lpa_graph *>(gc);
+  return run_guarded(g, [&]() -> int {
+    if (!g->ngraphs) return LPA_ERR_INVALID_ARG;
+    if (verified)
+      HIP_OK(hipMemcpy(verified, g->bgverified, sizeof(int32_t) * g->ngraphs, hipMemcpyDeviceToHost));
+    if (verify_changed)
+      HIP_OK(hipMemcpy(verify_changed, g->bgvchanged, sizeof(int32_t) * g->ngraphs, hipMemcpyDeviceToHost));
     return LPA_OK;
   });
 }
@@ -1520,7 +1544,6 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       !(tolerance == tolerance))
     return LPA_ERR_INVALID_ARG;
   if ((flags & LPA_FLAG_GATE) && !g->gate_loaded) return LPA_ERR_NO_GATE;
-  if ((flags & (LPA_FLAG_GATE | LPA_FLAG_VERIFY | LPA_FLAG_VERIFY_FULL)) && g->ngraphs) return LPA_ERR_INVALID_ARG;
   return run_guarded(g, [&]() -> int {
     Events ev;
     hipEvent_t e0 = ev.e[0], e1 = ev.e[1], t0 = ev.e[2], t1 = ev.e[3];
@@ -1552,9 +1575,13 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
                         g->stream);
     // A batched handle replays the whole run as one graph launch; otherwise
     // one sweep per launch, with the stop test polled one sweep behind.
-    // (a run that ends with a verification sweep needs the host between sweeps)
-    const bool one_launch = use_graph && (g->ngraphs > 0 || (flags & LPA_FLAG_ONE_LAUNCH)) &&
-                            !(flags & (LPA_FLAG_GATE | LPA_FLAG_VERIFY | LPA_FLAG_VERIFY_FULL));
+    // (a single graph's run that ends with a verification sweep needs the
+    // host between sweeps; a batch verifies every graph on the device, with
+    // room for each graph's verification and fallback sweeps)
+    const bool checked = flags & (LPA_FLAG_GATE | LPA_FLAG_VERIFY | LPA_FLAG_VERIFY_FULL);
+    const int batch_mode = g->ngraphs && checked && max_iters > 0 ? ((flags & LPA_FLAG_VERIFY_FULL) ? 2 : 1) : 0;
+    const int run_sweeps = batch_mode ? 2 * max_iters + 2 : max_iters;
+    const bool one_launch = use_graph && (g->ngraphs > 0 || ((flags & LPA_FLAG_ONE_LAUNCH) && !checked));
     // gate features: written while the gate is used or training traces are recorded
     const bool gate = flags & LPA_FLAG_GATE;
     const bool trace = flags & LPA_FLAG_TRACE;
@@ -1575,7 +1602,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     // per-sweep graphs of the early and the late asynchronous schedule
     hipGraphExec_t exec = nullptr, exec_late = nullptr, exec_first = nullptr;
     if (use_graph && max_iters > 0) {
-      exec = sweep_graph(g, mode, prune, one_launch ? max_iters : 1, 0, 0, one_launch ? snap : 0);
+      exec = sweep_graph(g, mode, prune, one_launch ? run_sweeps : 1, 0, 0, one_launch ? snap : 0);
       exec_late = one_launch ? exec : sweep_graph(g, mode, prune, 1, g->early_sweeps);
       if (snap && !one_launch) exec_first = sweep_graph(g, mode, prune, 1, 0, 0, snap);
     }
@@ -1595,13 +1622,13 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     HIP_OK(hipEventRecord(t0, g->stream));
     const int nfc = mode == LPA_MODE_DETERMINISTIC ? std::max(1, g->ncol) * NBINS : max_phases(g) * NBINS;
     const int dense = mode == LPA_MODE_ASYNC && prune && !(flags & LPA_FLAG_EXACT_MARKS);
-    launch_run_begin(g->ctl, tolerance, max_iters, g->n, g->n_active, g->fcount, nfc, g->host_done_dev, dense,
+    launch_run_begin(g->ctl, tolerance, run_sweeps, g->n, g->n_active, g->fcount, nfc, g->host_done_dev, dense,
                      !init_labels && !init_flags, gate ? 1 : 0, g->stream);
-    if (g->ngraphs) launch_batch_begin(g->ctl, batch_args(g), g->n, g->nlive, g->stream);
+    if (g->ngraphs) launch_batch_begin(g->ctl, batch_args(g), g->n, g->nlive, batch_mode, max_iters, g->stream);
     if (one_launch && exec) {
       HIP_OK(hipGraphLaunch(exec, g->stream));
     } else
-    for (int s = 0; s < max_iters; ++s) {
+    for (int s = 0; s < run_sweeps; ++s) {
       launch_sweep(s);
       HIP_OK(hipEventRecord(lag[s & 1], g->stream));
       if (s >= 1) {
@@ -1623,7 +1650,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       }
     };
     int verified = -1;
-    if ((flags & (LPA_FLAG_VERIFY | LPA_FLAG_VERIFY_FULL | LPA_FLAG_GATE)) && max_iters > 0 && !one_launch) {
+    if (checked && max_iters > 0 && !g->ngraphs) {
       // with the gate off no feature is read again: verification and any
       // fallback sweeps run the plain kernels (the plain late-sweep graph)
       g->feat_on = false;
@@ -1664,7 +1691,7 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       std::memset(stats, 0, sizeof(*stats));
       stats->iterations = h.iterations;
       stats->converged = h.converged;
-      stats->verified = verified > 0;
+      stats->verified = batch_mode ? h.batch_remaining == 0 && h.batch_unverified == 0 : verified > 0;
       stats->num_colors = mode == LPA_MODE_DETERMINISTIC ? g->ncol : 0;
       u64 prev = h.t_start;
       for (int s = 0; s < std::min(h.iterations, MAX_REC); ++s) {

@@ -150,7 +150,9 @@ __global__ void k_end_sweep(Ctl *ctl, int32_t *fcount, int nfc, int32_t *host_do
   // A gated sweep writes exact marks: its flags, with those the gate kept,
   // are all the verification sweep has to process (a dense sweep would flag
   // every vertex and turn the verification into a full sweep).
-  ctl->dense_cur = ctl->dense_enabled && !ctl->gate_on && (double)dn > ctl->dense_frac * (double)ctl->n_active;
+  // (likewise in a verified batch, where some graph may be verifying)
+  ctl->dense_cur = ctl->dense_enabled && !ctl->gate_on && !(ctl->batch && ctl->batch_mode) &&
+                   (double)dn > ctl->dense_frac * (double)ctl->n_active;
   ctl->iterations = it + 1;
   ctl->sweep = s + 1;
   if (ctl->batch) {
@@ -186,27 +188,44 @@ __global__ void k_batch_gid(BatchArgs b) {
     for (int64_t v = b.vptr[g] + threadIdx.x; v < b.vptr[g + 1]; v += blockDim.x) b.gid[v] = g;
 }
 
-__global__ void k_batch_begin(Ctl *ctl, BatchArgs b, int64_t n, int32_t live) {
+__global__ void k_batch_begin(Ctl *ctl, BatchArgs b, int64_t n, int32_t live, int mode, int iters) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
     b.chg[v] = 0;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < b.ngraphs; g += gridDim.x * blockDim.x) {
-    b.gdone[g] = b.vptr[g + 1] == b.vptr[g];  // an empty graph has nothing to do
+    const bool empty = b.vptr[g + 1] == b.vptr[g];  // an empty graph has nothing to do
+    b.gdone[g] = empty;
     b.giters[g] = 0;
-    b.gconv[g] = b.vptr[g + 1] == b.vptr[g];
+    b.gconv[g] = empty;
+    b.gphase[g] = empty ? BPH_DONE : BPH_MAIN;
+    b.gcap[g] = iters;
+    b.gverified[g] = empty;
+    b.gvchanged[g] = 0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->batch = 1;
     ctl->batch_remaining = live;
     ctl->batch_capped = 0;
+    ctl->batch_mode = mode;
+    ctl->batch_iters = iters;
+    ctl->batch_unverified = 0;
   }
 }
 
 // Per-graph stop test of the sweep just finished (Algorithm 1 applied to
-// every graph separately): dN_g counts the graph's changed vertices.
+// every graph separately): dN_g counts the graph's changed vertices.  In a
+// verified run every graph then goes through its own verification sweep
+// (gate off) and, if that changes more than tau * N_g labels, through plain
+// sweeps (at least one, at most `iters`, ending once the graph's sweeps,
+// verification included, reach 2 * iters) and a last verification sweep.
+// The batch therefore needs at most 2 * iters + 2 sweeps.  Sweep counts of a graph equal
+// the batch's, as every graph starts at sweep 0 and takes part in each sweep
+// until it is done.
 __global__ __launch_bounds__(256) void k_batch_end(Ctl *ctl, BatchArgs b) {
   if (__atomic_load_n(&ctl->done, __ATOMIC_RELAXED)) return;
   __shared__ int s_sum[4];
+  __shared__ int s_flag_all;
   const int s = ctl->sweep;
+  const int mode = ctl->batch_mode, iters = ctl->batch_iters;
   for (int g = blockIdx.x; g < b.ngraphs; g += gridDim.x) {
     const int64_t v0 = b.vptr[g], v1 = b.vptr[g + 1];
     int c = 0;
@@ -217,20 +236,48 @@ __global__ __launch_bounds__(256) void k_batch_end(Ctl *ctl, BatchArgs b) {
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) c += __shfl_xor(c, m, 64);
     if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = c;
+    if (threadIdx.x == 0) s_flag_all = 0;
     __syncthreads();
     if (threadIdx.x == 0 && !b.gdone[g]) {
       const int64_t dn = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
-      b.giters[g] = s + 1;
-      if ((double)dn / (double)(v1 - v0) <= ctl->tau) {
+      const bool small = (double)dn / (double)(v1 - v0) <= ctl->tau;
+      const int ph = b.gphase[g];
+      int next = ph;
+      bool finish = false;
+      if (ph == BPH_MAIN || ph == BPH_FALLBACK) {
+        b.giters[g] += 1;
+        if (small) b.gconv[g] = 1;
+        if (small || s + 1 >= (ph == BPH_MAIN ? iters : b.gcap[g])) {
+          if (mode == 0) finish = true;
+          else next = ph + 1;
+        }
+      } else {
+        b.gvchanged[g] += (int32_t)dn;
+        atomicAdd((unsigned long long *)&ctl->verify_changed, (unsigned long long)dn);
+        b.gverified[g] = small;
+        if (small || ph == BPH_VERIFY2) {
+          finish = true;
+        } else {
+          next = BPH_FALLBACK;
+          b.gcap[g] = min(2 * iters, s + 1 + iters);
+        }
+      }
+      if (finish) {
         b.gdone[g] = 1;
-        b.gconv[g] = 1;
+        b.gphase[g] = BPH_DONE;
         atomicSub(&ctl->batch_remaining, 1);
-      } else if (s + 1 >= ctl->max_iters) {
-        b.gdone[g] = 1;
-        atomicSub(&ctl->batch_remaining, 1);
-        atomicAdd(&ctl->batch_capped, 1);
+        if (!b.gconv[g]) atomicAdd(&ctl->batch_capped, 1);
+        if (mode && !b.gverified[g]) atomicAdd(&ctl->batch_unverified, 1);
+      } else {
+        b.gphase[g] = next;
+        // a full verification processes every vertex of the graph that has entries
+        if (mode == 2 && next != ph && (next == BPH_VERIFY || next == BPH_VERIFY2)) s_flag_all = 1;
       }
     }
+    __syncthreads();
+    if (s_flag_all)
+      for (int64_t v = v0 + threadIdx.x; v < v1; v += 256)
+        if (b.off[v + 1] > b.off[v]) b.F[v] = 1;
     __syncthreads();
   }
 }
@@ -239,8 +286,9 @@ void launch_batch_gid(const BatchArgs &b, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_gid, dim3(std::max(1, std::min(b.ngraphs, 8192))), dim3(256), 0, st, b);
 }
 
-void launch_batch_begin(Ctl *ctl, const BatchArgs &b, int64_t n, int32_t live, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_begin, dim3(4096), dim3(256), 0, st, ctl, b, n, live);
+void launch_batch_begin(Ctl *ctl, const BatchArgs &b, int64_t n, int32_t live, int mode, int iters,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_begin, dim3(4096), dim3(256), 0, st, ctl, b, n, live, mode, iters);
 }
 
 void launch_batch_end(Ctl *ctl, const BatchArgs &b, hipStream_t st) {
@@ -306,13 +354,16 @@ __device__ __forceinline__ float gate_logit_uniform(const float *__restrict__ P,
 }
 
 __global__ __launch_bounds__(256) void k_gate_pass(const Ctl *ctl, const float *__restrict__ gate, float z, FeatArgs f,
-                                                   const uint8_t *F, uint8_t *skip, int64_t n) {
+                                                   const uint8_t *F, uint8_t *skip, int64_t n,
+                                                   const int32_t *gid, const int32_t *gphase) {
   if (__atomic_load_n(&ctl->done, __ATOMIC_RELAXED)) return;
   const int sweep = ctl->sweep;
   if (!ctl->gate_on || ctl->verify_phase || sweep < 1) return;
   for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v - threadIdx.x < n; v += (int64_t)gridDim.x * 256) {
     const float *rec = f.feat + v * FEAT_STRIDE;
-    const int lp = v < n && F[v] ? record_lastp(rec) : -1;
+    // a batched graph past its gated sweeps (verifying, falling back, done) is not gated
+    const bool in_gate = v < n && F[v] && (!gphase || gphase[gid[v]] == BPH_MAIN);
+    const int lp = in_gate ? record_lastp(rec) : -1;
     float x[NFEAT] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (lp >= 0) decision_features(rec, lp, sweep, f.max_iters, x);
     float logit = 0.0f;
@@ -682,10 +733,12 @@ void launch_scan_bin(int bin, int variant, int wk, bool feat, int blocks, hipStr
 }
 
 void launch_gate_pass(const Ctl *ctl, const float *gate, float z, const FeatArgs &f, const uint8_t *F,
-                      uint8_t *skip, int64_t n, int cu_count, hipStream_t st) {
+                      uint8_t *skip, int64_t n, int cu_count, const int32_t *gid, const int32_t *gphase,
+                      hipStream_t st) {
   int64_t blocks = (n + 255) / 256;
   blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, (int64_t)cu_count * 16));
-  hipLaunchKernelGGL(k_gate_pass, dim3((unsigned)blocks), dim3(256), 0, st, ctl, gate, z, f, F, skip, n);
+  hipLaunchKernelGGL(k_gate_pass, dim3((unsigned)blocks), dim3(256), 0, st, ctl, gate, z, f, F, skip, n, gid,
+                     gphase);
 }
 
 void launch_compact(const CompactArgs &a, int blocks, hipStream_t st) {

@@ -27,8 +27,10 @@ struct CompactArgs {
 };
 
 void launch_compact(const CompactArgs &a, int blocks, hipStream_t st);
+// gid, gphase: batched runs (NULL otherwise); only graphs in their gated sweeps (phase 0) pass the gate
 void launch_gate_pass(const Ctl *ctl, const float *gate, float z, const FeatArgs &f, const uint8_t *F,
-                      uint8_t *skip, int64_t n, int cu_count, hipStream_t st);
+                      uint8_t *skip, int64_t n, int cu_count, const int32_t *gid, const int32_t *gphase,
+                      hipStream_t st);
 void launch_scan_bin(int bin, int variant, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a);
 int bin_vertices_per_block(int bin, int variant);
 // max_hubs: most flagged hubs the step can have (its hub-bin segment)
@@ -51,15 +53,25 @@ void launch_set_phase(Ctl *ctl, int verify, int gate_on, int extra_iters, int32_
 void launch_feat_reset(float *feat, int64_t n, hipStream_t st);
 
 // batched runs (graph g owns vertices [vptr[g], vptr[g+1]))
+// Phases of a graph in a verified run: BPH_MAIN (the method's sweeps, gated
+// when the gate is on), BPH_VERIFY (verification sweep), BPH_FALLBACK (plain
+// sweeps after a failed verification), BPH_VERIFY2 (the last verification),
+// BPH_DONE.
+enum { BPH_MAIN = 0, BPH_VERIFY = 1, BPH_FALLBACK = 2, BPH_VERIFY2 = 3, BPH_DONE = 4 };
 struct BatchArgs {
   int32_t ngraphs;
   const int64_t *vptr;
   int32_t *gid;
   uint8_t *chg;
   int32_t *gdone, *giters, *gconv;
+  int32_t *gphase, *gcap, *gverified, *gvchanged;  // verified runs (phase, fallback cap, outcome)
+  const int64_t *off;                               // full verification: flags every vertex with entries
+  uint8_t *F;
 };
 void launch_batch_gid(const BatchArgs &b, hipStream_t st);
-void launch_batch_begin(Ctl *ctl, const BatchArgs &b, int64_t n, int32_t live, hipStream_t st);
+// mode: verification mode (0 none, 1 flagged vertices, 2 all); iters: sweep cap of the method per graph
+void launch_batch_begin(Ctl *ctl, const BatchArgs &b, int64_t n, int32_t live, int mode, int iters,
+                        hipStream_t st);
 void launch_batch_end(Ctl *ctl, const BatchArgs &b, hipStream_t st);
 void launch_check_block_diagonal(const int64_t *off, const int32_t *idx, const int32_t *gid, int64_t n, int32_t *bad,
                                  hipStream_t st);

@@ -399,3 +399,159 @@ def test_gated_deterministic_equals_gated_oracle(kind):
     assert st["verify_changed"] == ref["verify_changed"]
     assert st["verify_edges_scanned"] == ref["verify_scanned"]
     assert st["verified"] == ref["verified"]
+
+
+# ---------------------------------------------------------------- gated and verified batches
+
+def _batch_parts(g, vptr, B, seed=0):
+    """Per graph of a batch: its vertex range, its subgraph and the
+    deterministic mode's order restricted to it (the greedy colouring of the
+    whole block-diagonal graph, checked equal to the library's)."""
+    colors, nc = B.color(seed)
+    ocol, onc = oracle.color(g, seed)
+    assert nc == onc and np.array_equal(colors, ocol), "colouring differs from the greedy oracle"
+    parts = []
+    for k in range(len(vptr) - 1):
+        lo, hi = int(vptr[k]), int(vptr[k + 1])
+        order = np.lexsort((np.arange(hi - lo), ocol[lo:hi])).astype(np.int32)
+        parts.append((lo, hi, oracle.subgraph(g, lo, hi), order))
+    return parts
+
+
+def _gated_refs(parts, theta, thr, tau, max_iters):
+    from oracle.gate_trace import lpa_gated
+    return [lpa_gated(sub, theta, thr, order=order, tau=tau, max_iters=max_iters) for _, _, sub, order in parts]
+
+
+def _check_batch(B, parts, refs, lab, st):
+    """Every graph of the batch against its own gated-method oracle run:
+    labels, counted sweeps, convergence, verification outcome and the labels
+    its verification sweeps changed; the run's totals follow."""
+    it, cv = B.graph_stats()
+    ok, vch = B.verify_stats()
+    for k, ((lo, hi, _, _), r) in enumerate(zip(parts, refs)):
+        assert np.array_equal(lab[lo:hi], r["labels"] + lo), f"graph {k}"
+        assert it[k] == r["iterations"] and cv[k] == r["converged"], f"graph {k}: {it[k]} {cv[k]}"
+        assert ok[k] == r["verified"] and vch[k] == r["verify_changed"], f"graph {k}: {ok[k]} {vch[k]}"
+    assert st["verified"] == all(r["verified"] for r in refs)
+    assert st["converged"] == all(r["converged"] for r in refs)
+    assert st["verify_changed"] == sum(r["verify_changed"] for r in refs)
+
+
+def _gate_batch(count=6, seed=3, n_range=(60, 300)):
+    return gg.sbm_batch(count=count, master_seed=seed, seed_base=700 + seed, n_range=n_range)
+
+
+@pytest.mark.parametrize("tau,max_iters,full", [(0.05, 20, False), (0.05, 20, True), (0.01, 2, False),
+                                                (0.01, 2, True), (0.0, 1, False)])
+def test_batch_verified_equals_oracle(tau, max_iters, full):
+    """A verified batch (gate off): each graph runs the method, its own
+    verification sweep and, where that fails (max_iters = 2 stops graphs
+    early), its fallback sweeps and last verification - the gated oracle at
+    threshold 0, graph by graph.  A full verification processes every vertex
+    and gives the same outcome.  tau = 0 with one sweep leaves graphs
+    unconverged and unverified at the end of their fallback."""
+    g, vptr = _gate_batch(12, 5)
+    B = abi.LPABatch(g, vptr)
+    parts = _batch_parts(g, vptr, B)
+    refs = _gated_refs(parts, random_params(1), 0.0, tau, max_iters)
+    say(f"verified batch: n={g.n} m={g.m} tau={tau} max_iters={max_iters} full={full} "
+        f"verified={[r['verified'] for r in refs]} iterations={[r['iterations'] for r in refs]}")
+    fl = abi.LPA_FLAG_VERIFY_FULL if full else abi.LPA_FLAG_VERIFY
+    lab, st = B.run(tau, max_iters, DET, True, flags=fl)
+    _check_batch(B, parts, refs, lab, st)
+    if max_iters <= 2:
+        assert any(r["verify_changed"] > 0 for r in refs)  # some graph's first verification found work
+    if max_iters == 1:
+        assert not all(r["verified"] for r in refs)
+    B.close()
+
+
+def _pick_batch_gate(parts, seeds=(21, 22, 23, 24, 25, 26), tau=0.05, max_iters=20, min_margin=1e-3):
+    """Gate parameters and a threshold in (0, 1) for which no decision of any
+    graph's gated oracle run lies within ``min_margin`` of the threshold's
+    logit and some flagged vertex is skipped; candidates are midpoints of the
+    widest gaps between the decision logits of the graphs' plain traces."""
+    from oracle.gate_trace import _logit_fp64
+    X = np.concatenate([lpa_trace(sub, order=order, tau=tau, max_iters=max_iters)["X"]
+                        for _, _, sub, order in parts])
+    for seed in seeds:
+        theta = random_params(seed)
+        z = np.sort(np.unique(_logit_fp64(mlp.bf16_round(theta), X)))
+        if len(z) < 8:
+            continue
+        lo, hi = len(z) // 4, 3 * len(z) // 4
+        gaps = np.diff(z[lo:hi + 1])
+        for k in np.argsort(gaps)[::-1][:6]:
+            zc = 0.5 * (z[lo + k] + z[lo + k + 1])
+            thr = float(np.float32(1.0 / (1.0 + np.exp(-zc))))
+            if not 0.0 < thr < 1.0:
+                continue
+            refs = _gated_refs(parts, theta, thr, tau, max_iters)
+            if min(r["margin"] for r in refs) >= min_margin and sum(int(r["gated"].sum()) for r in refs) > 0:
+                return theta, thr, refs
+    raise AssertionError("no gate with a safe margin found")
+
+
+def test_batch_gated_equals_gated_oracle():
+    """A gated batch in deterministic mode: the in-sweep network gates only the
+    graphs still in their gated sweeps, and every graph matches its own gated
+    oracle run (threshold chosen on the oracle side with a 1e-3 logit margin)."""
+    g, vptr = _gate_batch(6, 3)
+    B = abi.LPABatch(g, vptr)
+    parts = _batch_parts(g, vptr, B)
+    theta, thr, refs = _pick_batch_gate(parts)
+    say(f"gated batch: n={g.n} m={g.m} threshold={thr:.6f} gated={[int(r['gated'].sum()) for r in refs]} "
+        f"verified={[r['verified'] for r in refs]}")
+    B.gate_load(theta, thr)
+    lab, st = B.run(0.05, 20, DET, True, flags=abi.LPA_FLAG_GATE)
+    _check_batch(B, parts, refs, lab, st)
+    assert sum(st["gated_out"]) == sum(int(r["gated"].sum()) for r in refs)
+    B.close()
+
+
+@pytest.mark.parametrize("max_iters", [20, 5])
+def test_batch_gate_skipping_everything_falls_back(max_iters):
+    """Threshold 1 skips every flagged vertex after the first sweep: graphs
+    fail verification and recover through their fallback sweeps, each as its
+    gated oracle run says; a plain run on the same handle afterwards equals
+    the plain oracle again."""
+    g, vptr = _gate_batch(10, 4)
+    B = abi.LPABatch(g, vptr)
+    parts = _batch_parts(g, vptr, B)
+    theta = random_params(31)
+    refs = _gated_refs(parts, theta, 1.0, 0.05, max_iters)
+    say(f"threshold-1 batch: n={g.n} m={g.m} verified={[r['verified'] for r in refs]} "
+        f"iterations={[r['iterations'] for r in refs]} verify_changed={[r['verify_changed'] for r in refs]}")
+    assert any(r["verify_changed"] > 0 for r in refs)
+    B.gate_load(theta, 1.0)
+    lab, st = B.run(0.05, max_iters, DET, True, flags=abi.LPA_FLAG_GATE)
+    _check_batch(B, parts, refs, lab, st)
+    lab, st = B.run(0.05, 20, DET, True)
+    plain = oracle.lpa_batch(g, vptr, deterministic=True, tau=0.05, max_iters=20)
+    it, cv = B.graph_stats()
+    for k, (lo, hi, _, _) in enumerate(parts):
+        assert np.array_equal(lab[lo:hi], plain[k]["labels"]), f"graph {k}"
+        assert it[k] == plain[k]["iterations"] and cv[k] == plain[k]["converged"]
+    B.close()
+
+
+def test_batch_gated_async():
+    """Asynchronous gated batch: labels stay inside their graph, every graph
+    ends verified, and modularity stays within 0.01 of the plain batch run."""
+    g, vptr = gg.sbm_batch(count=200, master_seed=9, seed_base=900, n_range=(100, 3000))
+    B = abi.LPABatch(g, vptr)
+    plain, sp = B.run(0.05, 20, ASYNC, True)
+    qp = B.modularity(plain)
+    B.gate_load(random_params(22), 0.5)
+    lab, st = B.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_GATE)
+    ok, vch = B.verify_stats()
+    gid = np.searchsorted(vptr, np.arange(g.n), side="right") - 1
+    qg = B.modularity(lab)
+    say(f"async gated batch: n={g.n} m={g.m} Q plain {qp:.5f} gated {qg:.5f} skipped={sum(st['gated_out'])} "
+        f"verify_changed={st['verify_changed']} sweeps={st['iterations']}")
+    assert np.array_equal(gid[lab], gid)
+    assert ok.all() and st["verified"] and st["converged"]
+    assert sum(st["gated_out"]) > 0
+    assert abs(qg - qp) <= 0.01
+    B.close()
