@@ -63,48 +63,151 @@ __global__ void k_convert_weights(const float *w, int64_t m, int wk, void *out) 
   }
 }
 
-// K_v = summed stored weights of row v.  A lane sums a short row by itself;
-// the rows of more than 64 entries in a wave's 64 vertices are summed by the
-// whole wave together (rows are heavily skewed).
+// K_v = summed stored weights of row v (64-bit sums; a sum >= 2^32 is
+// reported).  Rows are read with coalesced loads whatever their lengths:
+//  * a wave takes 64 consecutive vertices; when their rows hold at most
+//    WD_TILE entries together, the wave streams that entry range 64 entries at
+//    a time, finds the row of every entry by a binary search over the 64 row
+//    starts (held one per lane), adds the weights of each row's run of lanes
+//    with a segmented scan, and the last lane of each run adds the run's sum
+//    into the row's accumulator in LDS;
+//  * otherwise each row of at most 64 entries is summed by its own lane and
+//    each longer one, up to WD_BIG entries, by the whole wave;
+//  * rows of more than WD_BIG entries are set to 0 here and summed by
+//    k_weighted_degree_big in chunks of WD_BIG entries added with atomics.
+constexpr int WD_TILE = 4096;
+constexpr int64_t WD_BIG = 65536;
+
 template <int WK>
 __global__ __launch_bounds__(256) void k_weighted_degree(const int64_t *off, const void *w, int64_t n, uint32_t *K,
                                                          CsrCheck *chk) {
+  __shared__ u64 s_acc[4][64];
   int big = 0;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t waves = (int64_t)gridDim.x * 4;
-  for (int64_t base = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; base < n; base += waves * 64) {
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + wv) * 64; base < n; base += waves * 64) {
     const int64_t v = base + lane;
+    const int cnt = (int)min((int64_t)64, n - base);  // vertices of the tile
     int64_t b = 0, e = 0;
     if (v < n) {
       b = off[v];
       e = off[v + 1];
     }
-    const bool longrow = e - b > 64;
-    u64 s = 0;
-    if (!longrow) {
-      if constexpr (WK == W_UNIT) s = (u64)(e - b);
-      else
-        for (int64_t k = b; k < e; ++k) s += load_w<WK>(w, k);
+    if constexpr (WK == W_UNIT) {
+      if (v < n) {
+        big |= (u64)(e - b) >= (1ull << 32);
+        K[v] = (uint32_t)(e - b);
+      }
+      continue;
     }
-    u64 mask = __ballot(longrow);
-    while (mask) {
-      const int src = __builtin_ctzll(mask);
-      mask &= mask - 1;
-      const int64_t bb = __shfl(b, src, 64), ee = __shfl(e, src, 64);
-      u64 part = 0;
-      if constexpr (WK == W_UNIT) part = lane == 0 ? (u64)(ee - bb) : 0;
-      else
-        for (int64_t k = bb + lane; k < ee; k += 64) part += load_w<WK>(w, k);
+    const int64_t E0 = __shfl(b, 0, 64), E1 = __shfl(e, cnt - 1, 64);
+    u64 s = 0;
+    if (E1 - E0 <= WD_TILE) {
+      const int rb = v < n ? (int)(b - E0) : WD_TILE + 1;  // row start relative to the tile
+      s_acc[wv][lane] = 0;
+      for (int64_t x0 = E0; x0 < E1; x0 += 64) {
+        const int64_t x = x0 + lane;
+        const bool ok = x < E1;
+        const uint32_t wt = ok ? load_w<WK>(w, x) : 0u;
+        // the last row whose start is <= x (rows with no entry start where the next one does)
+        const int rx = (int)(x - E0);
+        int row = 0;
 #pragma unroll
-      for (int m = 32; m > 0; m >>= 1) part += shfl_xor_u64(part, m);
-      if (lane == src) s = part;
+        for (int step = 32; step > 0; step >>= 1) {
+          const int cand = row + step;  // <= 63
+          const int start = __shfl(rb, cand, 64);
+          if (cand < cnt && start <= rx) row = cand;
+        }
+        if (!ok) row = 64;  // lanes past the tile form no run with a row
+        // inclusive scan of the weights within each run of equal rows (64 * 2^24 < 2^32)
+        uint32_t run = wt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t o = __shfl_up(run, d, 64);
+          const int orow = __shfl_up(row, d, 64);
+          if (lane >= d && orow == row) run += o;
+        }
+        const int next = __shfl_down(row, 1, 64);
+        if (ok && (lane == 63 || next != row)) s_acc[wv][row] += run;  // one last lane per row
+      }
+      s = s_acc[wv][lane];
+    } else {
+      const bool longrow = e - b > 64;
+      if (!longrow)
+        for (int64_t k = b; k < e; ++k) s += load_w<WK>(w, k);
+      u64 mask = __ballot(longrow && e - b <= WD_BIG);
+      while (mask) {
+        const int src = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const int64_t bb = __shfl(b, src, 64), ee = __shfl(e, src, 64);
+        u64 part = 0;
+        int64_t k = bb + lane;
+        for (; k + 192 < ee; k += 256)
+          part += (u64)load_w<WK>(w, k) + load_w<WK>(w, k + 64) + load_w<WK>(w, k + 128) +
+                  load_w<WK>(w, k + 192);
+        for (; k < ee; k += 64) part += load_w<WK>(w, k);
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) part += shfl_xor_u64(part, m);
+        if (lane == src) s = part;
+      }
     }
     if (v < n) {
       big |= s >= (1ull << 32);
-      K[v] = (uint32_t)s;
+      K[v] = e - b > WD_BIG ? 0u : (uint32_t)s;
     }
   }
   if (big) atomicOr(&chk->big_degree, 1);
+}
+
+// The rows of more than WD_BIG entries: chunk c of the entries, [c * WD_BIG,
+// (c + 1) * WD_BIG), meets at most two such rows (the ones holding its first
+// and its last entry; any row between them lies inside the chunk).  Each
+// part is summed by the workgroup and added to K with a 32-bit atomic; a part
+// or a running sum that reaches 2^32 is reported.
+template <int WK>
+__global__ __launch_bounds__(256) void k_weighted_degree_big(const int64_t *off, const void *w, int64_t n,
+                                                             uint32_t *K, CsrCheck *chk) {
+  __shared__ u64 s_red[4];
+  __shared__ int64_t s_rows[2];
+  const int64_t m = off[n];
+  const int64_t chunks = (m + WD_BIG - 1) / WD_BIG;
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const int64_t c0 = c * WD_BIG, c1 = min(m, c0 + WD_BIG);
+    if (threadIdx.x < 2) {
+      // the row holding entry x: the last r with off[r] <= x (off[n] = m > x)
+      const int64_t x = threadIdx.x == 0 ? c0 : c1 - 1;
+      int64_t lo = 0, hi = n;  // off[lo] <= x < off[hi]
+      while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid;
+      }
+      s_rows[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    const int64_t r0 = s_rows[0], r1 = s_rows[1];
+    __syncthreads();  // s_rows is rewritten by the next chunk
+    for (int q = 0; q < 2; ++q) {
+      const int64_t r = q == 0 ? r0 : r1;
+      if (q == 1 && r1 == r0) break;
+      const int64_t rb = off[r], re = off[r + 1];
+      if (re - rb <= WD_BIG) continue;  // uniform across the workgroup
+      const int64_t a = max(rb, c0), z = min(re, c1);
+      u64 part = 0;
+      for (int64_t k = a + threadIdx.x; k < z; k += 256) part += load_w<WK>(w, k);
+#pragma unroll
+      for (int mm = 32; mm > 0; mm >>= 1) part += shfl_xor_u64(part, mm);
+      if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = part;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const u64 t = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+        bool over = t >= (1ull << 32);
+        if (!over) over = (u64)atomicAdd(&K[r], (uint32_t)t) + t >= (1ull << 32);
+        if (over) atomicOr(&chk->big_degree, 1);
+      }
+      __syncthreads();  // s_red is reused by the next part
+    }
+  }
 }
 
 // Multiset fingerprint of (i, j, w) against (j, i, w): equal sums for a
@@ -323,10 +426,16 @@ void launch_convert_weights(const float *w, int64_t m, int wk, void *out, hipStr
 }
 void launch_weighted_degree(const int64_t *off, const void *w, int wk, int64_t n, uint32_t *K, CsrCheck *chk,
                             hipStream_t st) {
-  dim3 g(grid_for(n, 256, 4096)), b(256);
-  if (wk == W_UNIT) hipLaunchKernelGGL(k_weighted_degree<W_UNIT>, g, b, 0, st, off, w, n, K, chk);
-  else if (wk == W_U8) hipLaunchKernelGGL(k_weighted_degree<W_U8>, g, b, 0, st, off, w, n, K, chk);
-  else hipLaunchKernelGGL(k_weighted_degree<W_U32>, g, b, 0, st, off, w, n, K, chk);
+  dim3 g(grid_for(n, 256, 8192)), b(256), gb(8192);
+  if (wk == W_UNIT) {
+    hipLaunchKernelGGL(k_weighted_degree<W_UNIT>, g, b, 0, st, off, w, n, K, chk);
+  } else if (wk == W_U8) {
+    hipLaunchKernelGGL(k_weighted_degree<W_U8>, g, b, 0, st, off, w, n, K, chk);
+    hipLaunchKernelGGL(k_weighted_degree_big<W_U8>, gb, b, 0, st, off, w, n, K, chk);
+  } else {
+    hipLaunchKernelGGL(k_weighted_degree<W_U32>, g, b, 0, st, off, w, n, K, chk);
+    hipLaunchKernelGGL(k_weighted_degree_big<W_U32>, gb, b, 0, st, off, w, n, K, chk);
+  }
 }
 void launch_check_symmetric(const int64_t *off, const int32_t *idx, const void *w, int wk, int64_t n,
                             CsrCheck *chk, hipStream_t st) {

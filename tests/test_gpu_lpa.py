@@ -318,6 +318,45 @@ def test_modularity_matches_oracle_for_any_labels():
     G.close()
 
 
+@pytest.mark.parametrize("reorder", [True, False])
+@pytest.mark.parametrize("wmax", [8, 20000])
+def test_weighted_degrees_through_modularity(reorder, wmax):
+    """Weighted degrees K_v of every row shape - rows inside tiles of few
+    entries, rows of 65 to 65,536 entries, rows above 65,536 entries summed in
+    chunks - seen through modularity (Eq. (1) weighs every vertex by K_v),
+    which must equal the exact oracle for any labelling; one-byte (wmax 8)
+    and four-byte (wmax 20000) stored weights, degree order and id order."""
+    rng = np.random.default_rng(wmax)
+    r = gg.rmat(12, 8, seed=4)
+    src = np.repeat(np.arange(r.n), np.diff(r.offsets))
+    keep = src < r.indices
+    parts = [np.stack([src[keep], r.indices[keep]], 1)]
+    nxt = r.n
+    for hub, leaves in [(0, 150_000), (1, 70_000)] + [(h, 3000) for h in range(2, 10)]:
+        parts.append(np.stack([np.full(leaves, hub), np.arange(nxt, nxt + leaves)], 1))
+        nxt += leaves
+    e = np.concatenate(parts)
+    g = gg.from_edges(nxt, e, rng.integers(1, wmax + 1, len(e)))
+    say(f"weighted degrees: n={g.n} m={g.m} max row {int(np.diff(g.offsets).max())} reorder={reorder}")
+    G = abi.LPAGraph(g, reorder=reorder)
+    for k in (1, 7, 1000, g.n):
+        lab = rng.integers(0, k, g.n).astype(np.int32)
+        assert G.modularity(lab) == oracle.modularity(g, lab), k
+    lab, _ = G.run(0.05, 20, DET, True)
+    assert G.modularity(lab) == oracle.modularity(g, lab)
+    G.close()
+
+
+@pytest.mark.parametrize("leaves", [300, 5000, 70_000])
+def test_weighted_degree_overflow_reported(leaves):
+    """A weighted degree of 2^32 or more is refused (LPA_ERR_TOO_LARGE) on
+    each of the three summation paths."""
+    g = gg.from_edges(leaves + 1, [(0, i) for i in range(1, leaves + 1)], [2.0 ** 24] * leaves)
+    rc, h = abi.lpa_create(g.n, g.m, g.offsets, g.indices, g.weights, 0, None, 0)
+    assert rc == abi.LPA_ERR_TOO_LARGE
+    assert not h.value
+
+
 def _components(g):
     import scipy.sparse as sp
     import scipy.sparse.csgraph as cg
