@@ -320,6 +320,7 @@ struct HubArgs {
   int32_t first;             // snapshot first sweep: k_hub_owner zeroes the partition maxima
   u64 *blk;                  // per tile of frontier hubs: work items (chunks, partitions, groups), then offsets
   int32_t gbits;             // log2 partitions per merge group (0: every partition its own work item)
+  int32_t ids_identity;      // ids[k] == k for every hub (degree order): a hub's ordinal is its position
 };
 
 // Wave64 helpers.

@@ -122,6 +122,7 @@ struct lpa_graph {
   int32_t *hub_ord = nullptr;
   u64 *hub_cstart = nullptr, *hub_pstart = nullptr, *hub_gstart = nullptr, *hub_blk = nullptr;
   int32_t *hub_chunk_owner = nullptr, *hub_group_owner = nullptr, *hub_changed = nullptr;
+  bool hub_ids_identity = false;  // the hubs are positions 0 .. n_hubs - 1
   uint32_t *hub_part_w2 = nullptr, *hub_own_w = nullptr;
   int32_t *hub_part_nd = nullptr;
   // control
@@ -368,6 +369,8 @@ void build_hubs(lpa_graph *g) {
     if (g->h_off[v + 1] - g->h_off[v] > lim) ids.push_back((int32_t)v);
   const size_t nh = ids.size();
   g->n_hubs = (int32_t)nh;
+  g->hub_ids_identity = true;
+  for (size_t k = 0; k < nh; ++k) g->hub_ids_identity &= ids[k] == (int32_t)k;
   std::vector<int32_t> chunks(nh), pbits(nh);
   std::vector<int64_t> pair_base(nh), cnt_base(nh);
   int64_t pairs = 0, parts = 0, nch = 0;
@@ -428,6 +431,7 @@ void build_hubs(lpa_graph *g) {
 HubArgs hub_args(lpa_graph *g) {
   HubArgs h{};
   h.n_hubs = g->n_hubs;
+  h.ids_identity = g->hub_ids_identity ? 1 : 0;
   h.part_cap = g->hub_part_cap;
   h.ids = g->hub_ids;
   h.chunks = g->hub_chunks;
@@ -1625,14 +1629,19 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
     launch_run_begin(g->ctl, tolerance, run_sweeps, g->n, g->n_active, g->fcount, nfc, g->host_done_dev, dense,
                      !init_labels && !init_flags, gate ? 1 : 0, g->stream);
     if (g->ngraphs) launch_batch_begin(g->ctl, batch_args(g), g->n, g->nlive, batch_mode, max_iters, g->stream);
+    // The stop test is read one sweep behind, so that the next sweep is queued
+    // while the host waits; a deterministic sweep (thousands of colour-step
+    // kernels) is long enough to wait for before queueing the next one, which
+    // saves the sweep that would only find the run done.
+    const int behind = mode == LPA_MODE_DETERMINISTIC ? 0 : 1;
     if (one_launch && exec) {
       HIP_OK(hipGraphLaunch(exec, g->stream));
     } else
     for (int s = 0; s < run_sweeps; ++s) {
       launch_sweep(s);
       HIP_OK(hipEventRecord(lag[s & 1], g->stream));
-      if (s >= 1) {
-        HIP_OK(hipEventSynchronize(lag[(s - 1) & 1]));
+      if (s >= behind) {
+        HIP_OK(hipEventSynchronize(lag[(s - behind) & 1]));
         if (__atomic_load_n(g->host_done, __ATOMIC_ACQUIRE)) break;
       }
     }
@@ -1643,8 +1652,8 @@ int lpa_run(lpa_graph *g, double tolerance, int max_iters, int mode, int prune, 
       for (int s = 0; s < budget; ++s) {
         launch_sweep(max_iters + s);  // sweeps after a verification run in the late schedule
         HIP_OK(hipEventRecord(lag[s & 1], g->stream));
-        if (s >= 1) {
-          HIP_OK(hipEventSynchronize(lag[(s - 1) & 1]));
+        if (s >= behind) {
+          HIP_OK(hipEventSynchronize(lag[(s - behind) & 1]));
           if (__atomic_load_n(g->host_done, __ATOMIC_ACQUIRE)) break;
         }
       }

@@ -21,6 +21,20 @@
 
 namespace gvelpa {
 
+// Ordinal of vertex v among the sorted hub ids, -1 if it is no hub.  In
+// degree order the hubs are the first n_hubs positions (ids[k] == k) and the
+// ordinal is v itself; otherwise a binary search over the ids.
+__device__ __forceinline__ int hub_ordinal(const HubArgs &h, int v) {
+  if (h.ids_identity) return v >= 0 && v < h.n_hubs ? v : -1;
+  int lo = 0, hi = h.n_hubs;  // lower bound of v
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (h.ids[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < h.n_hubs && h.ids[lo] == v ? lo : -1;
+}
+
 __device__ __forceinline__ uint32_t part_of(uint32_t lbl, int pbits) {
   return pbits ? (fmix32(lbl) >> (32 - pbits)) : 0u;
 }
@@ -44,13 +58,8 @@ __global__ __launch_bounds__(PLAN_TILE) void k_hub_plan_tile(ScanArgs a, HubArgs
     u64 kc = 0, kp = 0, kg = 0;
     if (i < count) {
       const int v = a.front[i];
-      int lo = 0, hi = h.n_hubs;  // lower bound of v among the sorted hub ids
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (h.ids[mid] < v) lo = mid + 1;
-        else hi = mid;
-      }
-      if (lo >= h.n_hubs || h.ids[lo] != v) {  // every hub-bin vertex is listed; never expected
+      int lo = hub_ordinal(h, v);
+      if (lo < 0) {  // every hub-bin vertex is listed; never expected
         atomicOr(&a.ctl->error, 4);
         lo = 0;
       } else {
@@ -159,13 +168,8 @@ __global__ __launch_bounds__(PLAN_TILE) void k_hub_plan_small(ScanArgs a, HubArg
   u64 kc = 0, kp = 0, kg = 0;
   if (i < count) {
     const int v = a.front[i];
-    int lo = 0, hi = h.n_hubs;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (h.ids[mid] < v) lo = mid + 1;
-      else hi = mid;
-    }
-    if (lo >= h.n_hubs || h.ids[lo] != v) {
+    int lo = hub_ordinal(h, v);
+    if (lo < 0) {
       atomicOr(&a.ctl->error, 4);
       lo = 0;
     } else {
