@@ -321,6 +321,14 @@ struct HubArgs {
   u64 *blk;                  // per tile of frontier hubs: work items (chunks, partitions, groups), then offsets
   int32_t gbits;             // log2 partitions per merge group (0: every partition its own work item)
   int32_t ids_identity;      // ids[k] == k for every hub (degree order): a hub's ordinal is its position
+  // Chunks of all hubs in increasing storage position of their first
+  // neighbour, (hub ordinal << 32 | chunk of the hub); with static_order the
+  // chunk kernel walks them instead of the step's chunk ids, so that the
+  // chunks running at the same time gather labels from nearby positions.
+  const u64 *sorder;
+  int64_t sorder_len;
+  int32_t static_order;
+  int32_t *slot_of;          // per hub ordinal: its frontier entry in the current step, -1 when not flagged
 };
 
 // Wave64 helpers.

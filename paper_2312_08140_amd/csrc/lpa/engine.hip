@@ -123,6 +123,10 @@ struct lpa_graph {
   u64 *hub_cstart = nullptr, *hub_pstart = nullptr, *hub_gstart = nullptr, *hub_blk = nullptr;
   int32_t *hub_chunk_owner = nullptr, *hub_group_owner = nullptr, *hub_changed = nullptr;
   bool hub_ids_identity = false;  // the hubs are positions 0 .. n_hubs - 1
+  u64 *hub_sorder = nullptr;      // chunks of all hubs by the position of their first neighbour
+  int64_t hub_sorder_len = 0;
+  int32_t *hub_slot_of = nullptr;  // per hub ordinal: frontier entry in the current step, or -1
+  bool hub_static_ok = false;      // the sweeps being emitted may walk the hub chunks in position order
   uint32_t *hub_part_w2 = nullptr, *hub_own_w = nullptr;
   int32_t *hub_part_nd = nullptr;
   // control
@@ -358,7 +362,7 @@ void build_hubs(lpa_graph *g) {
                    (void **)&g->hub_pstart, (void **)&g->hub_gstart, (void **)&g->hub_blk, (void **)&g->hub_chunk_owner,
                    (void **)&g->hub_group_owner,
                    (void **)&g->hub_changed, (void **)&g->hub_part_w2, (void **)&g->hub_own_w,
-                   (void **)&g->hub_part_nd};
+                   (void **)&g->hub_part_nd, (void **)&g->hub_sorder, (void **)&g->hub_slot_of};
   for (void **b : bufs) {
     dfree(g, *b);
     *b = nullptr;
@@ -416,6 +420,42 @@ void build_hubs(lpa_graph *g) {
   g->hub_ovf = dalloc_n<uint32_t>(g, nh ? 4 * HUB_OVERFLOW_CAP : 4);
   HIP_OK(hipMemsetAsync(g->hub_pcnt, 0, sizeof(int32_t) * std::max<int64_t>(1, parts), g->stream));
   HIP_OK(hipMemsetAsync(g->hub_ovf_count, 0, sizeof(u64), g->stream));
+  g->hub_slot_of = dalloc_n<int32_t>(g, n1);
+  HIP_OK(hipMemsetAsync(g->hub_slot_of, 0xFF, sizeof(int32_t) * n1, g->stream));  // -1: no hub flagged
+  // Chunk order of a step that holds every hub: all chunks by the storage
+  // position of their first neighbour (rows are sorted, so a chunk covers a
+  // position range beginning there); ties by hub and chunk.
+  g->hub_sorder_len = 0;
+  const char *hub_order = std::getenv("GVELPA_HUB_ORDER");  // testing: "frontier" keeps the step's chunk ids
+  if (nch > 0 && !(hub_order && std::strcmp(hub_order, "frontier") == 0)) {
+    std::vector<int64_t> at((size_t)nch);
+    std::vector<u64> kj((size_t)nch);
+    size_t c = 0;
+    for (size_t k = 0; k < nh; ++k)
+      for (int32_t j = 0; j < chunks[k]; ++j, ++c) {
+        at[c] = g->h_off[ids[k]] + (int64_t)j * HUB_CHUNK;
+        kj[c] = ((u64)k << 32) | (uint32_t)j;
+      }
+    int64_t *at_d = dalloc_n<int64_t>(g, nch);
+    int32_t *pos_d = dalloc_n<int32_t>(g, nch);
+    HIP_OK(hipMemcpyAsync(at_d, at.data(), sizeof(int64_t) * nch, hipMemcpyHostToDevice, g->stream));
+    launch_gather_at(g->idx, at_d, nch, pos_d, g->stream);
+    std::vector<int32_t> pos((size_t)nch);
+    HIP_OK(hipMemcpyAsync(pos.data(), pos_d, sizeof(int32_t) * nch, hipMemcpyDeviceToHost, g->stream));
+    HIP_OK(hipStreamSynchronize(g->stream));
+    dfree(g, at_d);
+    dfree(g, pos_d);
+    std::vector<int64_t> perm((size_t)nch);
+    for (int64_t q = 0; q < nch; ++q) perm[(size_t)q] = q;
+    std::sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) {
+      return pos[(size_t)x] != pos[(size_t)y] ? pos[(size_t)x] < pos[(size_t)y] : x < y;
+    });
+    std::vector<u64> sorted((size_t)nch);
+    for (int64_t q = 0; q < nch; ++q) sorted[(size_t)q] = kj[(size_t)perm[(size_t)q]];
+    g->hub_sorder = dalloc_n<u64>(g, nch);
+    HIP_OK(hipMemcpyAsync(g->hub_sorder, sorted.data(), sizeof(u64) * nch, hipMemcpyHostToDevice, g->stream));
+    g->hub_sorder_len = nch;
+  }
   if (nh) {
     HIP_OK(hipMemcpyAsync(g->hub_ids, ids.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, g->stream));
     HIP_OK(hipMemcpyAsync(g->hub_chunks, chunks.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, g->stream));
@@ -432,6 +472,9 @@ HubArgs hub_args(lpa_graph *g) {
   HubArgs h{};
   h.n_hubs = g->n_hubs;
   h.ids_identity = g->hub_ids_identity ? 1 : 0;
+  h.sorder = g->hub_sorder;
+  h.sorder_len = g->hub_sorder_len;
+  h.slot_of = g->hub_slot_of;
   h.part_cap = g->hub_part_cap;
   h.ids = g->hub_ids;
   h.chunks = g->hub_chunks;
@@ -698,7 +741,9 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
                         h);
       tk_end(g, st, TK_HUB_FINISH);
     } else if (b == HUB_BIN) {
-      const HubArgs h = hub_args(g);
+      HubArgs h = hub_args(g);
+      // a step that may hold every hub walks their chunks in position order
+      h.static_order = g->hub_static_ok && g->hub_sorder_len > 0 && seg == g->n_hubs;
       tk_begin(g, st);
       launch_hub_plan(a, h, seg, grid_cap(seg, 1, max_blocks), std::max(1, std::min(hub_plan_tiles(seg), max_blocks)),
                       st);
@@ -734,6 +779,7 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late, int
   // the deterministic mode's colour steps hold few hubs each: every partition
   // its own merge work item, merged in parallel (its steps are latency-bound)
   g->hub_gbits = mode == LPA_MODE_DETERMINISTIC ? 0 : HUB_PART_GROUP_BITS;
+  g->hub_static_ok = mode == LPA_MODE_ASYNC;
   if (g->gate_active) {
     tk_begin(g, st);
     launch_gate_pass(g->ctl, g->gate_f, g->gate_z, g->cur_feat, g->F, g->gskip, g->n, g->cu_count,

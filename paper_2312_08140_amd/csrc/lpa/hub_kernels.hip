@@ -63,6 +63,7 @@ __global__ __launch_bounds__(PLAN_TILE) void k_hub_plan_tile(ScanArgs a, HubArgs
         atomicOr(&a.ctl->error, 4);
         lo = 0;
       } else {
+        h.slot_of[lo] = i;
         kc = (u64)h.chunks[lo];
         kp = (u64)1 << h.pbits[lo];
         kg = (u64)hub_merge_groups(h.pbits[lo], h.gbits);
@@ -173,6 +174,7 @@ __global__ __launch_bounds__(PLAN_TILE) void k_hub_plan_small(ScanArgs a, HubArg
       atomicOr(&a.ctl->error, 4);
       lo = 0;
     } else {
+      h.slot_of[lo] = i;
       kc = (u64)h.chunks[lo];
       kp = (u64)1 << h.pbits[lo];
       kg = (u64)hub_merge_groups(h.pbits[lo], h.gbits);
@@ -262,15 +264,26 @@ __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
                 "the partition counters fit in the table's memory");
   __shared__ u64 T[HUB_CHUNK_SLOTS];
   int32_t *hist = reinterpret_cast<int32_t *>(T);
-  const u64 total = a.ctl->hub_chunks;
+  const u64 total = h.static_order ? (u64)h.sorder_len : a.ctl->hub_chunks;
   int err = 0;
   for (u64 c = blockIdx.x; c < total; c += gridDim.x) {
-    const int i = h.chunk_owner[c];
+    int i, k;
+    int64_t j;  // chunk of the hub
+    if (h.static_order) {
+      const u64 sc = h.sorder[c];
+      k = (int)(sc >> 32);
+      i = h.slot_of[k];
+      if (i < 0) continue;  // the hub is not flagged in this step (uniform in the workgroup)
+      j = (int64_t)(uint32_t)sc;
+    } else {
+      i = h.chunk_owner[c];
+      k = h.ord[i];
+      j = (int64_t)(c - h.cstart[i]);
+    }
     const int v = a.front[i];
-    const int k = h.ord[i];
     const int pb = h.pbits[k];
     const int P = 1 << pb;
-    const int64_t eb = a.off[v] + (int64_t)(c - h.cstart[i]) * HUB_CHUNK;
+    const int64_t eb = a.off[v] + j * HUB_CHUNK;
     const int64_t ee = min(a.off[v + 1], eb + (int64_t)HUB_CHUNK);
     for (int s = threadIdx.x; s < HUB_CHUNK_SLOTS; s += 256) T[s] = EMPTY;
     __syncthreads();
@@ -503,6 +516,7 @@ __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
                        record_lastp(a.f.feat + (int64_t)v * FEAT_STRIDE));
     }
     if (lane == 0) {
+      h.slot_of[h.ord[i]] = -1;  // not flagged until a later plan says so
       h.changed[i] = changed;
       n_scanned += (u64)(a.off[v + 1] - a.off[v]);
       ++n_vert;

@@ -460,6 +460,14 @@ void launch_bin_scatter(const int64_t *off, int64_t n, const int32_t *color, con
 }
 uint32_t phase_seed() { return PHASE_SEED; }
 
+__global__ void k_gather_at(const int32_t *idx, const int64_t *at, int64_t count, int32_t *out) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < count; c += (int64_t)gridDim.x * blockDim.x)
+    out[c] = idx[at[c]];
+}
+void launch_gather_at(const int32_t *idx, const int64_t *at, int64_t count, int32_t *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_at, dim3(grid_for(count, 256)), dim3(256), 0, st, idx, at, count, out);
+}
+
 void launch_check_block_diagonal(const int64_t *off, const int32_t *idx, const int32_t *gid, int64_t n, int32_t *bad,
                                  hipStream_t st) {
   hipLaunchKernelGGL(k_check_block_diagonal, dim3(grid_for(n, 4, 16384)), dim3(256), 0, st, off, idx, gid, n, bad);

@@ -133,6 +133,8 @@ hipError_t sort_rows_chunk(const int64_t *off, int64_t r0, int64_t r1, int64_t e
                            void *w, int wk, u64 *keys, int32_t *perm, void *wcopy, void *temp, int64_t temp_bytes,
                            hipStream_t st);
 void launch_gather_i32(int32_t *dst, const int32_t *src, const int32_t *index, int64_t n, hipStream_t st);
+// out[c] = idx[at[c]] (64-bit positions)
+void launch_gather_at(const int32_t *idx, const int64_t *at, int64_t count, int32_t *out, hipStream_t st);
 void launch_gather_u8(uint8_t *dst, const uint8_t *src, const int32_t *index, int64_t n, hipStream_t st);
 
 // gate_kernels.hip: the gate network's forward pass, gradient of the weighted

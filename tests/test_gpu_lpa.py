@@ -473,6 +473,33 @@ def test_giant_hub_beyond_lds_partition_counts():
     assert np.all(ref["labels"] == 1) and st["iterations"] == 2
 
 
+@pytest.mark.parametrize("snapshot", [0, 1])
+def test_hub_chunk_position_order_changes_nothing(monkeypatch, snapshot):
+    """Every vertex through the hub path, one asynchronous step per sweep: a
+    sweep is then deterministic (a hub's label changes only after all chunks
+    are merged), so walking the chunks of all hubs in the position order of
+    their first neighbour must give exactly the labels and per-sweep counts
+    of the step's own chunk order."""
+    g = gg.rmat(13, 8, seed=21, weighted=True)
+    res = []
+    for order in ("frontier", "position"):
+        if order == "frontier":
+            monkeypatch.setenv("GVELPA_HUB_ORDER", "frontier")
+        else:
+            monkeypatch.delenv("GVELPA_HUB_ORDER", raising=False)
+        G = abi.LPAGraph(g)
+        G.set_bins([0, 0, 0, 0, 0, 0])
+        G.set_async_schedule(1, 0, 1)
+        G.set_first_sweep(snapshot)
+        lab, st = G.run(0.05, 20, ASYNC, True)
+        say(f"{order} order: sweeps={st['iterations']} changed={st['changed'][:st['iterations']]}")
+        res.append((lab, st))
+        G.close()
+    assert np.array_equal(res[0][0], res[1][0])
+    for key in ("iterations", "changed", "frontier", "edges_scanned"):
+        assert res[0][1][key] == res[1][1][key], key
+
+
 def test_hub_partition_spill_path(monkeypatch):
     """With partitions capped at 3 entries, almost every label spills to the
     shared overflow area; results must not change.  Rows above 512 entries
