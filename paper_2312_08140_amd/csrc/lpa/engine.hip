@@ -60,6 +60,11 @@ struct lpa_graph {
   int device = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
+  // deterministic sweeps under capture: the bins of a colour step on a second
+  // branch of the graph, beside the hub kernels (fork after the compaction,
+  // join before the next step)
+  hipStream_t side_stream = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int64_t n = 0, m = 0;
   int64_t n_active = 0;  // vertices with >= 1 stored entry
   // graph
@@ -690,8 +695,12 @@ ScanArgs base_args(lpa_graph *g, int prune) {
 
 // One step: compact the flagged vertices of `list` (bin segments given by
 // absolute `bounds` into list/front), then process the bins, hubs first.
+// side: a second stream joined to the capture; the step's bin kernels go there
+// while the hub kernels stay on st (a deterministic colour step: its vertices
+// are pairwise non-adjacent, so bins and hubs neither read nor write each
+// other's labels, and both only set flags).
 void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t *bounds, int32_t *fcount, int prune,
-               int64_t hub_chunks, int64_t hub_parts, int snap_kernels = 0) {
+               int64_t hub_chunks, int64_t hub_parts, int snap_kernels = 0, hipStream_t side = nullptr) {
   const int64_t base = bounds[0];
   const int64_t len = bounds[NBINS] - base;
   if (len <= 0) return;
@@ -712,6 +721,14 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
   launch_compact(ca, grid_cap(len, 2048, 4096), st);
   tk_end(g, st, TK_COMPACT);
   const int max_blocks = g->cu_count * 8;
+  bool fork = false;  // the step's bin kernels run on the side branch
+  if (side)
+    for (int b = 0; b < HUB_BIN; ++b) fork |= bounds[b + 1] > bounds[b];
+  if (fork) {
+    HIP_OK(hipEventRecord(g->fork_ev, st));
+    HIP_OK(hipStreamWaitEvent(side, g->fork_ev, 0));
+  }
+  const hipStream_t bst = fork ? side : st;  // stream of the bin kernels
   for (int k = 0; k < NBINS; ++k) {
     // bins from the hubs down to degree 1, or (hubs_last) the hubs after the others
     const int b = !g->hubs_last ? NBINS - 1 - k : (k < NBINS - 1 ? NBINS - 2 - k : HUB_BIN);
@@ -765,10 +782,14 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
       tk_end(g, st, TK_FIRST);
     } else {
       const int per_block = bin_vertices_per_block(b, g->variant[b]);
-      tk_begin(g, st);
-      launch_scan_bin(b, g->variant[b], g->wk, g->feat_on, grid_cap(seg, per_block, max_blocks), st, a);
-      tk_end(g, st, TK_BIN0 + b);
+      tk_begin(g, bst);
+      launch_scan_bin(b, g->variant[b], g->wk, g->feat_on, grid_cap(seg, per_block, max_blocks), bst, a);
+      tk_end(g, bst, TK_BIN0 + b);
     }
+  }
+  if (fork) {
+    HIP_OK(hipEventRecord(g->join_ev, side));
+    HIP_OK(hipStreamWaitEvent(st, g->join_ev, 0));
   }
 }
 
@@ -787,9 +808,11 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late, int
     tk_end(g, st, TK_GATE);
   }
   if (mode == LPA_MODE_DETERMINISTIC) {
+    // under capture, each colour step's bins form a branch beside its hub kernels
+    const hipStream_t side = st == g->cap_stream ? g->side_stream : nullptr;
     for (int c = 0; c < g->ncol; ++c)
       emit_step(g, st, g->dlist, &g->dstart[(size_t)c * NBINS], g->fcount + (size_t)c * NBINS, prune,
-                g->col_hub_chunks[c], g->col_hub_parts[c]);
+                g->col_hub_chunks[c], g->col_hub_parts[c], 0, side);
   } else {
     const lpa_graph::AsyncSched &sc = async_sched(g, late);
     for (int ph = 0; ph < sc.nphase; ++ph)
@@ -944,6 +967,9 @@ void lpa_destroy(lpa_graph *g) {
   for (auto &o : g->owned) (void)hipFree(o.first);
   if (g->host_done) (void)hipHostFree(g->host_done);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  if (g->side_stream) (void)hipStreamDestroy(g->side_stream);
+  if (g->fork_ev) (void)hipEventDestroy(g->fork_ev);
+  if (g->join_ev) (void)hipEventDestroy(g->join_ev);
   delete g;
 }
 
@@ -992,6 +1018,9 @@ static int create_graph(lpa_graph **out, int64_t n, int64_t m, const int64_t *of
     g->cu_count = prop.multiProcessorCount;
     HIP_OK(hipDeviceGetAttribute(&g->wall_khz, hipDeviceAttributeWallClockRate, device));
     HIP_OK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+    HIP_OK(hipStreamCreateWithFlags(&g->side_stream, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&g->join_ev, hipEventDisableTiming));
     HIP_OK(hipHostMalloc((void **)&g->host_done, sizeof(int32_t), hipHostMallocMapped));
     *g->host_done = 0;
     HIP_OK(hipHostGetDevicePointer((void **)&g->host_done_dev, g->host_done, 0));
