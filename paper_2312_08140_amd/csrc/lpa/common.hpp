@@ -61,6 +61,10 @@ __host__ __device__ constexpr int hub_merge_groups(int pbits, int gbits) {
 constexpr int HUB_MAX_PBITS = 21;  // partitions for hubs of up to 2^31 entries
 constexpr int HUB_LDS_PBITS = 12;  // up to here the chunk kernel counts its partitions in LDS
 constexpr int64_t HUB_OVERFLOW_CAP = 1 << 22;  // shared spill area for over-full partitions
+// Most partition maxima (chunks x partitions over a step's hubs) for which a
+// step decides and marks its hubs in one kernel, every chunk re-reading its
+// hub's maxima (8 MB of reads at most).
+constexpr int64_t HUB_FUSED_READS = 1 << 20;
 
 // Runtime degree limits of bins 0..NBINS-2 (the hub bin takes the rest).
 struct BinLimits {
@@ -313,7 +317,6 @@ struct HubArgs {
   u64 *gstart;               // per frontier entry: first merge group id of the step
   int32_t *chunk_owner;      // per chunk id of the step: frontier entry
   int32_t *group_owner;      // per merge group id of the step: frontier entry
-  int32_t *changed;          // per frontier entry: 1 if the hub took a new label
   uint32_t *part_w2;         // FEAT: second largest label weight of each partition
   int32_t *part_nd;          // FEAT: distinct labels of each partition
   uint32_t *own_w;           // FEAT: per frontier entry, weight of the hub's own label
@@ -329,6 +332,8 @@ struct HubArgs {
   int64_t sorder_len;
   int32_t static_order;
   int32_t *slot_of;          // per hub ordinal: its frontier entry in the current step, -1 when not flagged
+  int32_t *cur;              // per frontier entry: the hub's label when the step was planned
+  int32_t *changed;          // per frontier entry: 1 if the hub took a new label (k_hub_decide)
 };
 
 // Wave64 helpers.

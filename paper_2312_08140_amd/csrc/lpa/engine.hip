@@ -116,6 +116,7 @@ struct lpa_graph {
   int32_t hub_part_cap = HUB_PART_CAP;
   std::vector<int32_t> h_hub_ids, h_hub_chunks, h_hub_parts;
   std::vector<int64_t> col_hub_chunks, col_hub_parts;  // per colour class (deterministic grids)
+  std::vector<int64_t> col_hub_reads;  // per colour class: sum over its hubs of chunks x partitions
   std::vector<int32_t> h_color;
   int32_t *hub_ids = nullptr, *hub_chunks = nullptr, *hub_pbits = nullptr;
   int64_t *hub_pair_base = nullptr, *hub_cnt_base = nullptr;
@@ -131,6 +132,7 @@ struct lpa_graph {
   u64 *hub_sorder = nullptr;      // chunks of all hubs by the position of their first neighbour
   int64_t hub_sorder_len = 0;
   int32_t *hub_slot_of = nullptr;  // per hub ordinal: frontier entry in the current step, or -1
+  int32_t *hub_cur = nullptr;      // per frontier entry: label before the step
   bool hub_static_ok = false;      // the sweeps being emitted may walk the hub chunks in position order
   uint32_t *hub_part_w2 = nullptr, *hub_own_w = nullptr;
   int32_t *hub_part_nd = nullptr;
@@ -367,7 +369,7 @@ void build_hubs(lpa_graph *g) {
                    (void **)&g->hub_pstart, (void **)&g->hub_gstart, (void **)&g->hub_blk, (void **)&g->hub_chunk_owner,
                    (void **)&g->hub_group_owner,
                    (void **)&g->hub_changed, (void **)&g->hub_part_w2, (void **)&g->hub_own_w,
-                   (void **)&g->hub_part_nd, (void **)&g->hub_sorder, (void **)&g->hub_slot_of};
+                   (void **)&g->hub_part_nd, (void **)&g->hub_sorder, (void **)&g->hub_slot_of, (void **)&g->hub_cur};
   for (void **b : bufs) {
     dfree(g, *b);
     *b = nullptr;
@@ -414,6 +416,7 @@ void build_hubs(lpa_graph *g) {
   g->hub_pstart = dalloc_n<u64>(g, n1);
   g->hub_gstart = dalloc_n<u64>(g, n1);
   g->hub_blk = dalloc_n<u64>(g, 3 * (hub_plan_tiles(n1) + 1));
+  g->hub_cur = dalloc_n<int32_t>(g, n1);
   g->hub_changed = dalloc_n<int32_t>(g, n1);
   g->hub_own_w = dalloc_n<uint32_t>(g, n1);
   g->hub_part_w2 = dalloc_n<uint32_t>(g, std::max<int64_t>(1, parts));
@@ -480,6 +483,8 @@ HubArgs hub_args(lpa_graph *g) {
   h.sorder = g->hub_sorder;
   h.sorder_len = g->hub_sorder_len;
   h.slot_of = g->hub_slot_of;
+  h.cur = g->hub_cur;
+  h.changed = g->hub_changed;
   h.part_cap = g->hub_part_cap;
   h.ids = g->hub_ids;
   h.chunks = g->hub_chunks;
@@ -499,7 +504,6 @@ HubArgs hub_args(lpa_graph *g) {
   h.blk = g->hub_blk;
   h.gbits = g->hub_gbits;
   h.group_owner = g->hub_group_owner;
-  h.changed = g->hub_changed;
   h.part_w2 = g->hub_part_w2;
   h.part_nd = g->hub_part_nd;
   h.own_w = g->hub_own_w;
@@ -635,10 +639,12 @@ void ensure_dlists(lpa_graph *g) {
   ensure_fcount(g, nkeys);
   g->col_hub_chunks.assign(std::max(1, g->ncol), 0);
   g->col_hub_parts.assign(std::max(1, g->ncol), 0);
+  g->col_hub_reads.assign(std::max(1, g->ncol), 0);
   for (size_t k = 0; k < g->h_hub_ids.size(); ++k) {
     const int c = g->h_color[g->h_hub_ids[k]];
     g->col_hub_chunks[c] += g->h_hub_chunks[k];
     g->col_hub_parts[c] += g->h_hub_parts[k];
+    g->col_hub_reads[c] += (int64_t)g->h_hub_chunks[k] * g->h_hub_parts[k];
   }
   g->dlists_ready = true;
 }
@@ -700,7 +706,8 @@ ScanArgs base_args(lpa_graph *g, int prune) {
 // are pairwise non-adjacent, so bins and hubs neither read nor write each
 // other's labels, and both only set flags).
 void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t *bounds, int32_t *fcount, int prune,
-               int64_t hub_chunks, int64_t hub_parts, int snap_kernels = 0, hipStream_t side = nullptr) {
+               int64_t hub_chunks, int64_t hub_parts, int snap_kernels = 0, hipStream_t side = nullptr,
+               bool fuse_finish = false) {
   const int64_t base = bounds[0];
   const int64_t len = bounds[NBINS] - base;
   if (len <= 0) return;
@@ -754,8 +761,8 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
       tk_end(g, st, TK_FIRST);
       a.bin = FIRST_SLOT;
       tk_begin(g, st);
-      launch_hub_finish(grid_cap(seg, 4, max_blocks), grid_cap(hub_chunks, 1, max_blocks * 2), prune, false, st, a,
-                        h);
+      launch_hub_finish(grid_cap(seg, 4, max_blocks), grid_cap(hub_chunks, 1, max_blocks * 2), prune, false,
+                        fuse_finish, st, a, h);
       tk_end(g, st, TK_HUB_FINISH);
     } else if (b == HUB_BIN) {
       HubArgs h = hub_args(g);
@@ -772,8 +779,8 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
       launch_hub_part(grid_cap(hub_parts, 1, max_blocks * 2), g->feat_on, st, a, h);
       tk_end(g, st, TK_HUB_PART);
       tk_begin(g, st);
-      launch_hub_finish(grid_cap(seg, 4, max_blocks), grid_cap(hub_chunks, 1, max_blocks * 2), prune, g->feat_on, st,
-                        a, h);
+      launch_hub_finish(grid_cap(seg, 4, max_blocks), grid_cap(hub_chunks, 1, max_blocks * 2), prune, g->feat_on,
+                        fuse_finish, st, a, h);
       tk_end(g, st, TK_HUB_FINISH);
     } else if (first) {
       const int per_block = bin_vertices_per_block(b, g->variant[b]);
@@ -810,9 +817,12 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late, int
   if (mode == LPA_MODE_DETERMINISTIC) {
     // under capture, each colour step's bins form a branch beside its hub kernels
     const hipStream_t side = st == g->cap_stream ? g->side_stream : nullptr;
+    // a colour step with little hub work decides and marks its hubs in one
+    // kernel (every chunk re-reads its hub's partition maxima: at most
+    // HUB_FUSED_READS of them in the step)
     for (int c = 0; c < g->ncol; ++c)
       emit_step(g, st, g->dlist, &g->dstart[(size_t)c * NBINS], g->fcount + (size_t)c * NBINS, prune,
-                g->col_hub_chunks[c], g->col_hub_parts[c], 0, side);
+                g->col_hub_chunks[c], g->col_hub_parts[c], 0, side, g->col_hub_reads[c] <= HUB_FUSED_READS);
   } else {
     const lpa_graph::AsyncSched &sc = async_sched(g, late);
     for (int ph = 0; ph < sc.nphase; ++ph)

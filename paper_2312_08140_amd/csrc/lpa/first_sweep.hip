@@ -134,7 +134,7 @@ __global__ __launch_bounds__(BLOCK) void k_first_scan(ScanArgs a) {
 
 // Hub chunks: the chunk's best key, combined per hub with a 64-bit atomic
 // maximum in the slot of the hub's first partition (zeroed by k_hub_owner);
-// k_hub_decide then takes the maximum over the partitions as usual.
+// k_hub_finish then takes the maximum over the partitions as usual.
 template <int WK>
 __global__ __launch_bounds__(256) void k_hub_first_chunk(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;

@@ -13,7 +13,9 @@
 //                 the heaviest label (smallest id on ties);
 //   k_hub_decide  per hub: best over the partitions, update, clear the
 //                 partition counters;
-//   k_hub_mark    per chunk of a hub that changed: flag the neighbours.
+//   k_hub_mark    per chunk of a hub that changed: flag the neighbours;
+//   k_hub_finish  both in one kernel, per chunk (each chunk re-reads the
+//                 hub's partition maxima: for steps with little hub work).
 // Every label falls in exactly one partition, so the per-partition maxima
 // combine into the strict argmax of Eq. (2).
 #include "sweep_kernels.hpp"
@@ -69,6 +71,7 @@ __global__ __launch_bounds__(PLAN_TILE) void k_hub_plan_tile(ScanArgs a, HubArgs
         kg = (u64)hub_merge_groups(h.pbits[lo], h.gbits);
       }
       h.ord[i] = lo;
+      h.cur[i] = a.C[v];  // the hub's label before the step (its decision compares with it)
       if (h.own_w) h.own_w[i] = 0;
     }
     u64 xc = kc, xp = kp, xg = kg;
@@ -180,6 +183,7 @@ __global__ __launch_bounds__(PLAN_TILE) void k_hub_plan_small(ScanArgs a, HubArg
       kg = (u64)hub_merge_groups(h.pbits[lo], h.gbits);
     }
     h.ord[i] = lo;
+    h.cur[i] = a.C[v];  // the hub's label before the step (its decision compares with it)
     s_k[i] = lo;
     if (h.own_w) h.own_w[i] = 0;
   }
@@ -542,6 +546,79 @@ __global__ __launch_bounds__(256) void k_hub_mark(ScanArgs a, HubArgs h) {
   block_accum<256>(0, 0, 0, n_marks, 0, a.ctl, a.bin);
 }
 
+// Decision and neighbour marks in one pass, one workgroup per chunk of a
+// flagged hub: every workgroup of a hub takes the strict argmax over the hub's
+// partitions (the same in each), compares its label with the label the hub
+// had when the step was planned and, if it differs, flags the neighbours in
+// its chunk; the workgroup of the hub's first chunk also writes the label,
+// the counts and the features and clears the partition counters.
+template <bool FEAT>
+__global__ __launch_bounds__(256) void k_hub_finish(ScanArgs a, HubArgs h) {
+  if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
+  __shared__ u64 red[4];
+  __shared__ TabStats tred[FEAT ? 4 : 1];
+  // a dense sweep sets every flag at its end instead
+  const bool marks = a.prune && !__atomic_load_n(&a.ctl->dense_cur, __ATOMIC_RELAXED);
+  const u64 total = a.ctl->hub_chunks;
+  const int sweep = FEAT ? a.ctl->sweep : 0;
+  u64 n_changed = 0, n_scanned = 0, n_vert = 0, n_marks = 0;
+  for (u64 c = blockIdx.x; c < total; c += gridDim.x) {
+    const int i = h.chunk_owner[c];
+    const int k = h.ord[i];
+    const int v = a.front[i];
+    const int64_t j = (int64_t)(c - h.cstart[i]);  // chunk of the hub
+    const int P = 1 << h.pbits[k];
+    const u64 *pb = h.partbest + h.pstart[i];
+    u64 best = 0;
+    for (int p = threadIdx.x; p < P; p += 256) best = pb[p] > best ? pb[p] : best;
+    best = block_max<256>(best, red);
+    const int32_t cur = h.cur[i];
+    const int32_t cs = best != 0 ? (int32_t)key_label(best, tie_rule_of(a, v)) : cur;
+    const bool changed = cs != cur;
+    if (j == 0) {
+      int32_t *cnt = h.pcnt + h.cnt_base[k];
+      for (int p = threadIdx.x; p < P; p += 256) cnt[p] = 0;  // partitions start empty at the next step
+      if constexpr (FEAT) {
+        TabStats t{0u, 0u, 0};
+        const u64 q0 = h.pstart[i];
+        for (int p = threadIdx.x; p < P; p += 256) {
+          const u64 key = pb[p];
+          TabStats o;
+          o.w1 = key ? (uint32_t)(key >> 32) : 0u;
+          o.w2 = h.part_w2[q0 + p];
+          o.nd = h.part_nd[q0 + p];
+          t = merge_stats(t, o);
+        }
+        t = group_stats<64>(t);
+        if ((threadIdx.x & 63) == 0) tred[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          t = merge_stats(merge_stats(tred[0], tred[1]), merge_stats(tred[2], tred[3]));
+          write_features(a.f, v, sweep, a.off[v + 1] - a.off[v], t, h.own_w[i], changed, a.f.K[v],
+                         record_lastp(a.f.feat + (int64_t)v * FEAT_STRIDE));
+        }
+      }
+      if (threadIdx.x == 0) {
+        if (changed) {
+          a.C[v] = cs;
+          ++n_changed;
+          if (a.chg) a.chg[v] = 1;
+        }
+        h.slot_of[k] = -1;  // not flagged until a later plan says so
+        n_scanned += (u64)(a.off[v + 1] - a.off[v]);
+        ++n_vert;
+      }
+    }
+    if (changed && marks) {
+      const int64_t eb = a.off[v] + j * HUB_CHUNK;
+      const int64_t ee = min(a.off[v + 1], eb + (int64_t)HUB_CHUNK);
+      n_marks += mark_row<256, 8>(a.idx, a.F, eb, ee, v, threadIdx.x);
+    }
+    __syncthreads();  // red and tred are reused by the next chunk
+  }
+  block_accum<256>(n_changed, n_scanned, n_vert, n_marks, 0, a.ctl, a.bin);
+}
+
 void launch_hub_plan(const ScanArgs &a, const HubArgs &h, int64_t max_hubs, int blocks, int tile_blocks,
                      hipStream_t st) {
   if (max_hubs <= PLAN_TILE) {
@@ -566,8 +643,13 @@ void launch_hub_part(int blocks, bool feat, hipStream_t st, const ScanArgs &a, c
   else hipLaunchKernelGGL(k_hub_part<false>, dim3(blocks), dim3(256), 0, st, a, h);
 }
 
-void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, bool feat, hipStream_t st, const ScanArgs &a,
-                       const HubArgs &h) {
+void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, bool feat, bool fused, hipStream_t st,
+                       const ScanArgs &a, const HubArgs &h) {
+  if (fused) {
+    if (feat) hipLaunchKernelGGL(k_hub_finish<true>, dim3(chunk_blocks), dim3(256), 0, st, a, h);
+    else hipLaunchKernelGGL(k_hub_finish<false>, dim3(chunk_blocks), dim3(256), 0, st, a, h);
+    return;
+  }
   if (feat) hipLaunchKernelGGL(k_hub_decide<true>, dim3(hub_blocks), dim3(256), 0, st, a, h);
   else hipLaunchKernelGGL(k_hub_decide<false>, dim3(hub_blocks), dim3(256), 0, st, a, h);
   if (prune) hipLaunchKernelGGL(k_hub_mark, dim3(chunk_blocks), dim3(256), 0, st, a, h);

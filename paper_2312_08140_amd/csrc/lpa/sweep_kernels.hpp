@@ -42,8 +42,10 @@ void launch_hub_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, con
 void launch_first_bin(int bin, int variant, int wk, bool feat, int blocks, hipStream_t st, const ScanArgs &a);
 void launch_hub_first_chunk(int wk, int blocks, hipStream_t st, const ScanArgs &a, const HubArgs &h);
 void launch_hub_part(int blocks, bool feat, hipStream_t st, const ScanArgs &a, const HubArgs &h);
-void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, bool feat, hipStream_t st, const ScanArgs &a,
-                       const HubArgs &h);
+// the hub decision and neighbour marks: k_hub_decide + k_hub_mark, or (fused)
+// k_hub_finish, whose every chunk re-reads the hub's partition maxima
+void launch_hub_finish(int hub_blocks, int chunk_blocks, int prune, bool feat, bool fused, hipStream_t st,
+                       const ScanArgs &a, const HubArgs &h);
 void launch_init_state(const int64_t *off, int32_t *C, uint8_t *F, int64_t n, int set_labels, int set_flags,
                        int clear_isolated, const int32_t *orig, hipStream_t st);
 void launch_run_begin(Ctl *ctl, double tau, int max_iters, int64_t n, int64_t n_active, int32_t *fcount, int nfc,
