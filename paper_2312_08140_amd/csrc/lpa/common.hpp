@@ -334,6 +334,13 @@ struct HubArgs {
   int32_t *slot_of;          // per hub ordinal: its frontier entry in the current step, -1 when not flagged
   int32_t *cur;              // per frontier entry: the hub's label when the step was planned
   int32_t *changed;          // per frontier entry: 1 if the hub took a new label (k_hub_decide)
+  // Static plan (deterministic colour steps): the work items of every hub of
+  // the step's colour are planned once; the "frontier" is the colour's hub
+  // list, taken[i] says whether the compaction took hub i in this step, and
+  // the kernels skip the others.  The counts replace the plan's totals.
+  const uint8_t *taken;
+  int32_t static_plan;
+  int64_t static_count, static_chunks, static_groups;
 };
 
 // Wave64 helpers.

@@ -117,6 +117,14 @@ struct lpa_graph {
   std::vector<int32_t> h_hub_ids, h_hub_chunks, h_hub_parts;
   std::vector<int64_t> col_hub_chunks, col_hub_parts;  // per colour class (deterministic grids)
   std::vector<int64_t> col_hub_reads;  // per colour class: sum over its hubs of chunks x partitions
+  // static hub plans of the colour classes (their hubs in list order): per hub
+  // its ordinal and first chunk / partition / merge group inside its class,
+  // owners of the class's chunks and groups, and the taken flags the
+  // compaction writes; offsets of each class into these arrays
+  int32_t *col_ord = nullptr, *col_chunk_owner = nullptr, *col_group_owner = nullptr;
+  u64 *col_cstart = nullptr, *col_pstart = nullptr;
+  uint8_t *col_taken = nullptr;
+  std::vector<int64_t> col_hub_off, col_chunk_off, col_group_off;
   std::vector<int32_t> h_color;
   int32_t *hub_ids = nullptr, *hub_chunks = nullptr, *hub_pbits = nullptr;
   int64_t *hub_pair_base = nullptr, *hub_cnt_base = nullptr;
@@ -629,6 +637,66 @@ void ensure_colored(lpa_graph *g, uint32_t seed) {
   if (g->async_by_colour && (g->sched[0].nphase > 1 || g->sched[1].nphase > 1)) g->lists_ready = false;
 }
 
+// Static hub plans of the colour classes: each class's hub-bin list segment, in
+// list order, with every hub's work items numbered inside the class (merge
+// groups of one partition, as the deterministic mode merges).
+void build_colour_hub_plans(lpa_graph *g) {
+  void **bufs[] = {(void **)&g->col_ord, (void **)&g->col_chunk_owner, (void **)&g->col_group_owner,
+                   (void **)&g->col_cstart, (void **)&g->col_pstart, (void **)&g->col_taken};
+  for (void **b : bufs) {
+    dfree(g, *b);
+    *b = nullptr;
+  }
+  const int ncol = std::max(1, g->ncol);
+  g->col_hub_off.assign(ncol + 1, 0);
+  g->col_chunk_off.assign(ncol + 1, 0);
+  g->col_group_off.assign(ncol + 1, 0);
+  const size_t nh = g->h_hub_ids.size();
+  if (nh == 0) return;
+  std::vector<int32_t> list((size_t)g->n_active);
+  HIP_OK(hipMemcpyAsync(list.data(), g->dlist, sizeof(int32_t) * g->n_active, hipMemcpyDeviceToHost, g->stream));
+  HIP_OK(hipStreamSynchronize(g->stream));
+  std::vector<int32_t> ord, cown, gown;
+  std::vector<u64> cst, pst;
+  ord.reserve(nh);
+  cst.reserve(nh);
+  pst.reserve(nh);
+  for (int c = 0; c < ncol; ++c) {
+    const int64_t b0 = g->dstart[(size_t)c * NBINS + HUB_BIN], b1 = g->dstart[(size_t)c * NBINS + HUB_BIN + 1];
+    u64 nc = 0, np = 0;
+    for (int64_t q = b0; q < b1; ++q) {
+      const int32_t v = list[(size_t)q];
+      const auto it = std::lower_bound(g->h_hub_ids.begin(), g->h_hub_ids.end(), v);
+      if (it == g->h_hub_ids.end() || *it != v) throw Status{LPA_ERR_INTERNAL};  // every hub-bin vertex is a hub
+      const int32_t k = (int32_t)(it - g->h_hub_ids.begin());
+      const int32_t s = (int32_t)(q - b0);
+      ord.push_back(k);
+      cst.push_back(nc);
+      pst.push_back(np);
+      for (int32_t j = 0; j < g->h_hub_chunks[k]; ++j) cown.push_back(s);
+      for (int32_t j = 0; j < g->h_hub_parts[k]; ++j) gown.push_back(s);
+      nc += (u64)g->h_hub_chunks[k];
+      np += (u64)g->h_hub_parts[k];
+    }
+    g->col_hub_off[c + 1] = (int64_t)ord.size();
+    g->col_chunk_off[c + 1] = (int64_t)cown.size();
+    g->col_group_off[c + 1] = (int64_t)gown.size();
+  }
+  auto up = [&](auto *&dst, const auto &src) {
+    using T = typename std::decay<decltype(src[0])>::type;
+    dst = dalloc_n<T>(g, std::max<int64_t>(1, (int64_t)src.size()));
+    if (!src.empty())
+      HIP_OK(hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, g->stream));
+  };
+  up(g->col_ord, ord);
+  up(g->col_cstart, cst);
+  up(g->col_pstart, pst);
+  up(g->col_chunk_owner, cown);
+  up(g->col_group_owner, gown);
+  g->col_taken = dalloc_n<uint8_t>(g, (int64_t)nh);
+  HIP_OK(hipStreamSynchronize(g->stream));
+}
+
 void ensure_dlists(lpa_graph *g) {
   ensure_lists(g);
   if (g->dlists_ready) return;
@@ -646,6 +714,7 @@ void ensure_dlists(lpa_graph *g) {
     g->col_hub_parts[c] += g->h_hub_parts[k];
     g->col_hub_reads[c] += (int64_t)g->h_hub_chunks[k] * g->h_hub_parts[k];
   }
+  build_colour_hub_plans(g);
   g->dlists_ready = true;
 }
 
@@ -707,7 +776,7 @@ ScanArgs base_args(lpa_graph *g, int prune) {
 // other's labels, and both only set flags).
 void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t *bounds, int32_t *fcount, int prune,
                int64_t hub_chunks, int64_t hub_parts, int snap_kernels = 0, hipStream_t side = nullptr,
-               bool fuse_finish = false) {
+               bool fuse_finish = false, int colour = -1) {
   const int64_t base = bounds[0];
   const int64_t len = bounds[NBINS] - base;
   if (len <= 0) return;
@@ -724,6 +793,14 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
   ca.gdone = g->ngraphs ? g->bgdone : nullptr;
   ca.gskip = g->gate_active ? g->gskip : nullptr;
   ca.f = g->cur_feat;
+  // a colour step of the deterministic mode uses its class's static hub plan:
+  // the compaction marks which of the class's hubs it takes
+  const bool static_hubs = colour >= 0 && g->col_taken && g->hub_gbits == 0 &&
+                           bounds[HUB_BIN + 1] > bounds[HUB_BIN];
+  if (static_hubs) {
+    ca.hub_taken = g->col_taken + g->col_hub_off[colour];
+    ca.ovf_count = g->hub_ovf_count;
+  }
   tk_begin(g, st);
   launch_compact(ca, grid_cap(len, 2048, 4096), st);
   tk_end(g, st, TK_COMPACT);
@@ -768,10 +845,30 @@ void emit_step(lpa_graph *g, hipStream_t st, const int32_t *list, const int64_t 
       HubArgs h = hub_args(g);
       // a step that may hold every hub walks their chunks in position order
       h.static_order = g->hub_static_ok && g->hub_sorder_len > 0 && seg == g->n_hubs;
-      tk_begin(g, st);
-      launch_hub_plan(a, h, seg, grid_cap(seg, 1, max_blocks), std::max(1, std::min(hub_plan_tiles(seg), max_blocks)),
-                      st);
-      tk_end(g, st, TK_HUB_PLAN);
+      if (static_hubs) {
+        // the class's static plan: its hub list is the frontier, untaken hubs are skipped
+        const int64_t ho = g->col_hub_off[colour];
+        h.static_plan = 1;
+        h.taken = g->col_taken + ho;
+        h.static_count = seg;
+        h.static_chunks = g->col_chunk_off[colour + 1] - g->col_chunk_off[colour];
+        h.static_groups = g->col_group_off[colour + 1] - g->col_group_off[colour];
+        h.ord = g->col_ord + ho;
+        h.cstart = g->col_cstart + ho;
+        h.pstart = g->col_pstart + ho;
+        h.gstart = g->col_pstart + ho;  // one partition per merge group
+        h.chunk_owner = g->col_chunk_owner + g->col_chunk_off[colour];
+        h.group_owner = g->col_group_owner + g->col_group_off[colour];
+        h.cur += ho;
+        h.changed += ho;
+        h.own_w += ho;
+        a.front = g->dlist + bounds[HUB_BIN];
+      } else {
+        tk_begin(g, st);
+        launch_hub_plan(a, h, seg, grid_cap(seg, 1, max_blocks),
+                        std::max(1, std::min(hub_plan_tiles(seg), max_blocks)), st);
+        tk_end(g, st, TK_HUB_PLAN);
+      }
       tk_begin(g, st);
       launch_hub_chunk(g->wk, grid_cap(hub_chunks, 1, max_blocks * 2), st, a, h);
       tk_end(g, st, TK_HUB_SCAN);
@@ -822,7 +919,7 @@ void emit_sweep(lpa_graph *g, hipStream_t st, int mode, int prune, int late, int
     // HUB_FUSED_READS of them in the step)
     for (int c = 0; c < g->ncol; ++c)
       emit_step(g, st, g->dlist, &g->dstart[(size_t)c * NBINS], g->fcount + (size_t)c * NBINS, prune,
-                g->col_hub_chunks[c], g->col_hub_parts[c], 0, side, g->col_hub_reads[c] <= HUB_FUSED_READS);
+                g->col_hub_chunks[c], g->col_hub_parts[c], 0, side, g->col_hub_reads[c] <= HUB_FUSED_READS, c);
   } else {
     const lpa_graph::AsyncSched &sc = async_sched(g, late);
     for (int ph = 0; ph < sc.nphase; ++ph)

@@ -268,7 +268,9 @@ __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
                 "the partition counters fit in the table's memory");
   __shared__ u64 T[HUB_CHUNK_SLOTS];
   int32_t *hist = reinterpret_cast<int32_t *>(T);
-  const u64 total = h.static_order ? (u64)h.sorder_len : a.ctl->hub_chunks;
+  const u64 total = h.static_order  ? (u64)h.sorder_len
+                    : h.static_plan ? (u64)h.static_chunks
+                                    : a.ctl->hub_chunks;
   int err = 0;
   for (u64 c = blockIdx.x; c < total; c += gridDim.x) {
     int i, k;
@@ -281,10 +283,16 @@ __global__ __launch_bounds__(256) void k_hub_chunk(ScanArgs a, HubArgs h) {
       j = (int64_t)(uint32_t)sc;
     } else {
       i = h.chunk_owner[c];
+      if (h.static_plan && !h.taken[i]) continue;  // a hub not flagged in this step (uniform in the workgroup)
       k = h.ord[i];
       j = (int64_t)(c - h.cstart[i]);
     }
     const int v = a.front[i];
+    if (h.static_plan && j == 0 && threadIdx.x == 0) {
+      // what the plan records for a flagged hub
+      h.cur[i] = a.C[v];
+      if (h.own_w) h.own_w[i] = 0;
+    }
     const int pb = h.pbits[k];
     const int P = 1 << pb;
     const int64_t eb = a.off[v] + j * HUB_CHUNK;
@@ -447,11 +455,12 @@ __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
   __shared__ u64 T[HUB_PART_SLOTS];
   __shared__ u64 red[4];
   __shared__ int s_cm[HUB_PART_GROUP];  // pairs offered to each partition of the group, spilled ones included
-  const u64 total = a.ctl->hub_groups;
+  const u64 total = h.static_plan ? (u64)h.static_groups : a.ctl->hub_groups;
   const u64 nov = min(*h.ovf_count, (u64)HUB_OVERFLOW_CAP);
   int err = 0;
   for (u64 gq = blockIdx.x; gq < total; gq += gridDim.x) {
     const int i = h.group_owner[gq];
+    if (h.static_plan && !h.taken[i]) continue;  // uniform in the workgroup
     const int k = h.ord[i];
     const int pb = h.pbits[k];
     const int G = 1 << min(h.gbits, pb);
@@ -475,11 +484,15 @@ __global__ __launch_bounds__(256) void k_hub_part(ScanArgs a, HubArgs h) {
 template <bool FEAT>
 __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
-  const int count = *a.fcount;
+  const int count = h.static_plan ? (int)h.static_count : *a.fcount;
   const int lane = threadIdx.x & 63;
   const int sweep = FEAT ? a.ctl->sweep : 0;
   u64 n_changed = 0, n_scanned = 0, n_vert = 0;
   for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < count; i += gridDim.x * 4) {
+    if (h.static_plan && !h.taken[i]) {  // not flagged in this step: nothing decided, no marks
+      if (lane == 0) h.changed[i] = 0;
+      continue;
+    }
     const int v = a.front[i];
     const int P = 1 << h.pbits[h.ord[i]];
     const u64 *pb = h.partbest + h.pstart[i];
@@ -533,7 +546,7 @@ __global__ __launch_bounds__(256) void k_hub_decide(ScanArgs a, HubArgs h) {
 __global__ __launch_bounds__(256) void k_hub_mark(ScanArgs a, HubArgs h) {
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   if (__atomic_load_n(&a.ctl->dense_cur, __ATOMIC_RELAXED)) return;  // dense sweep: flags are set at its end
-  const u64 total = a.ctl->hub_chunks;
+  const u64 total = h.static_plan ? (u64)h.static_chunks : a.ctl->hub_chunks;
   u64 n_marks = 0;
   for (u64 c = blockIdx.x; c < total; c += gridDim.x) {
     const int i = h.chunk_owner[c];
@@ -559,11 +572,12 @@ __global__ __launch_bounds__(256) void k_hub_finish(ScanArgs a, HubArgs h) {
   __shared__ TabStats tred[FEAT ? 4 : 1];
   // a dense sweep sets every flag at its end instead
   const bool marks = a.prune && !__atomic_load_n(&a.ctl->dense_cur, __ATOMIC_RELAXED);
-  const u64 total = a.ctl->hub_chunks;
+  const u64 total = h.static_plan ? (u64)h.static_chunks : a.ctl->hub_chunks;
   const int sweep = FEAT ? a.ctl->sweep : 0;
   u64 n_changed = 0, n_scanned = 0, n_vert = 0, n_marks = 0;
   for (u64 c = blockIdx.x; c < total; c += gridDim.x) {
     const int i = h.chunk_owner[c];
+    if (h.static_plan && !h.taken[i]) continue;  // uniform in the workgroup
     const int k = h.ord[i];
     const int v = a.front[i];
     const int64_t j = (int64_t)(c - h.cstart[i]);  // chunk of the hub

@@ -383,6 +383,7 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
   const int sweep = a.ctl->sweep;
   const bool gate = a.gskip && a.ctl->gate_on && !a.ctl->verify_phase && sweep >= 1;
   int taken_total = 0, gated_total = 0;
+  if (a.ovf_count && blockIdx.x == 0 && threadIdx.x == 0) *a.ovf_count = 0;  // the step's hub spills start empty
   for (int64_t tile = (int64_t)blockIdx.x * 256 * CU; tile < a.len; tile += (int64_t)gridDim.x * 256 * CU) {
     if (threadIdx.x < NBINS) lcount[threadIdx.x] = 0;
     int v[CU];
@@ -423,6 +424,7 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
         slot[r] = atomicAdd(&lcount[bin[r]], 1);
         ++taken_total;
       }
+      if (a.hub_taken && v[r] >= 0 && bin[r] == HUB_BIN) a.hub_taken[p - a.bounds[HUB_BIN]] = f[r];
     }
     __syncthreads();
     if (threadIdx.x < NBINS && lcount[threadIdx.x] > 0)

@@ -24,6 +24,10 @@ struct CompactArgs {
   const int32_t *gdone;  // batched runs: 1 for a graph that has stopped
   const uint8_t *gskip;  // gate decisions of the sweep (k_gate_pass; NULL: no gate)
   FeatArgs f;
+  // static hub plan: taken[p - bounds[HUB_BIN]] = 1 for each hub-bin entry
+  // taken in this step, 0 for the others; the spill counter is cleared
+  uint8_t *hub_taken;
+  u64 *ovf_count;
 };
 
 void launch_compact(const CompactArgs &a, int blocks, hipStream_t st);
