@@ -210,9 +210,11 @@ int lpa_set_variants(lpa_graph *g, const int32_t *variant, int32_t count);
  * order of the bins in a step (lpa_set_bin_order; on a graph with hubs) and,
  * where the rows allow it, the kernels of each step of the first sweep that
  * read the initial labels (lpa_set_first_sweep: none, 1, 3 or all, then 2 and
- * 4 next to the best); the fastest combination is installed (read it back with
- * lpa_get_schedule) and its limits returned in bins_out (int32[6], may be
- * NULL).  Then it times every kernel
+ * 4 next to the best); the fastest combination is kept and, in the
+ * asynchronous mode, each bin's limit is then tried at the other fill levels
+ * on its own (limits kept non-decreasing; a change must be 1.5 % faster); the
+ * result is installed (read it back with lpa_get_schedule) and its limits
+ * returned in bins_out (int32[6], may be NULL).  Then it times every kernel
  * shape variant (per-kernel timing), keeps for each bin the fastest and
  * returns it in variant_out (int32[6], may be NULL) with the chosen kernels'
  * times in bin_ms_out (double[6], ms per run, 0 for an empty bin; may be

@@ -1548,8 +1548,8 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
     int best = 0, best_order = 0, best_snap = 0;
     // one configuration: converged (every graph of a batch) and within the
     // quality bar in the asynchronous mode; its faster run of two
-    auto trial = [&](int c, int order, int snap, double &ms) -> int {
-      int r = lpa_set_bins(g, lim_cand[c], NBINS - 1);
+    auto trial_lim = [&](const int32_t *lim, bool baseline, int order, int snap, double &ms) -> int {
+      int r = lpa_set_bins(g, lim, NBINS - 1);
       if (r == LPA_OK && async) r = lpa_set_bin_order(g, order);
       if (r == LPA_OK && async) r = lpa_set_first_sweep(g, snap);
       if (r != LPA_OK) return r;
@@ -1567,9 +1567,11 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
         r = lpa_modularity(g, nullptr, 0, &q);
         if (r != LPA_OK) return r;
       }
-      const bool first = c == 0 && order == 0 && snap == 0;
-      if (!(first || (converged && (!async || quality_ok(q))))) ms = 1e300;
+      if (!(baseline || (converged && (!async || quality_ok(q))))) ms = 1e300;
       return LPA_OK;
+    };
+    auto trial = [&](int c, int order, int snap, double &ms) -> int {
+      return trial_lim(lim_cand[c], c == 0 && order == 0 && snap == 0, order, snap, ms);
     };
     for (int c = 0; c < (int)(sizeof(lim_cand) / sizeof(lim_cand[0])); ++c)
       for (int order = 0; order < n_order; ++order)
@@ -1595,11 +1597,32 @@ int lpa_autotune(lpa_graph *g, double tolerance, int max_iters, int mode, int32_
           best_snap = snap;
         }
       }
-    rc = lpa_set_bins(g, lim_cand[best], NBINS - 1);
+    // Then, in the asynchronous mode, each bin's limit on its own: the four
+    // fill levels of its table with the other limits kept (limits stay
+    // non-decreasing); a single bin moves less work, so 1.5 % faster suffices.
+    int32_t lim[NBINS - 1];
+    std::memcpy(lim, lim_cand[best], sizeof(lim));
+    if (async)
+      for (int b = 0; b < NBINS - 1; ++b)
+        for (int c = 0; c < (int)(sizeof(lim_cand) / sizeof(lim_cand[0])); ++c) {
+          int32_t cand[NBINS - 1];
+          std::memcpy(cand, lim, sizeof(cand));
+          cand[b] = lim_cand[c][b];
+          if (cand[b] == lim[b] || (b > 0 && cand[b] < cand[b - 1]) || (b < NBINS - 2 && cand[b] > cand[b + 1]))
+            continue;
+          double ms = 0.0;
+          rc = trial_lim(cand, false, best_order, best_snap, ms);
+          if (rc != LPA_OK) return rc;
+          if (ms < 0.985 * best_ms) {
+            best_ms = ms;
+            std::memcpy(lim, cand, sizeof(lim));
+          }
+        }
+    rc = lpa_set_bins(g, lim, NBINS - 1);
     if (rc == LPA_OK && async) rc = lpa_set_bin_order(g, best_order);
     if (rc == LPA_OK && async) rc = lpa_set_first_sweep(g, best_snap);
     if (rc != LPA_OK) return rc;
-    if (bins_out) std::memcpy(bins_out, lim_cand[best], sizeof(lim_cand[best]));
+    if (bins_out) std::memcpy(bins_out, lim, sizeof(lim));
   }
   // 3. Kernel shapes: every bin is its own kernel, so one run per variant
   //    times all bins at once; each run is repeated and the faster kept.
