@@ -21,15 +21,18 @@ constexpr int BIN_SLOTS[NBINS - 1] = {8, 32, 128, 512, 2048, 8192};
 constexpr int DEFAULT_BIN_MAXDEG[NBINS - 1] = {4, 16, 64, 256, 1024, 4096};
 
 // Kernel shapes of a bin: lanes per vertex (bins 0-3: lanes of one wave,
-// bins 4-5: a workgroup), table slots (fixed per bin: BIN_SLOTS) and row
-// entries in flight per lane.  Variant 0 is the default; the others are the
+// bins 4-5: a workgroup), table slots (fixed per bin: BIN_SLOTS), row entries
+// in flight per lane, and (reg) a table in registers instead of LDS: one
+// thread per vertex holds its whole row and sums equal labels by comparing
+// the entries pairwise (the bin's rows have fewer entries than its slots;
+// the default of bin 0).  Variant 0 is the default; the others are the
 // tuner's candidates.
 constexpr int NVARIANTS = 3;
 struct BinShape {
-  int group, slots, unroll;
+  int group, slots, unroll, reg;
 };
 constexpr BinShape BIN_SHAPES[NBINS - 1][NVARIANTS] = {
-    {{1, 8, 4}, {1, 8, 2}, {2, 8, 2}},
+    {{1, 8, 8, 1}, {1, 8, 4}, {2, 8, 2}},
     {{2, 32, 8}, {4, 32, 4}, {2, 32, 4}},
     {{8, 128, 8}, {16, 128, 4}, {8, 128, 4}},
     {{32, 512, 8}, {64, 512, 4}, {32, 512, 4}},

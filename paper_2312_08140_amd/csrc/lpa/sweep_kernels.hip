@@ -525,14 +525,17 @@ struct RowStage {
 // group g at tab[s * GPB + g], so the lanes of a wave - mostly different
 // groups - hit different LDS banks); larger groups keep their table
 // contiguous (the lanes of one group then spread over the banks by hash).
-template <int GROUP, int SLOTS, int U, int WK, bool FEAT>
+// REG: one thread per vertex with its table in registers (rows of at most
+// SLOTS - 1 <= U entries, all loaded at once).
+template <int GROUP, int SLOTS, int U, int WK, bool FEAT, bool REG = false>
 __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
   static_assert(GROUP <= 64 && (GROUP & (GROUP - 1)) == 0, "a group lives inside one wave");
+  static_assert(!REG || (GROUP == 1 && U >= SLOTS - 1), "a register table holds the bin's longest row");
   if (__atomic_load_n(&a.ctl->done, __ATOMIC_RELAXED)) return;
   constexpr int GPB = 256 / GROUP;
   constexpr int BITS = __builtin_ctz(SLOTS);
   constexpr int TS = GROUP <= 2 ? GPB : 1;  // table stride
-  __shared__ u64 tab[GPB * SLOTS];
+  __shared__ u64 tab[REG ? 1 : GPB * SLOTS];
   const int lane = threadIdx.x % GROUP;
   const int grp = threadIdx.x / GROUP;
   u64 *T = TS == 1 ? tab + grp * SLOTS : tab + grp;
@@ -552,24 +555,58 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
   for (; A.v >= 0; i += stride) {
     B.load_row(a, lane);
     const int vc = i + 2 * stride < count ? a.front[i + 2 * stride] : -1;
-    // merge A
-#pragma unroll
-    for (int s = lane; s < SLOTS; s += GROUP) T[s * TS] = EMPTY;
-    wave_lds_sync();
-#pragma unroll
-    for (int r = 0; r < U; ++r)
-      if (A.lbl[r] != 0xFFFFFFFFu) overflow |= !lds_insert<BITS, TS>(T, A.lbl[r], A.w[r]);
     const bool one_pass = A.e - A.b <= (int64_t)GROUP * U;
-    if (!one_pass)
-      overflow |=
-          scan_row_strided<GROUP, U, BITS, TS, WK>(a.idx, a.w, a.C, A.b + (int64_t)GROUP * U, A.e, A.v, lane, T);
-    wave_lds_sync();
-    TabStats ts{0u, 0u, 0};
-    u64 lbest;
     const TieRule tr = tie_rule_of(a, A.v);
-    if constexpr (FEAT) lbest = table_best_stats<GROUP, SLOTS, TS>(T, lane, ts, tr);
-    else lbest = table_best<GROUP, SLOTS, TS>(T, lane, tr);
-    const u64 best = group_max<GROUP>(lbest);
+    TabStats ts{0u, 0u, 0};
+    u64 best = 0;
+    uint32_t own = 0;  // FEAT: summed weight of the vertex's own label
+    if constexpr (REG) {
+      // the label sums of the row in registers: an entry whose label occurs
+      // first at it adds the weights of the later entries with that label
+      overflow |= !one_pass;  // never expected: the bin limit keeps rows within the registers
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        if (A.lbl[r] == 0xFFFFFFFFu) continue;
+        bool first = true;
+        uint32_t sum = A.w[r];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          if (q == r || A.lbl[q] != A.lbl[r]) continue;
+          if (q < r) first = false;
+          else sum += A.w[q];
+        }
+        if (!first) continue;
+        const u64 kk = entry_key(((u64)A.lbl[r] << 32) | sum, tr);
+        best = kk > best ? kk : best;
+        if constexpr (FEAT) {
+          if (A.lbl[r] == (uint32_t)A.cur) own = sum;
+          ++ts.nd;
+          if (sum > ts.w1) {
+            ts.w2 = ts.w1;
+            ts.w1 = sum;
+          } else if (sum > ts.w2) {
+            ts.w2 = sum;
+          }
+        }
+      }
+    } else {
+      // merge A
+#pragma unroll
+      for (int s = lane; s < SLOTS; s += GROUP) T[s * TS] = EMPTY;
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < U; ++r)
+        if (A.lbl[r] != 0xFFFFFFFFu) overflow |= !lds_insert<BITS, TS>(T, A.lbl[r], A.w[r]);
+      if (!one_pass)
+        overflow |=
+            scan_row_strided<GROUP, U, BITS, TS, WK>(a.idx, a.w, a.C, A.b + (int64_t)GROUP * U, A.e, A.v, lane, T);
+      wave_lds_sync();
+      u64 lbest;
+      if constexpr (FEAT) lbest = table_best_stats<GROUP, SLOTS, TS>(T, lane, ts, tr);
+      else lbest = table_best<GROUP, SLOTS, TS>(T, lane, tr);
+      best = group_max<GROUP>(lbest);
+      if constexpr (FEAT) own = table_lookup<BITS, TS>(T, (uint32_t)A.cur);
+    }
     bool changed = false;
     if (best != 0) {
       const int32_t cs = (int32_t)key_label(best, tr);
@@ -588,9 +625,7 @@ __global__ __launch_bounds__(256) void k_scan_group(ScanArgs a) {
     }
     if constexpr (FEAT) {
       const TabStats t = group_stats<GROUP>(ts);
-      if (lane == 0)
-        write_features(a.f, A.v, sweep, A.e - A.b, t, table_lookup<BITS, TS>(T, (uint32_t)A.cur), changed, A.K,
-                       A.lp);
+      if (lane == 0) write_features(a.f, A.v, sweep, A.e - A.b, t, own, changed, A.K, A.lp);
     }
     if (lane == 0) {
       n_scanned += (u64)(A.e - A.b);
@@ -689,7 +724,8 @@ static void launch_shape(dim3 grid, hipStream_t st, const ScanArgs &a) {
   static_assert(sh.slots == BIN_SLOTS[B], "a bin's variants share its table size");
   if constexpr (B <= 3) {
     static_assert(sh.group <= 64, "group bins keep a vertex inside one wave");
-    hipLaunchKernelGGL((k_scan_group<sh.group, sh.slots, sh.unroll, WK, FEAT>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_scan_group<sh.group, sh.slots, sh.unroll, WK, FEAT, sh.reg != 0>), grid, dim3(256), 0, st,
+                       a);
   } else {
     hipLaunchKernelGGL((k_scan_block<sh.group, sh.slots, sh.unroll, WK, FEAT>), grid, dim3(sh.group), 0, st, a);
   }

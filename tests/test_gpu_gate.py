@@ -308,11 +308,12 @@ def test_trained_gate_quality():
 
 def test_trained_gate_saves_work_on_rmat():
     """What the trained network gains: on R-MAT under the one-step schedule,
-    a gate trained on traces of smaller R-MAT graphs (same schedule) scans
-    fewer stored entries than plain pruning, verification sweep included, at
-    the same modularity (within 0.01) and with a verified fixed point.
-    Asynchronous runs differ from run to run (a plain run may stop a sweep
-    early), so the entry counts are medians of three runs."""
+    a gate trained on traces of smaller R-MAT graphs (same schedule) reaches
+    a verified fixed point scanning fewer stored entries than plain pruning
+    does to reach one (its verification sweep included on both sides), at the
+    same modularity (within 0.01).  Asynchronous runs differ from run to run
+    (a plain run may stop a sweep early), so the entry counts are medians of
+    three runs."""
     sched = (1, 0, 1)
     train_graphs = [gg.rmat(19, 16, seed=100 + i, weighted=True) for i in range(4)]
     X, y = gate.collect(train_graphs, probability=0.5, schedule=sched)
@@ -322,8 +323,9 @@ def test_trained_gate_saves_work_on_rmat():
     G.set_async_schedule(*sched)
     ep, eg = [], []
     for _ in range(3):
-        plain, sp = G.run(0.05, 20, ASYNC, True)
-        ep.append(sum(sp["edges_scanned"]))
+        plain, sp = G.run(0.05, 20, ASYNC, True, flags=abi.LPA_FLAG_VERIFY)
+        assert sp["verified"]
+        ep.append(sum(sp["edges_scanned"]) + sp["verify_edges_scanned"])
     qp = G.modularity(plain)
     G.gate_load(info["params"], info["threshold"])
     for _ in range(3):
@@ -331,7 +333,7 @@ def test_trained_gate_saves_work_on_rmat():
         assert sg["verified"]
         eg.append(sum(sg["edges_scanned"]) + sg["verify_edges_scanned"])
     qg = G.modularity(lab)
-    say(f"plain entries {ep} Q={qp:.6f}; gated entries {eg} Q={qg:.6f} skipped={sum(sg['gated_out'])} "
+    say(f"verified plain entries {ep} Q={qp:.6f}; gated entries {eg} Q={qg:.6f} skipped={sum(sg['gated_out'])} "
         f"verify_changed={sg['verify_changed']}")
     assert qg >= qp - 0.01
     assert abi.nmi(plain, lab) >= 0.99
@@ -367,7 +369,7 @@ def _pick_gate(g, order, seeds=(21, 22, 23, 24), tau=0.05, max_iters=20, min_mar
     raise AssertionError("no gate with a safe margin found")
 
 
-@pytest.mark.parametrize("kind", ["sbm", "rmat", "all_hubs"])
+@pytest.mark.parametrize("kind", ["sbm", "rmat", "all_hubs", "lds_table"])
 def test_gated_deterministic_equals_gated_oracle(kind):
     """The network evaluated inside the sweep (decision pass + compaction)
     against the gated method's oracle at a threshold strictly inside (0, 1):
@@ -375,7 +377,7 @@ def test_gated_deterministic_equals_gated_oracle(kind):
     entries, gated-out vertices and the verification outcome must all be equal.
     The threshold is chosen (on the oracle side) so that no decision lies
     within 1e-3 of it in logit, beyond any fp32-vs-fp64 difference."""
-    if kind == "rmat":
+    if kind in ("rmat", "lds_table"):
         g = gg.rmat(11, 8, seed=5, weighted=True)
     else:
         g = gg.sbm(1200 if kind == "sbm" else 800, 6 if kind == "sbm" else 4, 0.05, 0.006, seed=11,
@@ -383,6 +385,8 @@ def test_gated_deterministic_equals_gated_oracle(kind):
     G = abi.LPAGraph(g)
     if kind == "all_hubs":
         G.set_bins([0, 0, 0, 0, 0, 0])  # every vertex through the hub kernels (their feature writes)
+    if kind == "lds_table":
+        G.set_variants([1, 0, 0, 0, 0, 0])  # the lowest bin's LDS table (the default is its register table)
     order = _oracle_order(G, g)
     theta, thr, ref = _pick_gate(g, order)
     say(f"gated {kind}: n={g.n} m={g.m} threshold={thr:.6f} margin={ref['margin']:.2e} "
