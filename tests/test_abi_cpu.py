@@ -79,6 +79,18 @@ def test_argument_errors():
     rc, _ = abi.lpa_create(1 << 31, 0, np.zeros(2, np.int64), None, None, 0, None, 0)
     assert rc == abi.LPA_ERR_TOO_LARGE
     assert abi.lpa_run(None, 0.05, 20, 0, 1) == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_batch_stats(None) == abi.LPA_ERR_INVALID_ARG
+    assert abi.lpa_batch_verify_stats(None) == abi.LPA_ERR_INVALID_ARG
+
+
+def test_batch_ranges_checked_on_host():
+    """The graph ranges of a batch are checked before any device work: at
+    least one graph, starting at 0, non-decreasing, ending at n."""
+    g = gg.from_edges(6, [(0, 1), (3, 4)])
+    for vptr, ng in (([0], 0), ([1, 6], 1), ([0, 4, 3, 6], 3), ([0, 3, 5], 2)):
+        rc, h = abi.lpa_batch_create(ng, np.array(vptr, np.int64), g.n, g.m, g.offsets, g.indices)
+        assert rc == abi.LPA_ERR_INVALID_ARG, vptr
+        assert not h.value
 
 
 def test_no_device_reports_device_error():
